@@ -1,0 +1,180 @@
+"""Oracle composite operator on a block-structured AMR hierarchy (FP64).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Every level l is held as a dense periodic array over the whole box at its own
+resolution h_l = dx0 / 2^l, together with
+  mask[l]    -- cells that belong to a level-l block,
+  covered[l] -- level-l cells that lie under a level-(l+1) block.
+Leaf cells (mask & ~covered) are the unknowns of the composite system.
+
+Composite operator (section 2.1 extended to the hierarchy):
+ 1. covered coarse B := mean of its 8 fine children (average down);
+ 2. every level-l cell outside the level's blocks (a ghost) gets the
+    cell-centred trilinear interpolant of level l-1 -- for B and for eta.
+    The paper does not state its coarse-fine interpolation; this reading is
+    "parity unpinned" against the paper (pinned only by invariants);
+ 3. face fluxes on each level by eqs. (4)-(6), (9)-(11);
+ 4. refluxing (section 4): on every coarse face next to a covered cell the
+    coarse flux is the mean of the 4 fine fluxes on that face;
+ 5. divergence (8) at leaf cells.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from ohm_inputs import BLOCK, HierSpec
+
+from . import ref
+from . import mg
+
+
+def face_restrict(Fd, d):
+    """Mean of the 4 fine fluxes on each coarse face.  ``Fd`` is a fine flux
+    array (3, NZ, NY, NX) through the faces p + e_d/2; the coarse face after
+    coarse cell P along d is tiled by the fine faces after fine index 2 P_d + 1
+    along d and 2 P_t, 2 P_t + 1 along the two other axes."""
+    ax = 3 - d
+    sl = [slice(None)] * 4
+    sl[ax] = slice(1, None, 2)
+    G = Fd[tuple(sl)]
+    for a in (1, 2, 3):
+        if a == ax:
+            continue
+        shp = list(G.shape)
+        shp[a:a + 1] = [shp[a] // 2, 2]
+        G = G.reshape(shp).mean(axis=a + 1)
+    return G
+
+
+class Composite:
+    def __init__(self, spec: HierSpec):
+        self.spec = spec
+        self.L = spec.nlevels
+        self.mask, self.covered = [], []
+        for l in range(self.L):
+            nx, ny, nz = spec.cells(l)
+            m = np.zeros((nz, ny, nx), dtype=bool)
+            for (i, j, k) in spec.levels[l]:
+                m[k * BLOCK:(k + 1) * BLOCK, j * BLOCK:(j + 1) * BLOCK, i * BLOCK:(i + 1) * BLOCK] = True
+            self.mask.append(m)
+        for l in range(self.L):
+            if l + 1 < self.L:
+                fm = self.mask[l + 1]
+                nz, ny, nx = self.mask[l].shape
+                cov = fm.reshape(nz, 2, ny, 2, nx, 2).any(axis=(1, 3, 5))
+                self.covered.append(cov)
+            else:
+                self.covered.append(np.zeros_like(self.mask[l]))
+        self.leaf = [m & ~c for m, c in zip(self.mask, self.covered)]
+
+    # -- conversions between block lists and dense level arrays -------------
+    def to_dense(self, l, blocks, fill=np.nan):
+        """blocks: [ncomp, nb, 8, 8, 8] or [nb, 8, 8, 8] -> dense level array."""
+        scalar = blocks.ndim == 4
+        b = blocks[None] if scalar else blocks
+        nx, ny, nz = self.spec.cells(l)
+        out = np.full((b.shape[0], nz, ny, nx), fill)
+        for n, (i, j, k) in enumerate(self.spec.levels[l]):
+            out[:, k * BLOCK:(k + 1) * BLOCK, j * BLOCK:(j + 1) * BLOCK,
+                i * BLOCK:(i + 1) * BLOCK] = b[:, n]
+        return out[0] if scalar else out
+
+    def to_blocks(self, l, dense):
+        scalar = dense.ndim == 3
+        d = dense[None] if scalar else dense
+        blk = self.spec.levels[l]
+        out = np.empty((d.shape[0], len(blk), BLOCK, BLOCK, BLOCK))
+        for n, (i, j, k) in enumerate(blk):
+            out[:, n] = d[:, k * BLOCK:(k + 1) * BLOCK, j * BLOCK:(j + 1) * BLOCK,
+                          i * BLOCK:(i + 1) * BLOCK]
+        return out[0] if scalar else out
+
+    # -- steps 1 and 2 --------------------------------------------------------
+    def average_down(self, Bs):
+        """Covered coarse cells := mean of the 8 children (finest first)."""
+        Bs = [b.copy() for b in Bs]
+        for l in range(self.L - 1, 0, -1):
+            r = ref.restrict(np.where(self.mask[l], Bs[l], 0.0))
+            cov = self.covered[l - 1]
+            Bs[l - 1] = np.where(cov, r, Bs[l - 1])
+        return Bs
+
+    def ghost_values(self, coarse_complete):
+        """Trilinear interpolant of a complete level-(l-1) array on level l."""
+        return ref.prolong(coarse_complete)
+
+    def fill_ghosts(self, Xs):
+        """Return copies of the level arrays with every non-block cell replaced
+        by the interpolant of the (already completed) next coarser level."""
+        out = [Xs[0].copy()]
+        for l in range(1, self.L):
+            g = self.ghost_values(out[l - 1])
+            out.append(np.where(self.mask[l], Xs[l], g))
+        return out
+
+    # -- steps 3-5 -------------------------------------------------------------
+    def fluxes(self, Bs, etas, complete=False):
+        if not complete:
+            Bs = self.fill_ghosts(self.average_down(Bs))
+            etas = self.fill_ghosts(etas)
+        F = [ref.flux(Bs[l], etas[l], self.spec.dx(l)) for l in range(self.L)]
+        for l in range(self.L - 1):
+            cov = self.covered[l]
+            for d in range(3):
+                avg = face_restrict(F[l + 1][d], d)
+                nbr = np.roll(cov, -1, axis=2 - d)    # is the cell across p + e_d/2 covered
+                F[l][d] = np.where((cov | nbr)[None], avg, F[l][d])
+        return F, Bs, etas
+
+    def divF(self, Bs, etas):
+        """(div F)_c at every cell of every level (meaningful at leaf cells)."""
+        F, Bc, ec = self.fluxes(Bs, etas)
+        return [ref.div(F[l], self.spec.dx(l)) for l in range(self.L)]
+
+    def apply(self, Bs, etas, coef):
+        """B + coef * div F on leaf cells; covered and ghost cells are 0."""
+        D = self.divF(Bs, etas)
+        return [np.where(self.leaf[l], Bs[l] + coef * D[l], 0.0) for l in range(self.L)]
+
+    def source(self, bs, etas, dt, lam=0.5):
+        return self.apply(bs, etas, -(1.0 - lam) * dt)
+
+    def residual(self, Bs, Ss, etas, lam_dt):
+        LB = self.apply(Bs, etas, lam_dt)
+        return [np.where(self.leaf[l], Ss[l] - LB[l], 0.0) for l in range(self.L)]
+
+    # -- leaf vectors ----------------------------------------------------------
+    def pack(self, Xs):
+        return np.concatenate([Xs[l][:, self.leaf[l]].ravel() for l in range(self.L)])
+
+    def unpack(self, x, template=None):
+        out, o = [], 0
+        for l in range(self.L):
+            n = int(self.leaf[l].sum())
+            nx, ny, nz = self.spec.cells(l)
+            a = np.zeros((3, nz, ny, nx)) if template is None else template[l].copy()
+            a[:, self.leaf[l]] = x[o:o + 3 * n].reshape(3, n)
+            out.append(a)
+            o += 3 * n
+        return out
+
+    def volumes(self):
+        """Cell volume of every packed unknown."""
+        return np.concatenate([np.full(3 * int(self.leaf[l].sum()), self.spec.dx(l) ** 3)
+                               for l in range(self.L)])
+
+    def solve(self, Ss, etas, lam_dt, x0s=None, rtol=1e-13, maxit=2000):
+        """Composite L^{-1} S by BiCGStab with a point-Jacobi preconditioner."""
+        zero = [np.zeros_like(s) for s in Ss]
+        Lop = lambda x: self.pack(self.apply(self.unpack(x, zero), etas, lam_dt))
+        al = [ref.alpha(self.fill_ghosts(etas)[l], self.spec.dx(l), lam_dt) for l in range(self.L)]
+        dinv = 1.0 / (1.0 + self.pack(al))
+        M = lambda r: dinv * r
+        x0 = self.pack(x0s) if x0s is not None else np.zeros(sum(3 * int(m.sum()) for m in self.leaf))
+        x, hist = mg.bicgstab(Lop, self.pack(Ss), x0, M, rtol, maxit)
+        return self.unpack(x, zero), hist
+
+    def cn_step(self, bs, etas, dt, lam=0.5, rtol=1e-13):
+        Ss = self.source(bs, etas, dt, lam)
+        return self.solve(Ss, etas, lam * dt, x0s=bs, rtol=rtol)

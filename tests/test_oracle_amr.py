@@ -1,0 +1,113 @@
+"""Pins of the oracle's composite AMR operator: uniform refinement reduces to a
+single level, linear fields are reproduced exactly through the coarse-fine
+ghosts and the refluxed faces, refluxing conserves the volume integral
+(section 4), and the composite solve matches a sparse direct solve."""
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import ohm_inputs as gen
+from oracle import amr, ref
+
+
+def _spec_one_patch(base_blocks=(2, 2, 2), patch=((1, 1, 1),), dx0=0.1):
+    lev0 = gen.full_level(base_blocks)
+    # a level-1 block at block coords P covers coarse cells 4P .. 4P+3
+    lev1 = gen.morton_order(np.array(patch, dtype=np.int32))
+    return gen.HierSpec(base_blocks, dx0, [lev0, lev1])
+
+
+def test_uniform_refinement_equals_single_fine_level():
+    spec0 = gen.HierSpec((1, 1, 1), 0.2, [gen.full_level((1, 1, 1))])
+    lev1 = gen.children_of(spec0.levels[0])
+    spec = gen.HierSpec((1, 1, 1), 0.2, [spec0.levels[0], gen.morton_order(lev1)])
+    comp = amr.Composite(spec)
+    rng = np.random.default_rng(0)
+    Bf = rng.standard_normal((3, 16, 16, 16))
+    ef = np.exp(rng.standard_normal((16, 16, 16)))
+    Bs = [np.zeros((3, 8, 8, 8)), Bf]
+    es = [ref.restrict(ef), ef]
+    out = comp.apply(Bs, es, 0.37)
+    ex = ref.apply(Bf, ef, 0.1, 0.37)
+    assert np.abs(out[1] - ex).max() <= 1e-13 * np.abs(ex).max()
+    assert not comp.leaf[0].any()
+
+
+def test_linear_fields_exact_across_coarse_fine_interface():
+    """Linear B and linear eta: fluxes are exact everywhere, including fine
+    faces that use interpolated ghosts and coarse faces that take the mean of
+    fine fluxes, so div F equals its continuum value (a constant)."""
+    spec = _spec_one_patch(base_blocks=(3, 3, 3), patch=((2, 2, 2), (3, 2, 2), (2, 3, 2)), dx0=0.1)
+    comp = amr.Composite(spec)
+    a = np.array([[0.3, 1.2, -0.7, 0.4], [-0.2, 0.5, 0.9, -1.1], [1.0, -0.6, 0.3, 0.8]])
+    g = np.array([2.0, 0.3, -0.2, 0.15])
+    Bs, es = [], []
+    for l in range(2):
+        nx, ny, nz = spec.cells(l)
+        h = spec.dx(l)
+        z, y, x = np.meshgrid((np.arange(nz) + 0.5) * h, (np.arange(ny) + 0.5) * h,
+                              (np.arange(nx) + 0.5) * h, indexing="ij")
+        Bs.append(np.stack([a[c, 0] + a[c, 1] * x + a[c, 2] * y + a[c, 3] * z for c in range(3)]))
+        es.append(g[0] + g[1] * x + g[2] * y + g[3] * z)
+    D = comp.divF(Bs, es)
+    # continuum: F_d[c] = eta (d_c B_d - d_d B_c) with constant gradients G[c, d] = dB_c/dx_d
+    G = a[:, 1:]
+    exact = np.array([sum(g[1 + d] * (G[d, c] - G[c, d]) for d in range(3)) for c in range(3)])
+    # compare at leaf cells at least 3 coarse cells from the periodic seam
+    for l in range(2):
+        nx, ny, nz = spec.cells(l)
+        m = 3 * (1 << l)
+        sel = np.zeros_like(comp.leaf[l])
+        sel[m:nz - m, m:ny - m, m:nx - m] = True
+        sel &= comp.leaf[l]
+        assert sel.sum() > 0
+        for c in range(3):
+            assert np.abs(D[l][c][sel] - exact[c]).max() < 1e-11, (l, c)
+
+
+def test_refluxing_conserves_volume_integral():
+    spec = _spec_one_patch(base_blocks=(2, 2, 2), patch=((1, 1, 1), (2, 1, 1)), dx0=0.25)
+    comp = amr.Composite(spec)
+    rng = np.random.default_rng(2)
+    Bs, es = [], []
+    for l in range(2):
+        nx, ny, nz = spec.cells(l)
+        Bs.append(rng.standard_normal((3, nz, ny, nx)))
+        es.append(np.exp(rng.standard_normal((nz, ny, nx))))
+    D = comp.divF(Bs, es)
+    for c in range(3):
+        tot = sum((D[l][c][comp.leaf[l]]).sum() * spec.dx(l) ** 3 for l in range(2))
+        mag = sum(np.abs(D[l][c][comp.leaf[l]]).sum() * spec.dx(l) ** 3 for l in range(2))
+        assert abs(tot) <= 1e-12 * mag
+
+
+def test_composite_solve_matches_sparse_direct():
+    """Tiny hierarchy (one 8^3 base block, one refined 8^3 fine block):
+    assemble the composite matrix by unit probes and solve by SuperLU."""
+    spec = gen.HierSpec((1, 1, 1), 0.125, [gen.full_level((1, 1, 1)),
+                                          np.array([[1, 0, 1]], dtype=np.int32)])
+    comp = amr.Composite(spec)
+    rng = np.random.default_rng(3)
+    etas = [np.exp(rng.standard_normal((8, 8, 8))), None]
+    etas[1] = np.exp(rng.standard_normal((16, 16, 16)))
+    lam_dt = 0.5 * gen.explicit_dt(spec.dx(1), float(max(e.max() for e in etas)), 30.0)
+    nunk = sum(3 * int(m.sum()) for m in comp.leaf)
+    zero = [np.zeros((3, 8, 8, 8)), np.zeros((3, 16, 16, 16))]
+    cols = []
+    for j in range(nunk):
+        e = np.zeros(nunk)
+        e[j] = 1.0
+        cols.append(sp.csc_matrix(comp.pack(comp.apply(comp.unpack(e, zero), etas, lam_dt))[:, None]))
+    A = sp.hstack(cols).tocsc()
+    S = [rng.standard_normal(z.shape) for z in zero]
+    x_direct = spla.spsolve(A, comp.pack(S))
+    xs, hist = comp.solve(S, etas, lam_dt, rtol=1e-13)
+    assert hist[-1] <= 1e-13
+    x_it = comp.pack(xs)
+    assert np.linalg.norm(x_it - x_direct) <= 1e-11 * np.linalg.norm(x_direct)
+    # conservation as a matrix property: volume-weighted column sums of the
+    # flux part vanish
+    vol = comp.volumes()
+    Adiv = (A - sp.identity(nunk)) / lam_dt
+    colsum = np.asarray((sp.diags(vol) @ Adiv).sum(axis=0)).ravel()
+    assert np.abs(colsum).max() <= 1e-11 * np.abs(Adiv).max() * vol.max()
