@@ -218,3 +218,11 @@ void oref_prolong_add(int nxc, int nyc, int nzc, int ncomp, const double *coarse
         fine[(size_t)c * Nf + at(gf, I, J, K)] += v;
     }
 }
+
+/* threads the OpenMP loops above use */
+#ifdef _OPENMP
+#include <omp.h>
+int oref_threads(void) { return omp_get_max_threads(); }
+#else
+int oref_threads(void) { return 1; }
+#endif

@@ -37,7 +37,14 @@ def lib():
             f = getattr(_lib, name)
             f.argtypes = args
             f.restype = None
+        _lib.oref_threads.argtypes = []
+        _lib.oref_threads.restype = ctypes.c_int
     return _lib
+
+
+def threads() -> int:
+    """OpenMP threads of the C primitives."""
+    return int(lib().oref_threads())
 
 
 def _p(a: np.ndarray):

@@ -1,0 +1,222 @@
+"""MI355X library for the implicit ohmic-dissipation step of Matsumoto (PASJ
+2011): one Crank-Nicolson step of dB/dt = -curl(eta curl B) on the 8^3-cell
+blocks of a periodic AMR hierarchy, solved by multigrid on the GPU.
+
+The Python layer only marshals arguments to the C ABI (include/ohm.h); fields
+are torch tensors in GPU memory.  Functions keep the names of the C calls.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import CnOpts, CnStats, OhmError, OHM_F32, OHM_F64, check, dptr, host_doubles, lib, stream_ptr
+
+BLOCK = 8
+__all__ = ["Hierarchy", "ohm_fill_ghosts", "ohm_apply", "ohm_residual", "ohm_smooth", "ohm_restrict",
+           "ohm_prolong", "ohm_reflux", "ohm_cn_step", "default_opts", "OhmError", "to_blocks", "from_blocks"]
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return OHM_F64
+    if t.dtype == torch.float32:
+        return OHM_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+class Hierarchy:
+    """Handle over one or more periodic problems (``ohm_hier_create``).
+
+    problems: list of (base_blocks (3 ints), dx0, [int32 [nb, 3] block coords per level]).
+    """
+
+    def __init__(self, problems, stream=None):
+        L = lib()
+        self.nprob = len(problems)
+        descs = (_lib.ProblemDesc * self.nprob)()
+        self._keep = []
+        for d, (bb, dx0, levels) in zip(descs, problems):
+            d.nlevels = len(levels)
+            for a in range(3):
+                d.base_blocks[a] = int(bb[a])
+            d.dx0 = float(dx0)
+            for l, blk in enumerate(levels):
+                arr = np.ascontiguousarray(np.asarray(blk, dtype=np.int32).reshape(-1, 3))
+                self._keep.append(arr)
+                d.nblocks[l] = len(arr)
+                d.block_ijk[l] = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        h = ctypes.c_void_p()
+        check(L.ohm_hier_create(descs, self.nprob, stream_ptr(stream) if stream is not None else None,
+                                ctypes.byref(h)))
+        self.h = h
+        self.nlevels = max(len(p[2]) for p in problems)
+        self.min_level = 0
+        self.prob_min_level = []
+        for p in range(self.nprob):
+            ml = ctypes.c_int32()
+            check(L.ohm_hier_problem_info(h, p, 0, None, None, ctypes.byref(ml)))
+            self.prob_min_level.append(ml.value)
+            self.min_level = min(self.min_level, ml.value)
+
+    def level_info(self, level):
+        nb, nc, ng = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(lib().ohm_hier_level_info(self.h, level, ctypes.byref(nb), ctypes.byref(nc), ctypes.byref(ng)))
+        return nb.value, nc.value, ng.value
+
+    def problem_info(self, prob, level):
+        off, dims = ctypes.c_int64(), (ctypes.c_int32 * 3)()
+        check(lib().ohm_hier_problem_info(self.h, prob, level, ctypes.byref(off), dims, None))
+        return off.value, tuple(dims)
+
+    def field(self, level, ncomp=3, dtype=None, fill=0.0):
+        """A zero field of ``level`` in the library's layout."""
+        import torch
+        dtype = torch.float64 if dtype is None else dtype
+        nb, nc, _ = self.level_info(level)
+        shape = (ncomp, nb, BLOCK, BLOCK, BLOCK) if level >= 0 else (ncomp, nc)
+        return torch.full(shape, fill, dtype=dtype, device="cuda")
+
+    def ghost(self, level, ncomp=3, dtype=None):
+        import torch
+        dtype = torch.float64 if dtype is None else dtype
+        _, _, ng = self.level_info(level)
+        return torch.zeros((ncomp, max(ng, 1), BLOCK, BLOCK, BLOCK), dtype=dtype, device="cuda")
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ohm_hier_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _coef(h: Hierarchy, c):
+    vals = np.broadcast_to(np.asarray(c, dtype=np.float64), (h.nprob,))
+    return host_doubles(vals)
+
+
+def ohm_fill_ghosts(h: Hierarchy, level, coarse, ghost, stream=None):
+    ncomp = coarse.shape[0]
+    check(lib().ohm_fill_ghosts(h.h, level, dptr(coarse), dptr(ghost), ncomp, _dtype_code(coarse), stream_ptr(stream)))
+
+
+def ohm_apply(h: Hierarchy, level, B, eta, coef, out, B_ghost=None, eta_ghost=None, stream=None):
+    check(lib().ohm_apply(h.h, level, dptr(B), dptr(B_ghost), dptr(eta), dptr(eta_ghost), _coef(h, coef), dptr(out),
+                          _dtype_code(B), stream_ptr(stream)))
+
+
+def ohm_residual(h: Hierarchy, level, B, S, eta, lam_dt, R=None, B_ghost=None, eta_ghost=None, norms=False,
+                 stream=None):
+    """Returns (nprob, 3, 2) numpy norms (sum R^2, max |R|) when norms=True."""
+    nrm = (ctypes.c_double * (6 * h.nprob))() if norms else None
+    check(lib().ohm_residual(h.h, level, dptr(B), dptr(B_ghost), dptr(S), dptr(eta), dptr(eta_ghost),
+                             _coef(h, lam_dt), dptr(R), nrm, _dtype_code(B), stream_ptr(stream)))
+    if norms:
+        return np.array(nrm[:]).reshape(h.nprob, 3, 2)
+    return None
+
+
+def ohm_smooth(h: Hierarchy, level, B, S, eta, lam_dt, nsweeps, tmp, B_ghost=None, eta_ghost=None, stream=None):
+    check(lib().ohm_smooth(h.h, level, dptr(B), dptr(B_ghost), dptr(S), dptr(eta), dptr(eta_ghost), _coef(h, lam_dt),
+                           int(nsweeps), dptr(tmp), _dtype_code(B), stream_ptr(stream)))
+
+
+def ohm_restrict(h: Hierarchy, fine_level, fine, coarse, stream=None):
+    check(lib().ohm_restrict(h.h, fine_level, dptr(fine), dptr(coarse), fine.shape[0], _dtype_code(fine),
+                             stream_ptr(stream)))
+
+
+def ohm_prolong(h: Hierarchy, coarse_level, coarse, fine, accumulate=True, stream=None):
+    check(lib().ohm_prolong(h.h, coarse_level, dptr(coarse), dptr(fine), coarse.shape[0], int(bool(accumulate)),
+                            _dtype_code(coarse), stream_ptr(stream)))
+
+
+def ohm_reflux(h: Hierarchy, level, B_coarse, eta_coarse, B_fine, eta_fine, coef, out, B_fine_ghost=None,
+               eta_fine_ghost=None, zero_covered=True, stream=None):
+    check(lib().ohm_reflux(h.h, level, dptr(B_coarse), dptr(eta_coarse), dptr(B_fine), dptr(B_fine_ghost),
+                           dptr(eta_fine), dptr(eta_fine_ghost), _coef(h, coef), dptr(out), int(bool(zero_covered)),
+                           _dtype_code(B_coarse), stream_ptr(stream)))
+
+
+def default_opts(**kw) -> CnOpts:
+    o = CnOpts()
+    lib().ohm_cn_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, "lambda_" if k == "lam" else k, v)
+    return o
+
+
+class Workspace:
+    """Device workspace of ohm_cn_step, allocated through torch once per size."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes):
+        import torch
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.buf.data_ptr()
+        off = (-base) % 256
+        return base + off, self.buf.numel() - off
+
+
+def ohm_cn_step(h: Hierarchy, B, eta, dt, opts: CnOpts | None = None, workspace: Workspace | None = None,
+                stream=None):
+    """One CN step in place on the per-level FP64 fields ``B`` (list) with
+    resistivity ``eta`` (list).  Returns (status, per-problem stats)."""
+    L = lib()
+    opts = default_opts() if opts is None else opts
+    nb = ctypes.c_size_t()
+    check(L.ohm_cn_workspace_size(h.h, ctypes.byref(opts), ctypes.byref(nb)))
+    ws = workspace if workspace is not None else Workspace()
+    ptr, size = ws.get(nb.value)
+    Bp = (ctypes.c_void_p * len(B))(*[b.data_ptr() for b in B])
+    Ep = (ctypes.c_void_p * len(eta))(*[e.data_ptr() for e in eta])
+    stats = (CnStats * h.nprob)()
+    st = L.ohm_cn_step(h.h, Bp, Ep, _coef(h, dt), ctypes.byref(opts), ctypes.c_void_p(ptr), size, stats,
+                       stream_ptr(stream))
+    out = [dict(iters=s.iters, mg_apps=s.mg_apps, rel_res=s.rel_res, max_res=tuple(s.max_res)) for s in stats]
+    if st not in (_lib.OHM_OK, _lib.OHM_ERR_NOCONV):
+        check(st)
+    return st, out
+
+
+def to_blocks(dense, block_ijk):
+    """(ncomp, nz, ny, nx) tensor/array -> (ncomp, nb, 8, 8, 8) for the listed blocks."""
+    ijk = np.asarray(block_ijk).reshape(-1, 3)
+    parts = [dense[:, k * 8:(k + 1) * 8, j * 8:(j + 1) * 8, i * 8:(i + 1) * 8] for (i, j, k) in ijk]
+    try:
+        import torch
+        if isinstance(dense, torch.Tensor):
+            return torch.stack(parts, dim=1).contiguous()
+    except ImportError:
+        pass
+    return np.ascontiguousarray(np.stack(parts, axis=1))
+
+
+def from_blocks(blocks, block_ijk, dims):
+    """Inverse of :func:`to_blocks` for a level that the blocks cover."""
+    ijk = np.asarray(block_ijk).reshape(-1, 3)
+    nx, ny, nz = dims
+    try:
+        import torch
+        is_t = isinstance(blocks, torch.Tensor)
+    except ImportError:
+        is_t = False
+    if is_t:
+        out = torch.zeros((blocks.shape[0], nz, ny, nx), dtype=blocks.dtype, device=blocks.device)
+    else:
+        out = np.zeros((blocks.shape[0], nz, ny, nx), dtype=blocks.dtype)
+    for n, (i, j, k) in enumerate(ijk):
+        out[:, k * 8:(k + 1) * 8, j * 8:(j + 1) * 8, i * 8:(i + 1) * 8] = blocks[:, n]
+    return out

@@ -1,0 +1,647 @@
+// One Crank-Nicolson step (eq. 7) on every problem of a handle.
+//
+// Outer iteration in FP64 on the composite leaf cells of the AMR hierarchy:
+// either the iterative use of multigrid of eqs. (16)-(18) or BiCGStab, with a
+// multigrid cycle as the (right) preconditioner.  The cycle runs in FP64 or,
+// in mixed precision, in FP32 with the FP64 residual, update and coarsest
+// solve around it.  Cycle: on AMR levels a coarse-grid-correction sweep over
+// the levels (smooth on each level with coarse-fine ghosts, restrict the level
+// residual under the finer blocks), then a V-cycle or full multigrid on the
+// base grid and its coarsenings, with a dense FP64 solve on the coarsest grid.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "common.h"
+
+using namespace ohm;
+
+namespace {
+
+inline size_t al(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Plan {
+    int T32 = 0;                // 1: FP32 multigrid
+    long long NBt = 0, NGt = 0; // blocks / ghost blocks over all AMR levels
+    long long LB[OHM_MAX_LEVELS] = {0}, LG[OHM_MAX_LEVELS] = {0};
+    size_t total = 0;
+    // byte offsets
+    size_t x, r, rhat, p, v, s, t, ph, sh, S, og, oeg;
+    size_t rhs, e, tmp, res, mg_g, eta_t, eta_tg;
+    size_t d_rhs[16], d_e[16], d_tmp[16], d_res[16], d_eta[16], d_eta64[16];
+    size_t inv, aug, jobs, part, dots, scal, ranges, mlprob, active, cmask, coefs;
+    size_t inv_elems = 0, aug_elems = 0;
+};
+
+Plan make_plan(const ohm_hier *h, const ohm_cn_opts *o)
+{
+    Plan P;
+    P.T32 = o->precision == 1;
+    for (int l = 0; l < h->nlev; ++l) {
+        P.LB[l] = P.NBt;
+        P.LG[l] = P.NGt;
+        P.NBt += h->nb_host[l];
+        P.NGt += h->ng_host[l];
+    }
+    const size_t tb = P.T32 ? 4 : 8;
+    const size_t V = 3 * (size_t)P.NBt * NC, G = 3 * (size_t)P.NGt * NC;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o_ = off;
+        off += al(bytes);
+        return o_;
+    };
+    P.x = take(8 * V);
+    P.r = take(8 * V);
+    P.rhat = take(8 * V);
+    P.p = take(8 * V);
+    P.v = take(8 * V);
+    P.s = take(8 * V);
+    P.t = take(8 * V);
+    P.ph = take(8 * V);
+    P.sh = take(8 * V);
+    P.S = take(8 * V);
+    P.og = take(8 * G + 8);
+    P.oeg = take(8 * G / 3 + 8);
+    P.rhs = take(tb * V);
+    P.e = take(tb * V);
+    P.tmp = take(tb * V);
+    P.res = take(tb * V);
+    P.mg_g = take(tb * G + 8);
+    P.eta_t = take(P.T32 ? tb * V / 3 : 8);
+    P.eta_tg = take(P.T32 ? tb * G / 3 + 8 : 8);
+    for (int d = 1; d <= -h->min_level; ++d) {
+        const size_t nc = (size_t)h->dense_cells[d];
+        P.d_rhs[d] = take(tb * 3 * nc);
+        P.d_e[d] = take(tb * 3 * nc);
+        P.d_tmp[d] = take(tb * 3 * nc);
+        P.d_res[d] = take(tb * 3 * nc);
+        P.d_eta[d] = take(tb * nc);
+        P.d_eta64[d] = take(8 * nc);
+    }
+    coarse_sizes(h, &P.inv_elems, &P.aug_elems);
+    P.inv = take(8 * P.inv_elems + 8);
+    P.aug = take(8 * P.aug_elems + 8);
+    P.jobs = take(coarse_job_bytes() * (size_t)h->nprob * 17 + 8);
+    P.part = take(8 * (size_t)P.NBt * 8);
+    P.dots = take(8 * (size_t)h->nprob * 8);
+    P.scal = take(8 * (size_t)h->nprob * scal_stride());
+    P.ranges = take(8 * (size_t)h->nprob * OHM_MAX_LEVELS * 2);
+    P.mlprob = take(4 * (size_t)P.NBt);
+    P.active = take(4 * (size_t)h->nprob);
+    P.cmask = take(4 * (size_t)h->nprob * 17);
+    P.coefs = take(8 * (size_t)h->nprob * 4);
+    P.total = off;
+    return P;
+}
+
+bool valid_opts(const ohm_cn_opts *o)
+{
+    return o && o->lambda > 0.0 && o->lambda <= 1.0 && o->rtol > 0.0 && o->max_iters >= 1 && o->nu_pre >= 0 &&
+           o->nu_post >= 0 && o->nu_pre + o->nu_post >= 1 && o->n_vcycles >= 1 && (o->cycle == 0 || o->cycle == 1) &&
+           (o->outer == 0 || o->outer == 1) && (o->precision == 0 || o->precision == 1) && o->coarse_sweeps >= 0;
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Solver {
+    ohm_hier *h;
+    const ohm_cn_opts *o;
+    Plan P;
+    char *ws;
+    hipStream_t st;
+    void *const *Buser;
+    const void *const *Euser;
+    // derived pointers
+    const int *mlprob, *active;
+    int *active_mut;
+    double *lam_dt, *src_coef, *neg_lam_dt;
+    long long VN, GN;            // component strides of multi-level vectors / ghosts
+    std::vector<int> njobs;      // coarse jobs per depth
+    std::vector<long long> ranges_host;
+
+    template <typename U> U *at(size_t off) const { return (U *)(ws + off); }
+    double *vec(size_t off, int l) const { return at<double>(off) + P.LB[l] * NC; }
+    T *mg(size_t off, int l) const { return at<T>(off) + P.LB[l] * NC; }
+    const double *eta64(int l) const { return (const double *)Euser[l]; }
+    const T *etaT(int l) const
+    {
+        if (P.T32) return at<T>(P.eta_t) + P.LB[l] * NC;
+        return (const T *)Euser[l];
+    }
+    const double *etag64(int l) const { return at<double>(P.oeg) + P.LG[l] * NC; }
+    const T *etagT(int l) const { return P.T32 ? at<T>(P.eta_tg) + P.LG[l] * NC : (const T *)etag64(l); }
+    int nlev() const { return h->nlev; }
+
+    // ---- outer composite operator (FP64) --------------------------------------
+    // y = L x (mode APPLY, coef) or y = S - L x (mode RESID) on leaf cells;
+    // covered cells of y are zero.
+    ohm_status composite(size_t xo, size_t yo, int mode, const double *coef, const double *reflux_coef, size_t So)
+    {
+        const int L = nlev();
+        for (int l = L - 1; l >= 1; --l)
+            OHM_TRY(launch_restrict_blk<double>(h, l, vec(xo, l), VN, vec(xo, l - 1), VN, 3, active, st));
+        for (int l = 1; l < L; ++l)
+            OHM_TRY(launch_fill_ghosts<double>(h, l, vec(xo, l - 1), VN, at<double>(P.og) + P.LG[l] * NC, GN, 3,
+                                               active, st));
+        for (int l = 0; l < L; ++l)
+            OHM_TRY(launch_blk_stencil<double>(h, l, mode, vec(xo, l), at<double>(P.og) + P.LG[l] * NC, VN, GN,
+                                               So ? vec(So, l) : nullptr, eta64(l), etag64(l), coef, vec(yo, l), 0,
+                                               nullptr, (l + 1 < L) ? h->amr[l].cov : nullptr, active, st));
+        for (int l = 0; l + 1 < L; ++l)
+            OHM_TRY(launch_reflux<double>(h, l, vec(xo, l), VN, eta64(l), vec(xo, l + 1), VN,
+                                          at<double>(P.og) + P.LG[l + 1] * NC, GN, eta64(l + 1), etag64(l + 1),
+                                          reflux_coef, vec(yo, l), active, st));
+        return OHM_OK;
+    }
+
+    // per-problem reductions of per-block partials over all AMR levels
+    ohm_status reduce(int k, int ksum, double *out)
+    {
+        return launch_reduce_problem(h->nprob, nlev(), at<long long>(P.ranges), at<double>(P.part), k, ksum, out, st);
+    }
+
+    ohm_status dots(const double *const *x, const double *const *y, int nq)
+    {
+        OHM_TRY(vdot((int)P.NBt, mlprob, active, VN, x, y, nq, at<double>(P.part), st));
+        return reduce(nq, nq, at<double>(P.dots));
+    }
+
+    // ---- multigrid cycle (precision T) ----------------------------------------
+    ohm_status smooth_blk(int l, int n)
+    {
+        for (int k = 0; k < n; ++k)
+            for (int c = 0; c < 2; ++c) {
+                T *src = c == 0 ? mg(P.e, l) : mg(P.tmp, l);
+                T *dst = c == 0 ? mg(P.tmp, l) : mg(P.e, l);
+                OHM_TRY(launch_blk_stencil<T>(h, l, MODE_SMOOTH, src, at<T>(P.mg_g) + P.LG[l] * NC, VN, GN,
+                                              mg(P.rhs, l), etaT(l), etagT(l), lam_dt, dst, c, nullptr, nullptr,
+                                              active, st));
+            }
+        return OHM_OK;
+    }
+    ohm_status resid_blk(int l)
+    {
+        return launch_blk_stencil<T>(h, l, MODE_RESID, mg(P.e, l), at<T>(P.mg_g) + P.LG[l] * NC, VN, GN,
+                                     mg(P.rhs, l), etaT(l), etagT(l), lam_dt, mg(P.res, l), 0, nullptr, nullptr,
+                                     active, st);
+    }
+    T *dv(size_t const *arr, int d) const { return at<T>(arr[d]); }
+    ohm_status smooth_dense(int d, int n, const int *filter, bool all)
+    {
+        for (int k = 0; k < n; ++k)
+            for (int c = 0; c < 2; ++c) {
+                T *src = c == 0 ? dv(P.d_e, d) : dv(P.d_tmp, d);
+                T *dst = c == 0 ? dv(P.d_tmp, d) : dv(P.d_e, d);
+                OHM_TRY(launch_dense_stencil<T>(h, -d, MODE_SMOOTH, src, dv(P.d_rhs, d), dv(P.d_eta, d), lam_dt, dst,
+                                                c, all, filter, st));
+            }
+        return OHM_OK;
+    }
+    // coarsest grids at depth d (e_d already zero): dense inverse for small
+    // grids, FP-T smoothing sweeps for the others
+    ohm_status coarsest(int d)
+    {
+        void *jobs = at<char>(P.jobs) + coarse_job_bytes() * (size_t)h->nprob * d;
+        if (njobs[d] > 0)
+            OHM_TRY(launch_coarse_apply<T>(h, d, jobs, njobs[d], at<double>(P.inv), dv(P.d_rhs, d), dv(P.d_e, d),
+                                           active, st));
+        if (has_big[d] && o->coarse_sweeps > 0)
+            OHM_TRY(smooth_dense(d, o->coarse_sweeps, at<int>(P.cmask) + (size_t)h->nprob * d, true));
+        return OHM_OK;
+    }
+    ohm_status zero_level(size_t off, int l)
+    {
+        for (int c = 0; c < 3; ++c) OHM_TRY(vfill<T>(mg(off, l) + c * VN, (long long)h->nb_host[l] * NC, T(0), st));
+        return OHM_OK;
+    }
+    std::vector<int> has_big;
+
+    // V-cycle on the base stack at level lev (0 or dense -d); e at lev holds
+    // the initial guess (the caller zeroes it for a zero guess)
+    ohm_status vcycle_base(int lev)
+    {
+        const int nu1 = o->nu_pre, nu2 = o->nu_post;
+        if (lev == 0) {
+            OHM_TRY(smooth_blk(0, nu1));
+            OHM_TRY(resid_blk(0));
+            OHM_TRY(launch_restrict_blk<T>(h, 0, mg(P.res, 0), VN, dv(P.d_rhs, 1), h->dense_cells[1], 3, active, st));
+            OHM_TRY(down_dense(1));
+            OHM_TRY(launch_prolong_blk<T>(h, -1, dv(P.d_e, 1), h->dense_cells[1], mg(P.e, 0), VN, 3, 1, active, st));
+            OHM_TRY(smooth_blk(0, nu2));
+            return OHM_OK;
+        }
+        const int d = -lev;
+        OHM_TRY(smooth_dense(d, nu1, active, false));
+        OHM_TRY(launch_dense_stencil<T>(h, -d, MODE_RESID, dv(P.d_e, d), dv(P.d_rhs, d), dv(P.d_eta, d), lam_dt,
+                                        dv(P.d_res, d), 0, false, active, st));
+        OHM_TRY(launch_dense_restrict<T>(h, -d, dv(P.d_res, d), dv(P.d_rhs, d + 1), 3, active, st));
+        OHM_TRY(down_dense(d + 1));
+        OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), dv(P.d_e, d + 1), dv(P.d_e, d), 3, 1, active, st));
+        OHM_TRY(smooth_dense(d, nu2, active, false));
+        return OHM_OK;
+    }
+    // enter dense depth d with its rhs set: zero guess, coarsest solves for the
+    // problems bottoming out here, a V-cycle for the others
+    ohm_status down_dense(int d)
+    {
+        OHM_TRY(vfill<T>(dv(P.d_e, d), 3 * h->dense_cells[d], T(0), st));
+        OHM_TRY(coarsest(d));
+        if (h->dense[d].ntile > 0) OHM_TRY(vcycle_base(-d));
+        return OHM_OK;
+    }
+
+    ohm_status fmg_base()
+    {
+        // restrict the right-hand side down the base stack, solve the coarsest
+        // grids, then interpolate upward with n_vcycles V-cycles per level
+        OHM_TRY(launch_restrict_blk<T>(h, 0, mg(P.rhs, 0), VN, dv(P.d_rhs, 1), h->dense_cells[1], 3, active, st));
+        const int D = -h->min_level;
+        for (int d = 1; d < D; ++d)
+            OHM_TRY(launch_dense_restrict<T>(h, -d, dv(P.d_rhs, d), dv(P.d_rhs, d + 1), 3, active, st));
+        for (int d = 1; d <= D; ++d) OHM_TRY(vfill<T>(dv(P.d_e, d), 3 * h->dense_cells[d], T(0), st));
+        for (int d = 1; d <= D; ++d) OHM_TRY(coarsest(d));
+        for (int d = D - 1; d >= 1; --d) {
+            if (h->dense[d].ntile == 0) continue;
+            OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), dv(P.d_e, d + 1), dv(P.d_e, d), 3, 0, active, st));
+            for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(-d));
+        }
+        OHM_TRY(launch_prolong_blk<T>(h, -1, dv(P.d_e, 1), h->dense_cells[1], mg(P.e, 0), VN, 3, 0, active, st));
+        for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(0));
+        return OHM_OK;
+    }
+
+    // z = M(r): the multigrid cycle applied to an FP64 multi-level vector
+    ohm_status precond(size_t ro, size_t zo)
+    {
+        const long long n = 3 * P.NBt * NC;
+        OHM_TRY(vconvert<double, T>(at<double>(ro), at<T>(P.rhs), n, st));
+        const int L = nlev();
+        // AMR levels, finest first: smooth with zero coarse-fine ghosts,
+        // restrict the level residual under the finer blocks
+        if (L > 1 && P.NGt > 0) OHM_TRY(vfill<T>(at<T>(P.mg_g), 3 * P.NGt * NC, T(0), st));
+        for (int l = L - 1; l >= 1; --l) {
+            OHM_TRY(zero_level(P.e, l));
+            OHM_TRY(smooth_blk(l, o->nu_pre));
+            OHM_TRY(resid_blk(l));
+            OHM_TRY(launch_restrict_blk<T>(h, l, mg(P.res, l), VN, mg(P.rhs, l - 1), VN, 3, active, st));
+        }
+        if (o->cycle == 1) {
+            OHM_TRY(fmg_base());
+        } else {
+            OHM_TRY(zero_level(P.e, 0));
+            for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(0));
+        }
+        for (int l = 1; l < L; ++l) {
+            OHM_TRY(launch_prolong_blk<T>(h, l - 1, mg(P.e, l - 1), VN, mg(P.e, l), VN, 3, 1, active, st));
+            OHM_TRY(launch_fill_ghosts<T>(h, l, mg(P.e, l - 1), VN, at<T>(P.mg_g) + P.LG[l] * NC, GN, 3, active, st));
+            OHM_TRY(smooth_blk(l, o->nu_post));
+        }
+        OHM_TRY(vconvert<T, double>(at<T>(P.e), at<double>(zo), n, st));
+        return OHM_OK;
+    }
+
+    // ---- setup ----------------------------------------------------------------
+    ohm_status setup(const double *dt)
+    {
+        const int np = h->nprob, L = nlev();
+        VN = P.NBt * NC;
+        GN = P.NGt * NC;
+        // tables: multi-level block -> problem, per-problem block ranges
+        std::vector<int> mp;
+        mp.reserve(P.NBt);
+        for (int l = 0; l < L; ++l) mp.insert(mp.end(), h->blk_prob_host[l].begin(), h->blk_prob_host[l].end());
+        ranges_host.assign((size_t)np * L * 2, 0);
+        for (int p = 0; p < np; ++p)
+            for (int l = 0; l < L; ++l) {
+                const ohm_prob_host &Q = h->probs[p];
+                long long b0 = 0, b1 = 0;
+                if (l < Q.nlevels) {
+                    b0 = P.LB[l] + Q.boff[l];
+                    b1 = b0 + Q.nb[l];
+                }
+                ranges_host[2 * ((size_t)p * L + l)] = b0;
+                ranges_host[2 * ((size_t)p * L + l) + 1] = b1;
+            }
+        std::vector<double> coefs(4 * (size_t)np);
+        for (int p = 0; p < np; ++p) {
+            if (!(dt[p] > 0.0) || !std::isfinite(dt[p])) return fail(OHM_ERR_ARG, "dt[%d] must be positive", p);
+            coefs[p] = o->lambda * dt[p];
+            coefs[np + p] = -(1.0 - o->lambda) * dt[p];
+            coefs[2 * np + p] = -o->lambda * dt[p];
+        }
+        OHM_HIP(hipMemcpyAsync(at<int>(P.mlprob), mp.data(), sizeof(int) * mp.size(), hipMemcpyHostToDevice, st));
+        OHM_HIP(hipMemcpyAsync(at<long long>(P.ranges), ranges_host.data(), sizeof(long long) * ranges_host.size(),
+                               hipMemcpyHostToDevice, st));
+        OHM_HIP(hipMemcpyAsync(at<double>(P.coefs), coefs.data(), sizeof(double) * coefs.size(), hipMemcpyHostToDevice,
+                               st));
+        std::vector<int> ones(np, 1);
+        OHM_HIP(hipMemcpyAsync(at<int>(P.active), ones.data(), sizeof(int) * np, hipMemcpyHostToDevice, st));
+        mlprob = at<int>(P.mlprob);
+        active_mut = at<int>(P.active);
+        active = active_mut;
+        lam_dt = at<double>(P.coefs);
+        src_coef = lam_dt + np;
+        neg_lam_dt = lam_dt + 2 * np;
+        // coarse-fine ghosts of eta (FP64), FP32 copies
+        for (int l = 1; l < L; ++l)
+            OHM_TRY(launch_fill_ghosts<double>(h, l, eta64(l - 1), (long long)h->nb_host[l - 1] * NC,
+                                               at<double>(P.oeg) + P.LG[l] * NC, 0, 1, nullptr, st));
+        if (P.T32) {
+            for (int l = 0; l < L; ++l)
+                OHM_TRY(vconvert<double, T>(eta64(l), at<T>(P.eta_t) + P.LB[l] * NC, (long long)h->nb_host[l] * NC, st));
+            OHM_TRY(vconvert<double, T>(at<double>(P.oeg), at<T>(P.eta_tg), P.NGt * NC, st));
+        }
+        // resistivity of the dense levels: mean of the 8 children
+        const int D = -h->min_level;
+        for (int d = 1; d <= D; ++d) {
+            if (d == 1)
+                OHM_TRY(launch_restrict_blk<double>(h, 0, eta64(0), 0, at<double>(P.d_eta64[1]), 0, 1, nullptr, st));
+            else
+                OHM_TRY(launch_dense_restrict<double>(h, -(d - 1), at<double>(P.d_eta64[d - 1]), at<double>(P.d_eta64[d]),
+                                                      1, nullptr, st));
+            OHM_TRY(vconvert<double, T>(at<double>(P.d_eta64[d]), at<T>(P.d_eta[d]), h->dense_cells[d], st));
+        }
+        // coarsest grids: dense inverses (rebuilt when lam_dt changes)
+        bool rebuild = false;
+        for (int p = 0; p < np; ++p)
+            if (h->cinv_lamdt[p] != coefs[p]) rebuild = true;
+        njobs.assign(17, 0);
+        has_big.assign(17, 0);
+        std::vector<int> cmask((size_t)np * 17, 0);
+        for (int p = 0; p < np; ++p) {
+            const ohm_prob_host &Q = h->probs[p];
+            const int dd = -Q.min_level;
+            const int *dm = Q.dims[dd];
+            if (3LL * dm[0] * dm[1] * dm[2] > 768) {
+                has_big[dd] = 1;
+                cmask[(size_t)np * dd + p] = 1;
+            }
+        }
+        OHM_HIP(hipMemcpyAsync(at<int>(P.cmask), cmask.data(), sizeof(int) * cmask.size(), hipMemcpyHostToDevice, st));
+        for (int d = 1; d <= D; ++d) {
+            void *jobs = at<char>(P.jobs) + coarse_job_bytes() * (size_t)np * d;
+            int nj = 0;
+            OHM_TRY(upload_coarse_jobs(h, d, jobs, &nj, st));
+            njobs[d] = nj;
+        }
+        // the inverse depends on eta too: rebuild every step (cheap next to the
+        // solve for the small grids it is used on)
+        rebuild = true;
+        if (rebuild && P.inv_elems > 0) {
+            std::vector<const double *> ed(17, nullptr);
+            for (int d = 1; d <= D; ++d) ed[d] = at<double>(P.d_eta64[d]);
+            void *jobs_tmp = at<char>(P.jobs);   // depth-0 slot is free for the build
+            OHM_TRY(build_coarse_inverses(h, ed.data(), coefs.data(), at<double>(P.inv), at<double>(P.aug), jobs_tmp,
+                                          st));
+            for (int p = 0; p < np; ++p) h->cinv_lamdt[p] = coefs[p];
+        }
+        // x = b (user B), S = b - (1 - lambda) dt div F(b) on leaf cells
+        for (int l = 0; l < L; ++l)
+            OHM_TRY(vcopy_level<double, double>((const double *)Buser[l], (long long)h->nb_host[l] * NC, vec(P.x, l),
+                                                VN, (long long)h->nb_host[l] * NC, 3, st));
+        OHM_TRY(composite(P.x, P.S, MODE_APPLY, src_coef, src_coef, 0));
+        return OHM_OK;
+    }
+
+    // |S|^2 per problem and the current residual norms
+    std::vector<double> Snorm2, rr;
+
+    ohm_status read_rr(std::vector<double> &out)
+    {
+        out.resize(h->nprob);
+        std::vector<double> d((size_t)h->nprob * 8);
+        OHM_HIP(hipMemcpyAsync(d.data(), at<double>(P.dots), sizeof(double) * 8 * h->nprob, hipMemcpyDeviceToHost, st));
+        OHM_HIP(hipStreamSynchronize(st));
+        for (int p = 0; p < h->nprob; ++p) out[p] = d[p];
+        return OHM_OK;
+    }
+
+    // true residual r = S - L x, returns per-problem |r|^2 (in dots[p*1])
+    ohm_status true_residual(std::vector<double> &r2)
+    {
+        OHM_TRY(composite(P.x, P.r, MODE_RESID, lam_dt, neg_lam_dt, P.S));
+        const double *xs[1] = {at<double>(P.r)};
+        OHM_TRY(dots(xs, xs, 1));
+        // dots are packed with stride nq = 1
+        std::vector<double> d(h->nprob);
+        OHM_HIP(hipMemcpyAsync(d.data(), at<double>(P.dots), sizeof(double) * h->nprob, hipMemcpyDeviceToHost, st));
+        OHM_HIP(hipStreamSynchronize(st));
+        r2 = d;
+        return OHM_OK;
+    }
+
+    ohm_status set_active(const std::vector<int> &a)
+    {
+        OHM_HIP(hipMemcpyAsync(active_mut, a.data(), sizeof(int) * a.size(), hipMemcpyHostToDevice, st));
+        return OHM_OK;
+    }
+
+    ohm_status run(ohm_cn_stats *stats)
+    {
+        const int np = h->nprob;
+        std::vector<int> iters(np, 0), mgapps(np, 0), act(np, 1);
+        // |S|^2
+        {
+            const double *xs[1] = {at<double>(P.S)};
+            OHM_TRY(dots(xs, xs, 1));
+            std::vector<double> d(np);
+            OHM_HIP(hipMemcpyAsync(d.data(), at<double>(P.dots), sizeof(double) * np, hipMemcpyDeviceToHost, st));
+            OHM_HIP(hipStreamSynchronize(st));
+            Snorm2 = d;
+        }
+        std::vector<double> r2;
+        OHM_TRY(true_residual(r2));
+        auto converged = [&](int p, double v) {
+            return !(v > o->rtol * o->rtol * std::max(Snorm2[p], 1e-300));
+        };
+        ohm_status result = OHM_OK;
+        for (int p = 0; p < np; ++p) {
+            if (!std::isfinite(r2[p])) return fail(OHM_ERR_NONFINITE, "problem %d: non-finite residual", p);
+            if (converged(p, r2[p])) act[p] = 0;
+        }
+        OHM_TRY(set_active(act));
+        const int maxit = o->max_iters;
+        auto any = [&]() { return std::any_of(act.begin(), act.end(), [](int a) { return a != 0; }); };
+        if (o->outer == 0) {
+            // eqs. (16)-(18): R = S - L B; B <- B + M(R)
+            for (int it = 0; it < maxit && any(); ++it) {
+                OHM_TRY(precond(P.r, P.ph));
+                OHM_TRY(vaxpy1((int)P.NBt, mlprob, active, VN, at<double>(P.x), at<double>(P.ph), st));
+                OHM_TRY(true_residual(r2));
+                for (int p = 0; p < np; ++p)
+                    if (act[p]) {
+                        ++iters[p];
+                        ++mgapps[p];
+                        if (!std::isfinite(r2[p])) return fail(OHM_ERR_NONFINITE, "problem %d: non-finite residual", p);
+                        if (converged(p, r2[p])) act[p] = 0;
+                    }
+                OHM_TRY(set_active(act));
+            }
+        } else {
+            // BiCGStab; restarted from the true residual when the recurrence
+            // residual has converged but the true one has not
+            int it_total = 0;
+            while (any() && it_total < maxit) {
+                // restart: rhat = r, p = v = 0, rho = alpha = omega = 1
+                const long long n = 3 * P.NBt * NC;
+                OHM_TRY(vconvert<double, double>(at<double>(P.r), at<double>(P.rhat), n, st));
+                OHM_TRY(vfill<double>(at<double>(P.p), n, 0.0, st));
+                OHM_TRY(vfill<double>(at<double>(P.v), n, 0.0, st));
+                {
+                    const double *xs[1] = {at<double>(P.r)};
+                    OHM_TRY(dots(xs, xs, 1));
+                    OHM_TRY(vscal(np, 0, active, at<double>(P.dots), 1, at<double>(P.scal), st));
+                }
+                std::vector<int> inner(act);
+                while (it_total < maxit) {
+                    OHM_TRY(vscal(np, 1, active, at<double>(P.dots), 1, at<double>(P.scal), st));
+                    OHM_TRY(vbicg_p((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.r),
+                                    at<double>(P.v), at<double>(P.p), st));
+                    OHM_TRY(precond(P.p, P.ph));
+                    OHM_TRY(composite(P.ph, P.v, MODE_APPLY, lam_dt, lam_dt, 0));
+                    {
+                        const double *xs[1] = {at<double>(P.rhat)}, *ys[1] = {at<double>(P.v)};
+                        OHM_TRY(dots(xs, ys, 1));
+                        OHM_TRY(vscal(np, 2, active, at<double>(P.dots), 1, at<double>(P.scal), st));
+                    }
+                    OHM_TRY(vbicg_s((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.r),
+                                    at<double>(P.v), at<double>(P.s), st));
+                    OHM_TRY(precond(P.s, P.sh));
+                    OHM_TRY(composite(P.sh, P.t, MODE_APPLY, lam_dt, lam_dt, 0));
+                    {
+                        const double *xs[2] = {at<double>(P.t), at<double>(P.t)},
+                                     *ys[2] = {at<double>(P.s), at<double>(P.t)};
+                        OHM_TRY(dots(xs, ys, 2));
+                        OHM_TRY(vscal(np, 3, active, at<double>(P.dots), 2, at<double>(P.scal), st));
+                    }
+                    OHM_TRY(vbicg_xr((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.x),
+                                     at<double>(P.ph), at<double>(P.sh), at<double>(P.s), at<double>(P.t),
+                                     at<double>(P.r), at<double>(P.rhat), at<double>(P.part), st));
+                    OHM_TRY(reduce(2, 2, at<double>(P.dots)));
+                    OHM_TRY(vscal(np, 4, active, at<double>(P.dots), 2, at<double>(P.scal), st));
+                    ++it_total;
+                    std::vector<double> d((size_t)np * 2);
+                    OHM_HIP(hipMemcpyAsync(d.data(), at<double>(P.dots), sizeof(double) * 2 * np, hipMemcpyDeviceToHost,
+                                           st));
+                    OHM_HIP(hipStreamSynchronize(st));
+                    bool any_inner = false;
+                    for (int p = 0; p < np; ++p)
+                        if (inner[p]) {
+                            ++iters[p];
+                            mgapps[p] += 2;
+                            if (!std::isfinite(d[2 * p]))
+                                return fail(OHM_ERR_NONFINITE, "problem %d: non-finite residual", p);
+                            if (converged(p, d[2 * p])) inner[p] = 0;
+                            any_inner |= inner[p] != 0;
+                        }
+                    // stop updating problems whose recurrence residual converged
+                    OHM_TRY(set_active(inner));
+                    if (!any_inner) break;
+                }
+                // verify with the true residual
+                OHM_TRY(set_active(act));
+                OHM_TRY(true_residual(r2));
+                for (int p = 0; p < np; ++p)
+                    if (act[p] && converged(p, r2[p])) act[p] = 0;
+                OHM_TRY(set_active(act));
+            }
+        }
+        // final state: true residual of every problem, average-down, copy out
+        std::vector<int> all(np, 1);
+        OHM_TRY(set_active(all));
+        OHM_TRY(true_residual(r2));
+        OHM_TRY(vnorms((int)P.NBt, mlprob, active, VN, at<double>(P.r), at<double>(P.part), st));
+        OHM_TRY(reduce(6, 3, at<double>(P.dots)));
+        std::vector<double> nrm((size_t)np * 6);
+        OHM_HIP(hipMemcpyAsync(nrm.data(), at<double>(P.dots), sizeof(double) * 6 * np, hipMemcpyDeviceToHost, st));
+        OHM_HIP(hipStreamSynchronize(st));
+        for (int p = 0; p < np; ++p) {
+            const double rel = std::sqrt(r2[p] / std::max(Snorm2[p], 1e-300));
+            if (stats) {
+                stats[p].iters = iters[p];
+                stats[p].mg_apps = mgapps[p];
+                stats[p].rel_res = rel;
+                for (int c = 0; c < 3; ++c) stats[p].max_res[c] = nrm[6 * p + 3 + c];
+            }
+            if (!std::isfinite(r2[p])) result = fail(OHM_ERR_NONFINITE, "problem %d: non-finite residual", p);
+            else if (!converged(p, r2[p]) && result == OHM_OK)
+                result = fail(OHM_ERR_NOCONV, "problem %d: relative residual %.3e after %d iterations", p, rel,
+                              iters[p]);
+        }
+        const int L = nlev();
+        for (int l = L - 1; l >= 1; --l)
+            OHM_TRY(launch_restrict_blk<double>(h, l, vec(P.x, l), VN, vec(P.x, l - 1), VN, 3, nullptr, st));
+        for (int l = 0; l < L; ++l)
+            OHM_TRY(vcopy_level<double, double>(vec(P.x, l), VN, (double *)Buser[l], (long long)h->nb_host[l] * NC,
+                                                (long long)h->nb_host[l] * NC, 3, st));
+        OHM_HIP(hipStreamSynchronize(st));
+        return result;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+void ohm_cn_default_opts(ohm_cn_opts *o)
+{
+    if (!o) return;
+    o->lambda = 0.5;
+    o->rtol = 1e-10;
+    o->max_iters = 100;
+    o->nu_pre = 2;
+    o->nu_post = 2;
+    o->n_vcycles = 1;
+    o->cycle = 0;
+    o->outer = 1;
+    o->precision = 0;
+    o->coarse_sweeps = 16;
+}
+
+ohm_status ohm_cn_workspace_size(const ohm_hier *h, const ohm_cn_opts *opts, size_t *bytes)
+{
+    if (!h || !bytes) return fail(OHM_ERR_ARG, "NULL argument");
+    if (!valid_opts(opts)) return fail(OHM_ERR_ARG, "invalid options");
+    *bytes = make_plan(h, opts).total;
+    return OHM_OK;
+}
+
+ohm_status ohm_cn_step(ohm_hier *h, void *const B[], const void *const eta[], const double *dt,
+                       const ohm_cn_opts *opts, void *workspace, size_t ws_bytes, ohm_cn_stats *stats,
+                       hipStream_t stream)
+{
+    if (!h) return fail(OHM_ERR_ARG, "handle is NULL");
+    if (!B || !eta || !dt) return fail(OHM_ERR_ARG, "NULL argument");
+    if (!valid_opts(opts)) return fail(OHM_ERR_ARG, "invalid options");
+    for (int l = 0; l < h->nlev; ++l)
+        if (!B[l] || !eta[l]) return fail(OHM_ERR_ARG, "B[%d] or eta[%d] is NULL", l, l);
+    Plan P = make_plan(h, opts);
+    if (!workspace || ws_bytes < P.total)
+        return fail(OHM_ERR_NOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, P.total);
+    if (((uintptr_t)workspace & 255) != 0) return fail(OHM_ERR_ARG, "workspace must be 256-byte aligned");
+    if (opts->precision == 1) {
+        Solver<float> S;
+        S.h = h;
+        S.o = opts;
+        S.P = P;
+        S.ws = (char *)workspace;
+        S.st = stream;
+        S.Buser = B;
+        S.Euser = eta;
+        OHM_TRY(S.setup(dt));
+        return S.run(stats);
+    }
+    Solver<double> S;
+    S.h = h;
+    S.o = opts;
+    S.P = P;
+    S.ws = (char *)workspace;
+    S.st = stream;
+    S.Buser = B;
+    S.Euser = eta;
+    OHM_TRY(S.setup(dt));
+    return S.run(stats);
+}
+
+}  // extern "C"

@@ -1,0 +1,220 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "ohm.h"
+
+namespace ohm {
+
+constexpr int NB = 8;          // cells per block edge
+constexpr int NC = 512;        // cells per block
+constexpr int NXCD = 8;        // MI355X compute dies: workgroups are dealt round-robin
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+void set_error(const std::string &msg);
+ohm_status fail(ohm_status st, const char *fmt, ...);
+
+#define OHM_HIP(call)                                                               \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return ::ohm::fail(OHM_ERR_HIP, "%s failed: %s (%s:%d)", #call,         \
+                               hipGetErrorString(e_), __FILE__, __LINE__);          \
+    } while (0)
+
+#define OHM_TRY(...)                                                                \
+    do {                                                                            \
+        ohm_status s_ = (__VA_ARGS__);                                              \
+        if (s_ != OHM_OK) return s_;                                                \
+    } while (0)
+
+ohm_status check_launch(const char *what);
+
+// ---------------------------------------------------------------------------
+// device-side tables of one AMR level (all problems of a handle)
+// ---------------------------------------------------------------------------
+// Neighbour entry of a block: >= 0 index of a same-level block; <= -1 means the
+// ghost block -1-entry; NBR_NONE means absent (only allowed for corners).
+constexpr int NBR_NONE = -(1 << 30);
+
+struct AmrLevelDev {
+    int nb = 0;                // blocks
+    int ng = 0;                // coarse-fine ghost blocks
+    int *nbr = nullptr;        // [nb][27] neighbour entries, index (dx+1)+3(dy+1)+9(dz+1)
+    int *prob = nullptr;       // [nb] problem of each block
+    int *ijk = nullptr;        // [nb][3] block coordinates at this level
+    int *parent = nullptr;     // [nb] level-1 block containing the block (level >= 1)
+    int *octant = nullptr;     // [nb] octant of the parent the block fills (x + 2y + 4z)
+    int *gparent = nullptr;    // [ng] level-1 block containing each ghost block
+    int *goctant = nullptr;    // [ng] its octant
+    int *gprob = nullptr;      // [ng] problem of the ghost block
+    uint8_t *cov = nullptr;    // [nb] octants covered by level+1 blocks (bit x+2y+4z)
+    double *inv_h2 = nullptr;  // [nprob] 1 / h^2 of this level per problem (0 if absent)
+    double *inv_h = nullptr;   // [nprob] 1 / h
+    int *dense_map = nullptr;  // level 0 only: [nb] cell offset of the block's 4^3 coarse
+                               // cells inside the problem's first dense level (-1 level)
+    // refluxing: coarse cells of this level with faces next to covered cells
+    int nrf = 0;
+    int *rf = nullptr;         // [nrf][RF_INTS]
+};
+constexpr int RF_INTS = 16;    // block, cell, facemask, 6 x fine block, 6 x fine base cell, pad
+
+// Dense multigrid level (below level 0)
+struct DenseProbDev {
+    int nx, ny, nz;
+    int active;                // 1 if the level is not the problem's coarsest
+    long long off;             // first cell of the problem in a field of this level
+    double inv_h2;             // 1 / h^2 of this level
+};
+
+struct DenseLevelDev {
+    int ncells = 0;
+    int ntile = 0;             // 256-cell tiles of problems that are not coarsest here
+    int *tiles = nullptr;      // [ntile][2]: problem, first cell
+    int ntile_all = 0;         // tiles of every problem present
+    int *tiles_all = nullptr;
+    DenseProbDev *probs = nullptr;   // [nprob] (nx = 0 if the problem lacks the level)
+};
+
+}  // namespace ohm
+
+// ---------------------------------------------------------------------------
+// the handle
+// ---------------------------------------------------------------------------
+struct ohm_prob_host {
+    int nlevels;
+    int bb[3];
+    double dx0;
+    int min_level;                   // deepest multigrid level (<= -1)
+    int dims[16][3];                 // dense dims per depth d = -level (d >= 1)
+    long long boff[OHM_MAX_LEVELS];  // first block of the problem at each AMR level
+    int nb[OHM_MAX_LEVELS];
+    long long doff[16];              // first cell at each dense depth
+    std::vector<int32_t> blocks[OHM_MAX_LEVELS];
+};
+
+struct ohm_hier {
+    int nprob = 0;
+    int nlev = 0;                    // max AMR levels
+    int min_level = 0;               // most negative multigrid level
+    std::vector<ohm_prob_host> probs;
+    ohm::AmrLevelDev amr[OHM_MAX_LEVELS];
+    std::vector<int> nb_host;        // blocks per AMR level
+    std::vector<int> ng_host;        // ghosts per AMR level
+    ohm::DenseLevelDev dense[16];    // index d = -level
+    long long dense_cells[16] = {0};
+    // host copies used by the driver
+    std::vector<std::vector<int>> blk_prob_host;  // per level
+    // scratch for per-problem scalars uploaded by the primitives
+    double *d_scal = nullptr;        // [4 * nprob]
+    double *d_part = nullptr;        // reduction partials
+    size_t part_cap = 0;
+    double *d_norms = nullptr;       // [nprob * 6]
+    // ring of device slots for per-problem coefficients passed by the host to
+    // the primitive calls (slot reuse waits on the event of its last use)
+    double *d_ring = nullptr;        // [RING][nprob]
+    hipEvent_t ring_ev[64] = {};
+    bool ring_live[64] = {};
+    int ring_pos = 0;
+    // solver state cache
+    double *d_coarse_inv = nullptr;  // per-problem dense inverse of the coarsest grid
+    std::vector<long long> cinv_off; // element offset per problem, -1 if none
+    std::vector<int> cinv_n;         // unknowns per problem
+    std::vector<double> cinv_lamdt;  // lam_dt the inverse was built for
+    std::vector<int> cinv_prec;
+};
+
+namespace ohm {
+
+// launchers implemented in the kernel translation units ----------------------
+template <typename T>
+ohm_status launch_blk_stencil(const ohm_hier *h, int level, int mode, const T *B, const T *Bg,
+                              long long cs, long long gcs, const T *S, const T *eta, const T *etag,
+                              const double *coef_dev, T *out, int colour, double *partials,
+                              const uint8_t *cov_zero, const int *active, hipStream_t s);
+enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_SMOOTH = 2 };
+
+template <typename T>
+ohm_status launch_dense_stencil(const ohm_hier *h, int level, int mode, const T *B, const T *S,
+                                const T *eta, const double *coef_dev, T *out, int colour,
+                                bool coarsest_too, const int *active, hipStream_t s);
+
+template <typename T>
+ohm_status launch_restrict(const ohm_hier *h, int fine_level, const T *fine, long long fcs,
+                           T *coarse, long long ccs, int ncomp, const int *active, hipStream_t s);
+template <typename T>
+ohm_status launch_prolong(const ohm_hier *h, int coarse_level, const T *coarse, long long ccs,
+                          T *fine, long long fcs, int ncomp, int accumulate, const int *active,
+                          hipStream_t s);
+template <typename T>
+ohm_status launch_fill_ghosts(const ohm_hier *h, int level, const T *coarse, long long ccs,
+                              T *ghost, long long gcs, int ncomp, const int *active, hipStream_t s);
+template <typename T>
+ohm_status launch_reflux(const ohm_hier *h, int level, const T *Bc, long long ccs, const T *etac,
+                         const T *Bf, long long fcs, const T *Bfg, long long fgcs, const T *etaf,
+                         const T *etafg, const double *coef_dev, T *out, const int *active,
+                         hipStream_t s);
+template <typename T>
+ohm_status launch_zero_covered(const ohm_hier *h, int level, T *out, long long cs, int ncomp,
+                               hipStream_t s);
+
+// per-problem reduction of per-block partials [block][k] into out[nprob][k]:
+// range_dev holds [nprob][nrange][2] block ranges; quantities q < ksum are summed,
+// the others maxed
+ohm_status launch_reduce_problem(int nprob, int nrange, const long long *range_dev, const double *part, int k,
+                                 int ksum, double *out, hipStream_t s);
+template <typename T>
+ohm_status launch_restrict_blk(const ohm_hier *h, int fine_level, const T *fine, long long fcs, T *coarse,
+                               long long ccs, int ncomp, const int *active, hipStream_t s);
+template <typename T>
+ohm_status launch_prolong_blk(const ohm_hier *h, int coarse_level, const T *coarse, long long ccs, T *fine,
+                              long long fcs, int ncomp, int accumulate, const int *active, hipStream_t s);
+
+// dense multigrid levels (k_dense.hip)
+template <typename T>
+ohm_status launch_dense_restrict(const ohm_hier *h, int fine_level, const T *fine, T *coarse, int ncomp,
+                                 const int *active, hipStream_t s);
+template <typename T>
+ohm_status launch_dense_prolong(const ohm_hier *h, int coarse_level, const T *coarse, T *fine, int ncomp,
+                                int accumulate, const int *active, hipStream_t s);
+ohm_status coarse_sizes(const ohm_hier *h, size_t *inv_elems, size_t *aug_elems);
+size_t coarse_job_bytes();
+size_t coarse_job_count(const ohm_hier *h, int depth);
+ohm_status build_coarse_inverses(ohm_hier *h, const double *const *eta_dense, const double *lam_dt_host,
+                                 double *inv, double *aug, void *jobs_dev, hipStream_t s);
+ohm_status upload_coarse_jobs(const ohm_hier *h, int depth, void *jobs_dev, int *njobs, hipStream_t s);
+template <typename T>
+ohm_status launch_coarse_apply(const ohm_hier *h, int depth, const void *jobs_dev, int njobs, const double *inv,
+                               const T *r, T *e, const int *active, hipStream_t s);
+
+// vector kernels (k_vec.hip)
+template <typename T>
+ohm_status vfill(T *a, long long n, T v, hipStream_t s);
+template <typename S, typename D>
+ohm_status vconvert(const S *a, D *b, long long n, hipStream_t s);
+template <typename S, typename D>
+ohm_status vcopy_level(const S *a, long long acs, D *b, long long bcs, long long n, int ncomp, hipStream_t s);
+ohm_status vdot(int nblk, const int *prob_of, const int *active, long long cs, const double *const *x,
+                const double *const *y, int nq, double *part, hipStream_t s);
+ohm_status vnorms(int nblk, const int *prob_of, const int *active, long long cs, const double *x, double *part,
+                  hipStream_t s);
+ohm_status vbicg_p(int nblk, const int *prob_of, const int *active, long long cs, const double *scal,
+                   const double *r, const double *v, double *p, hipStream_t s);
+ohm_status vbicg_s(int nblk, const int *prob_of, const int *active, long long cs, const double *scal,
+                   const double *r, const double *v, double *sv, hipStream_t s);
+ohm_status vbicg_xr(int nblk, const int *prob_of, const int *active, long long cs, const double *scal, double *x,
+                    const double *ph, const double *sh, const double *sv, const double *t, double *r,
+                    const double *rhat, double *part, hipStream_t s);
+ohm_status vaxpy1(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,
+                  hipStream_t s);
+ohm_status vscal(int nprob, int stage, const int *active, const double *dots, int nq, double *scal, hipStream_t s);
+int scal_stride();
+
+}  // namespace ohm

@@ -1,0 +1,487 @@
+// Handle creation: validation of the block hierarchy and the device tables
+// (neighbours, coarse-fine ghost blocks, parents, covered octants, refluxing
+// faces, dense multigrid levels).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstring>
+#include <unordered_map>
+
+#include "common.h"
+
+namespace ohm {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+ohm_status fail(ohm_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+ohm_status check_launch(const char *what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(OHM_ERR_HIP, "launch of %s failed: %s", what, hipGetErrorString(e));
+    return OHM_OK;
+}
+
+namespace {
+
+inline int wrapi(int i, int n) { i %= n; return i < 0 ? i + n : i; }
+
+inline uint64_t key3(int i, int j, int k)
+{
+    return ((uint64_t)(uint32_t)i << 42) | ((uint64_t)(uint32_t)j << 21) | (uint64_t)(uint32_t)k;
+}
+
+struct LevelMap {
+    std::unordered_map<uint64_t, int> idx;  // block coords -> local index
+    int box[3];
+    bool has(int i, int j, int k) const
+    {
+        return idx.count(key3(wrapi(i, box[0]), wrapi(j, box[1]), wrapi(k, box[2]))) != 0;
+    }
+    int get(int i, int j, int k) const
+    {
+        auto it = idx.find(key3(wrapi(i, box[0]), wrapi(j, box[1]), wrapi(k, box[2])));
+        return it == idx.end() ? -1 : it->second;
+    }
+};
+
+bool coarsen_ok(const int n[3])
+{
+    return n[0] % 2 == 0 && n[1] % 2 == 0 && n[2] % 2 == 0 && n[0] >= 4 && n[1] >= 4 &&
+           n[2] >= 4 && (long long)n[0] * n[1] * n[2] > 64;
+}
+
+template <typename V>
+ohm_status upload(V **dptr, const std::vector<V> &h)
+{
+    *dptr = nullptr;
+    if (h.empty()) return OHM_OK;
+    OHM_HIP(hipMalloc((void **)dptr, sizeof(V) * h.size()));
+    OHM_HIP(hipMemcpy(*dptr, h.data(), sizeof(V) * h.size(), hipMemcpyHostToDevice));
+    return OHM_OK;
+}
+
+}  // namespace
+
+static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
+{
+    H->nprob = nprob;
+    H->probs.resize(nprob);
+    // ---- validate and record each problem -------------------------------
+    std::vector<std::vector<LevelMap>> maps(nprob);
+    for (int p = 0; p < nprob; ++p) {
+        const ohm_problem_desc &d = probs[p];
+        ohm_prob_host &P = H->probs[p];
+        if (d.nlevels < 1 || d.nlevels > OHM_MAX_LEVELS)
+            return fail(OHM_ERR_ARG, "problem %d: nlevels %d outside 1..%d", p, d.nlevels, OHM_MAX_LEVELS);
+        if (!(d.dx0 > 0.0)) return fail(OHM_ERR_ARG, "problem %d: dx0 must be positive", p);
+        for (int a = 0; a < 3; ++a)
+            if (d.base_blocks[a] < 1 || d.base_blocks[a] > 4096)
+                return fail(OHM_ERR_ARG, "problem %d: base_blocks[%d] = %d", p, a, d.base_blocks[a]);
+        P.nlevels = d.nlevels;
+        P.dx0 = d.dx0;
+        memcpy(P.bb, d.base_blocks, sizeof P.bb);
+        maps[p].resize(d.nlevels);
+        for (int l = 0; l < d.nlevels; ++l) {
+            if (d.nblocks[l] < 1 || !d.block_ijk[l])
+                return fail(OHM_ERR_ARG, "problem %d level %d: no blocks", p, l);
+            LevelMap &M = maps[p][l];
+            for (int a = 0; a < 3; ++a) M.box[a] = d.base_blocks[a] << l;
+            P.blocks[l].assign(d.block_ijk[l], d.block_ijk[l] + 3 * (size_t)d.nblocks[l]);
+            P.nb[l] = d.nblocks[l];
+            for (int b = 0; b < d.nblocks[l]; ++b) {
+                const int *q = &P.blocks[l][3 * b];
+                for (int a = 0; a < 3; ++a)
+                    if (q[a] < 0 || q[a] >= M.box[a])
+                        return fail(OHM_ERR_LAYOUT, "problem %d level %d block %d: (%d,%d,%d) outside the box",
+                                    p, l, b, q[0], q[1], q[2]);
+                if (!M.idx.emplace(key3(q[0], q[1], q[2]), b).second)
+                    return fail(OHM_ERR_LAYOUT, "problem %d level %d: duplicate block (%d,%d,%d)", p, l,
+                                q[0], q[1], q[2]);
+            }
+        }
+        long long full = (long long)d.base_blocks[0] * d.base_blocks[1] * d.base_blocks[2];
+        if (d.nblocks[0] != full)
+            return fail(OHM_ERR_LAYOUT, "problem %d: level 0 has %d blocks, the box needs %lld", p,
+                        d.nblocks[0], full);
+        // proper nesting: the 1-cell dilation of every level block and of every
+        // face/edge neighbour position lies in level-(l-1) blocks
+        for (int l = 1; l < d.nlevels; ++l) {
+            const LevelMap &M = maps[p][l], &C = maps[p][l - 1];
+            for (int b = 0; b < d.nblocks[l]; ++b) {
+                const int *q = &P.blocks[l][3 * b];
+                for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int nz_ = (dx != 0) + (dy != 0) + (dz != 0);
+                    if (nz_ == 3) continue;
+                    int n[3] = {q[0] + dx, q[1] + dy, q[2] + dz};
+                    if (nz_ > 0 && M.has(n[0], n[1], n[2])) continue;
+                    // coarse cells [4n-1, 4n+4] per axis -> coarse blocks
+                    int lo[3], hi[3];
+                    for (int a = 0; a < 3; ++a) {
+                        lo[a] = (int)std::floor((4.0 * n[a] - 1) / 8.0);
+                        hi[a] = (int)std::floor((4.0 * n[a] + 4) / 8.0);
+                    }
+                    for (int ck = lo[2]; ck <= hi[2]; ++ck)
+                    for (int cj = lo[1]; cj <= hi[1]; ++cj)
+                    for (int ci = lo[0]; ci <= hi[0]; ++ci)
+                        if (!C.has(ci, cj, ck))
+                            return fail(OHM_ERR_LAYOUT,
+                                        "problem %d: level %d block (%d,%d,%d) is not properly nested in "
+                                        "level %d (coarse block (%d,%d,%d) missing)",
+                                        p, l, q[0], q[1], q[2], l - 1, wrapi(ci, C.box[0]),
+                                        wrapi(cj, C.box[1]), wrapi(ck, C.box[2]));
+                }
+            }
+        }
+        // multigrid coarsenings of the base grid
+        int n[3] = {8 * d.base_blocks[0], 8 * d.base_blocks[1], 8 * d.base_blocks[2]};
+        int depth = 0;
+        while (coarsen_ok(n)) {
+            if (depth + 1 >= 16) break;
+            for (int a = 0; a < 3; ++a) n[a] /= 2;
+            ++depth;
+            for (int a = 0; a < 3; ++a) P.dims[depth][a] = n[a];
+        }
+        P.min_level = -depth;
+    }
+    // ---- global level sizes -------------------------------------------------
+    H->nlev = 0;
+    H->min_level = 0;
+    for (auto &P : H->probs) {
+        H->nlev = std::max(H->nlev, P.nlevels);
+        H->min_level = std::min(H->min_level, P.min_level);
+    }
+    H->nb_host.assign(H->nlev, 0);
+    H->ng_host.assign(H->nlev, 0);
+    H->blk_prob_host.assign(H->nlev, {});
+    for (int l = 0; l < H->nlev; ++l)
+        for (int p = 0; p < nprob; ++p) {
+            ohm_prob_host &P = H->probs[p];
+            if (l < P.nlevels) {
+                P.boff[l] = H->nb_host[l];
+                H->nb_host[l] += P.nb[l];
+                for (int b = 0; b < P.nb[l]; ++b) H->blk_prob_host[l].push_back(p);
+            } else {
+                P.boff[l] = -1;
+                P.nb[l] = 0;
+            }
+        }
+    for (int dd = 1; dd <= -H->min_level; ++dd) {
+        long long c = 0;
+        for (auto &P : H->probs) {
+            if (-P.min_level >= dd) {
+                P.doff[dd] = c;
+                c += (long long)P.dims[dd][0] * P.dims[dd][1] * P.dims[dd][2];
+            } else {
+                P.doff[dd] = -1;
+            }
+        }
+        H->dense_cells[dd] = c;
+    }
+    // ---- AMR level tables ---------------------------------------------------
+    for (int l = 0; l < H->nlev; ++l) {
+        AmrLevelDev &L = H->amr[l];
+        L.nb = H->nb_host[l];
+        std::vector<int> nbr((size_t)L.nb * 27, NBR_NONE), prob(L.nb), ijk((size_t)L.nb * 3);
+        std::vector<int> parent(L.nb, -1), octant(L.nb, 0), dmap;
+        std::vector<int> gparent, goctant, gprob;
+        std::vector<uint8_t> cov(L.nb, 0);
+        if (l == 0) dmap.assign(L.nb, -1);
+        int ng = 0;
+        for (int p = 0; p < nprob; ++p) {
+            ohm_prob_host &P = H->probs[p];
+            if (l >= P.nlevels) continue;
+            const LevelMap &M = maps[p][l];
+            std::unordered_map<uint64_t, int> ghost_of;
+            for (int b = 0; b < P.nb[l]; ++b) {
+                int gb = (int)P.boff[l] + b;
+                const int *q = &P.blocks[l][3 * b];
+                prob[gb] = p;
+                for (int a = 0; a < 3; ++a) ijk[3 * gb + a] = q[a];
+                for (int dz = -1; dz <= 1; ++dz)
+                for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    int e = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+                    int n = M.get(q[0] + dx, q[1] + dy, q[2] + dz);
+                    if (n >= 0) {
+                        nbr[27 * (size_t)gb + e] = (int)P.boff[l] + n;
+                        continue;
+                    }
+                    if ((dx != 0) + (dy != 0) + (dz != 0) == 3) continue;  // corners: unused
+                    int w[3] = {wrapi(q[0] + dx, M.box[0]), wrapi(q[1] + dy, M.box[1]),
+                                wrapi(q[2] + dz, M.box[2])};
+                    uint64_t k = key3(w[0], w[1], w[2]);
+                    auto it = ghost_of.find(k);
+                    int g;
+                    if (it == ghost_of.end()) {
+                        g = ng++;
+                        ghost_of.emplace(k, g);
+                        const LevelMap &C = maps[p][l - 1];
+                        int pb = C.get(w[0] >> 1, w[1] >> 1, w[2] >> 1);
+                        if (pb < 0) return fail(OHM_ERR_LAYOUT, "internal: ghost without parent");
+                        gparent.push_back((int)P.boff[l - 1] + pb);
+                        goctant.push_back((w[0] & 1) + 2 * (w[1] & 1) + 4 * (w[2] & 1));
+                        gprob.push_back(p);
+                    } else {
+                        g = it->second;
+                    }
+                    nbr[27 * (size_t)gb + e] = -1 - g;
+                }
+                if (l >= 1) {
+                    const LevelMap &C = maps[p][l - 1];
+                    int pb = C.get(q[0] >> 1, q[1] >> 1, q[2] >> 1);
+                    parent[gb] = (int)P.boff[l - 1] + pb;
+                    octant[gb] = (q[0] & 1) + 2 * (q[1] & 1) + 4 * (q[2] & 1);
+                }
+                if (l + 1 < P.nlevels) {
+                    const LevelMap &F = maps[p][l + 1];
+                    for (int o = 0; o < 8; ++o)
+                        if (F.has(2 * q[0] + (o & 1), 2 * q[1] + ((o >> 1) & 1), 2 * q[2] + (o >> 2)))
+                            cov[gb] |= (uint8_t)(1u << o);
+                }
+                if (l == 0) {
+                    const int *dn = P.dims[1];
+                    dmap[gb] = (int)(P.doff[1] + ((long long)(4 * q[2]) * dn[1] + 4 * q[1]) * dn[0] + 4 * q[0]);
+                }
+            }
+        }
+        L.ng = ng;
+        H->ng_host[l] = ng;
+        std::vector<double> ih2(nprob, 0.0), ih(nprob, 0.0);
+        for (int p = 0; p < nprob; ++p)
+            if (l < H->probs[p].nlevels) {
+                double hh = H->probs[p].dx0 / (double)(1 << l);
+                ih[p] = 1.0 / hh;
+                ih2[p] = 1.0 / (hh * hh);
+            }
+        OHM_TRY(upload(&L.inv_h2, ih2));
+        OHM_TRY(upload(&L.inv_h, ih));
+        OHM_TRY(upload(&L.nbr, nbr));
+        OHM_TRY(upload(&L.prob, prob));
+        OHM_TRY(upload(&L.ijk, ijk));
+        OHM_TRY(upload(&L.cov, cov));
+        if (l >= 1) {
+            OHM_TRY(upload(&L.parent, parent));
+            OHM_TRY(upload(&L.octant, octant));
+            OHM_TRY(upload(&L.gparent, gparent));
+            OHM_TRY(upload(&L.goctant, goctant));
+            OHM_TRY(upload(&L.gprob, gprob));
+        }
+        if (l == 0) OHM_TRY(upload(&L.dense_map, dmap));
+    }
+    // ---- refluxing faces: leaf cells of level l next to covered cells --------
+    for (int l = 0; l + 1 < H->nlev; ++l) {
+        std::vector<int> rf;
+        for (int p = 0; p < nprob; ++p) {
+            ohm_prob_host &P = H->probs[p];
+            if (l + 1 >= P.nlevels) continue;
+            const LevelMap &M = maps[p][l], &F = maps[p][l + 1];
+            int box[3] = {M.box[0] * NB, M.box[1] * NB, M.box[2] * NB};
+            auto covered = [&](int X, int Y, int Z) {   // level-l global cell
+                X = wrapi(X, box[0]); Y = wrapi(Y, box[1]); Z = wrapi(Z, box[2]);
+                return F.has(X >> 2, Y >> 2, Z >> 2);    // fine block covering the cell
+            };
+            for (int b = 0; b < P.nb[l]; ++b) {
+                const int *q = &P.blocks[l][3 * b];
+                for (int z = 0; z < NB; ++z)
+                for (int y = 0; y < NB; ++y)
+                for (int x = 0; x < NB; ++x) {
+                    int X = q[0] * NB + x, Y = q[1] * NB + y, Z = q[2] * NB + z;
+                    if (covered(X, Y, Z)) continue;
+                    int ent[RF_INTS];
+                    for (int t = 0; t < RF_INTS; ++t) ent[t] = -1;
+                    int mask = 0;
+                    for (int d = 0; d < 3; ++d)
+                        for (int s = 0; s < 2; ++s) {
+                            int sg = s ? -1 : 1;
+                            int Q[3] = {X, Y, Z};
+                            Q[d] += sg;
+                            if (!covered(Q[0], Q[1], Q[2])) continue;
+                            int f = 2 * d + s;
+                            mask |= 1 << f;
+                            for (int a = 0; a < 3; ++a) Q[a] = wrapi(Q[a], box[a]);
+                            int fb = F.get(Q[0] >> 2, Q[1] >> 2, Q[2] >> 2);
+                            // fine children of Q next to the face: along d the
+                            // low child (2Q) when Q is above, the high one (2Q+1)
+                            // when below; transverse the low child 2Q_t
+                            int fl[3];
+                            for (int a = 0; a < 3; ++a)
+                                fl[a] = 2 * Q[a] - NB * (Q[a] >> 2);   // local fine index
+                            if (sg < 0) fl[d] += 1;
+                            ent[3 + f] = (int)P.boff[l + 1] + fb;
+                            ent[9 + f] = fl[0] + NB * (fl[1] + NB * fl[2]);
+                        }
+                    if (!mask) continue;
+                    ent[0] = (int)P.boff[l] + b;
+                    ent[1] = x + NB * (y + NB * z);
+                    ent[2] = mask;
+                    ent[15] = p;
+                    rf.insert(rf.end(), ent, ent + RF_INTS);
+                }
+            }
+        }
+        H->amr[l].nrf = (int)(rf.size() / RF_INTS);
+        OHM_TRY(upload(&H->amr[l].rf, rf));
+    }
+    // ---- dense levels ---------------------------------------------------------
+    for (int dd = 1; dd <= -H->min_level; ++dd) {
+        DenseLevelDev &D = H->dense[dd];
+        D.ncells = (int)H->dense_cells[dd];
+        std::vector<DenseProbDev> dp(nprob);
+        std::vector<int> tiles, tiles_all;
+        for (int p = 0; p < nprob; ++p) {
+            ohm_prob_host &P = H->probs[p];
+            DenseProbDev &q = dp[p];
+            memset(&q, 0, sizeof q);
+            if (-P.min_level < dd) continue;
+            q.nx = P.dims[dd][0];
+            q.ny = P.dims[dd][1];
+            q.nz = P.dims[dd][2];
+            q.active = (-P.min_level > dd) ? 1 : 0;
+            q.off = P.doff[dd];
+            double h = P.dx0 * (double)(1 << dd);
+            q.inv_h2 = 1.0 / (h * h);
+            int nc = q.nx * q.ny * q.nz;
+            for (int s = 0; s < nc; s += 256) {
+                tiles_all.push_back(p);
+                tiles_all.push_back(s);
+                if (q.active) {
+                    tiles.push_back(p);
+                    tiles.push_back(s);
+                }
+            }
+        }
+        D.ntile = (int)tiles.size() / 2;
+        D.ntile_all = (int)tiles_all.size() / 2;
+        OHM_TRY(upload(&D.tiles, tiles));
+        OHM_TRY(upload(&D.tiles_all, tiles_all));
+        OHM_TRY(upload(&D.probs, dp));
+    }
+    // ---- scratch ---------------------------------------------------------------
+    OHM_HIP(hipMalloc((void **)&H->d_scal, sizeof(double) * 4 * nprob));
+    OHM_HIP(hipMalloc((void **)&H->d_norms, sizeof(double) * 8 * nprob));
+    size_t maxnb = 1;
+    for (int l = 0; l < H->nlev; ++l) maxnb = std::max(maxnb, (size_t)H->nb_host[l]);
+    H->part_cap = maxnb * 8 + 2 * (size_t)nprob * OHM_MAX_LEVELS + 64;
+    OHM_HIP(hipMalloc((void **)&H->d_part, sizeof(double) * H->part_cap));
+    H->cinv_off.assign(nprob, -1);
+    H->cinv_n.assign(nprob, 0);
+    H->cinv_lamdt.assign(nprob, -1.0);
+    H->cinv_prec.assign(nprob, -1);
+    return OHM_OK;
+}
+
+static void free_all(ohm_hier *H)
+{
+    for (int l = 0; l < OHM_MAX_LEVELS; ++l) {
+        AmrLevelDev &L = H->amr[l];
+        void *ptrs[] = {L.nbr, L.prob, L.ijk, L.parent, L.octant, L.gparent, L.goctant, L.gprob,
+                        L.cov, L.dense_map, L.rf, L.inv_h2, L.inv_h};
+        for (void *q : ptrs)
+            if (q) (void)hipFree(q);
+    }
+    for (int d = 0; d < 16; ++d) {
+        DenseLevelDev &D = H->dense[d];
+        void *ptrs[] = {D.tiles, D.tiles_all, D.probs};
+        for (void *q : ptrs)
+            if (q) (void)hipFree(q);
+    }
+    void *ptrs[] = {H->d_scal, H->d_part, H->d_norms, H->d_coarse_inv, H->d_ring};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    for (int i = 0; i < 64; ++i)
+        if (H->ring_ev[i]) (void)hipEventDestroy(H->ring_ev[i]);
+}
+
+}  // namespace ohm
+
+using namespace ohm;
+
+extern "C" {
+
+const char *ohm_last_error(void) { return g_err.c_str(); }
+
+ohm_status ohm_hier_create(const ohm_problem_desc *probs, int32_t nprob, hipStream_t stream,
+                           ohm_hier **out)
+{
+    (void)stream;
+    if (!out) return fail(OHM_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!probs || nprob < 1) return fail(OHM_ERR_ARG, "need at least one problem");
+    ohm_hier *H = new (std::nothrow) ohm_hier();
+    if (!H) return fail(OHM_ERR_NOMEM, "host allocation failed");
+    ohm_status st = build(H, probs, nprob);
+    if (st != OHM_OK) {
+        free_all(H);
+        delete H;
+        return st;
+    }
+    *out = H;
+    return OHM_OK;
+}
+
+ohm_status ohm_hier_destroy(ohm_hier *h)
+{
+    if (!h) return OHM_OK;
+    free_all(h);
+    delete h;
+    return OHM_OK;
+}
+
+ohm_status ohm_hier_level_info(const ohm_hier *h, int32_t level, int64_t *nblocks, int64_t *ncells,
+                               int64_t *nghost)
+{
+    if (!h) return fail(OHM_ERR_ARG, "handle is NULL");
+    int64_t nb = 0, nc = 0, ng = 0;
+    if (level >= 0) {
+        if (level >= h->nlev) return fail(OHM_ERR_ARG, "level %d >= %d", level, h->nlev);
+        nb = h->nb_host[level];
+        nc = nb * NC;
+        ng = h->ng_host[level];
+    } else {
+        if (level < h->min_level) return fail(OHM_ERR_ARG, "level %d below %d", level, h->min_level);
+        nc = h->dense_cells[-level];
+    }
+    if (nblocks) *nblocks = nb;
+    if (ncells) *ncells = nc;
+    if (nghost) *nghost = ng;
+    return OHM_OK;
+}
+
+ohm_status ohm_hier_problem_info(const ohm_hier *h, int32_t prob, int32_t level, int64_t *cell_offset,
+                                 int32_t dims[3], int32_t *min_level)
+{
+    if (!h) return fail(OHM_ERR_ARG, "handle is NULL");
+    if (prob < 0 || prob >= h->nprob) return fail(OHM_ERR_ARG, "problem %d out of range", prob);
+    const ohm_prob_host &P = h->probs[prob];
+    if (min_level) *min_level = P.min_level;
+    int64_t off = -1;
+    int32_t d3[3] = {0, 0, 0};
+    if (level >= 0) {
+        if (level < P.nlevels) {
+            off = P.boff[level] * NC;
+            for (int a = 0; a < 3; ++a) d3[a] = NB * (P.bb[a] << level);
+        }
+    } else if (level >= P.min_level) {
+        off = P.doff[-level];
+        for (int a = 0; a < 3; ++a) d3[a] = P.dims[-level][a];
+    }
+    if (cell_offset) *cell_offset = off;
+    if (dims) memcpy(dims, d3, sizeof d3);
+    return OHM_OK;
+}
+
+}  // extern "C"

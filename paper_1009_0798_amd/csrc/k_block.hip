@@ -1,0 +1,509 @@
+// Kernels on the 8^3-cell blocks of AMR levels: operator apply, residual and
+// red-black half-sweep (one workgroup per block, block plus a one-cell face and
+// edge halo staged in LDS), restriction, prolongation, coarse-fine ghost fill,
+// refluxing and per-problem norm reductions.
+#include "common.h"
+#include "stencil.h"
+
+namespace ohm {
+
+namespace {
+
+constexpr int TW = NB + 2;             // tile edge with a one-cell halo
+constexpr int TC = TW * TW * TW;       // tile cells
+
+// Workgroups are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+// run of blocks (blocks are in Z-order, so a compact region whose halo stays
+// in that XCD's L2).
+__device__ __forceinline__ int xcd_block(int w, int n)
+{
+    int q = n / NXCD, r = n % NXCD;
+    int x = w % NXCD, i = w / NXCD;
+    return x * q + min(x, r) + i;
+}
+
+__device__ __forceinline__ int side(int c) { return c < 0 ? -1 : (c >= NB ? 1 : 0); }
+
+// Load component arrays of block b plus halo into LDS tile(s).
+template <typename T, int NCOMP>
+__device__ __forceinline__ void load_tile(T (*tile)[TC], const T *f, const T *g, long long cs,
+                                          long long gcs, const int *nbr)
+{
+    for (int t = threadIdx.x; t < TC; t += blockDim.x) {
+        int x = t % TW - 1, y = (t / TW) % TW - 1, z = t / (TW * TW) - 1;
+        int sx = side(x), sy = side(y), sz = side(z);
+        int n = nbr[(sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
+        int li = (x - NB * sx) + NB * ((y - NB * sy) + NB * (z - NB * sz));
+        if (n >= 0) {
+#pragma unroll
+            for (int c = 0; c < NCOMP; ++c) tile[c][t] = f[c * cs + (long long)n * NC + li];
+        } else if (n != NBR_NONE) {
+            int gi = -1 - n;
+#pragma unroll
+            for (int c = 0; c < NCOMP; ++c) tile[c][t] = g[c * gcs + (long long)gi * NC + li];
+        } else {
+#pragma unroll
+            for (int c = 0; c < NCOMP; ++c) tile[c][t] = T(0);
+        }
+    }
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256)
+k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ prob_of,
+              const uint8_t *__restrict__ cov_zero, const int *__restrict__ active,
+              const double *__restrict__ inv_h2_p, const double *__restrict__ coef_p,
+              const T *__restrict__ B, const T *__restrict__ Bg, long long cs, long long gcs,
+              const T *__restrict__ S, const T *__restrict__ eta, const T *__restrict__ etag,
+              T *__restrict__ out, int colour, double *__restrict__ partials)
+{
+    __shared__ T sB[3][TC];
+    __shared__ T sE[1][TC];
+    __shared__ int snbr[27];
+    __shared__ double sred[6][4];
+    const int b = xcd_block(blockIdx.x, nblk);
+    const int pr = prob_of[b];
+    if (active && !active[pr]) return;
+    if (threadIdx.x < 27) snbr[threadIdx.x] = nbr_tab[27 * (long long)b + threadIdx.x];
+    __syncthreads();
+    load_tile<T, 3>(sB, B, Bg, cs, gcs, snbr);
+    load_tile<T, 1>(sE, eta, etag, 0, 0, snbr);
+    __syncthreads();
+    const T ih2 = T(inv_h2_p[pr]);
+    const T coef = T(coef_p[pr]);
+    const uint8_t cov = cov_zero ? cov_zero[b] : 0;
+    double ss[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int cell = threadIdx.x + 256 * half;
+        const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
+        const int p = (x + 1) + TW * ((y + 1) + TW * (z + 1));
+        const bool zero = (cov >> ((x >> 2) + 2 * (y >> 2) + 4 * (z >> 2))) & 1;
+        const long long gi = (long long)b * NC + cell;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T dv = divF_cube<T, TW>(sB[0], sB[1], sB[2], sE[0], p, c) * ih2;
+            T LB = sB[c][p] + coef * dv;
+            if (MODE == MODE_APPLY) {
+                out[c * cs + gi] = zero ? T(0) : LB;
+            } else if (MODE == MODE_RESID) {
+                T r = zero ? T(0) : S[c * cs + gi] - LB;
+                if (out) out[c * cs + gi] = r;
+                double rd = (double)r;
+                ss[c] += rd * rd;
+                mx[c] = fmax(mx[c], fabs(rd));
+            } else {  // smoother half-sweep
+                T v = sB[c][p];
+                if (((x + y + z) & 1) == colour) {
+                    T r = S[c * cs + gi] - LB;
+                    v += r / (T(1) + coef * ih2 * alpha_cube<T, TW>(sE[0], p, c));
+                }
+                out[c * cs + gi] = v;
+            }
+        }
+    }
+    if (MODE == MODE_RESID && partials) {
+        // wavefront reduction, then across the 4 wavefronts in fixed order
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double a = ss[c], m = mx[c];
+            for (int o = 32; o > 0; o >>= 1) {
+                a += __shfl_down(a, o, 64);
+                m = fmax(m, __shfl_down(m, o, 64));
+            }
+            if (lane == 0) {
+                sred[c][wv] = a;
+                sred[3 + c][wv] = m;
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < 6) {
+            int k = threadIdx.x;
+            double v = sred[k][0];
+            for (int w = 1; w < 4; ++w) v = (k < 3) ? v + sred[k][w] : fmax(v, sred[k][w]);
+            partials[6 * (long long)b + k] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// restriction: fine block -> the octant of its parent block (AMR levels), and
+// level-0 block -> the first dense level
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_restrict_blk(int nfine, const int *__restrict__ parent, const int *__restrict__ octant,
+               const int *__restrict__ fprob, const int *__restrict__ active, const T *__restrict__ fine,
+               long long fcs, T *__restrict__ coarse, long long ccs, int ncomp)
+{
+    const int b = xcd_block(blockIdx.x, nfine);
+    if (active && !active[fprob[b]]) return;
+    const int t = threadIdx.x;          // 4^3 coarse cells of the octant
+    const int i = t & 3, j = (t >> 2) & 3, k = t >> 4;
+    const int o = octant[b];
+    const int ci = 4 * (o & 1) + i, cj = 4 * ((o >> 1) & 1) + j, ck = 4 * (o >> 2) + k;
+    const long long cidx = (long long)parent[b] * NC + ci + NB * (cj + NB * ck);
+    for (int c = 0; c < ncomp; ++c) {
+        const T *f = fine + c * fcs + (long long)b * NC;
+        T s = T(0);
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx) s += f[(2 * i + dx) + NB * ((2 * j + dy) + NB * (2 * k + dz))];
+        coarse[c * ccs + cidx] = s * T(0.125);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(64)
+k_restrict_blk0_dense(int nblk, const int *__restrict__ dense_map, const int *__restrict__ prob_of,
+                      const DenseProbDev *__restrict__ dp, const int *__restrict__ active,
+                      const T *__restrict__ fine, long long fcs, T *__restrict__ coarse, long long ccs,
+                      int ncomp)
+{
+    const int b = xcd_block(blockIdx.x, nblk);
+    const int pr = prob_of[b];
+    if (active && !active[pr]) return;
+    const int t = threadIdx.x;
+    const int i = t & 3, j = (t >> 2) & 3, k = t >> 4;
+    const DenseProbDev q = dp[pr];
+    const long long cidx = dense_map[b] + i + (long long)q.nx * (j + (long long)q.ny * k);
+    for (int c = 0; c < ncomp; ++c) {
+        const T *f = fine + c * fcs + (long long)b * NC;
+        T s = T(0);
+#pragma unroll
+        for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                for (int dx = 0; dx < 2; ++dx) s += f[(2 * i + dx) + NB * ((2 * j + dy) + NB * (2 * k + dz))];
+        coarse[c * ccs + cidx] = s * T(0.125);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// prolongation (cell-centred trilinear, 27/9/3/1 over 64) into fine blocks or
+// ghost blocks from their parent block (and its neighbours) one level coarser
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_prolong_blk(int nfine, const int *__restrict__ parent, const int *__restrict__ octant,
+              const int *__restrict__ fprob, const int *__restrict__ active, const int *__restrict__ cnbr,
+              const T *__restrict__ coarse, long long ccs, T *__restrict__ fine, long long fcs, int ncomp,
+              int accumulate)
+{
+    // coarse region of the octant plus a one-cell halo: 6^3 cells
+    __shared__ T sc[3][216];
+    __shared__ int snbr[27];
+    const int b = xcd_block(blockIdx.x, nfine);
+    if (active && !active[fprob[b]]) return;
+    const int pb = parent[b];
+    const int o = octant[b];
+    const int ox = 4 * (o & 1), oy = 4 * ((o >> 1) & 1), oz = 4 * (o >> 2);
+    if (threadIdx.x < 27) snbr[threadIdx.x] = cnbr[27 * (long long)pb + threadIdx.x];
+    __syncthreads();
+    for (int t = threadIdx.x; t < 216; t += blockDim.x) {
+        int x = ox - 1 + t % 6, y = oy - 1 + (t / 6) % 6, z = oz - 1 + t / 36;
+        int sx = side(x), sy = side(y), sz = side(z);
+        int n = snbr[(sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
+        int li = (x - NB * sx) + NB * ((y - NB * sy) + NB * (z - NB * sz));
+        for (int c = 0; c < ncomp; ++c) sc[c][t] = (n >= 0) ? coarse[c * ccs + (long long)n * NC + li] : T(0);
+    }
+    __syncthreads();
+    for (int cell = threadIdx.x; cell < NC; cell += blockDim.x) {
+        const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
+        // parent cell in the 6^3 tile and the side of the fine cell
+        const int px = (x >> 1) + 1, py = (y >> 1) + 1, pz = (z >> 1) + 1;
+        const int sx = (x & 1) ? 1 : -1, sy = (y & 1) ? 1 : -1, sz = (z & 1) ? 1 : -1;
+        const int p0 = px + 6 * (py + 6 * pz);
+        const int qx = sx, qy = 6 * sy, qz = 36 * sz;
+        for (int c = 0; c < ncomp; ++c) {
+            const T *C = sc[c];
+            T v = T(27) * C[p0] + T(9) * (C[p0 + qx] + C[p0 + qy] + C[p0 + qz]) +
+                  T(3) * (C[p0 + qx + qy] + C[p0 + qx + qz] + C[p0 + qy + qz]) + C[p0 + qx + qy + qz];
+            v *= T(1.0 / 64.0);
+            long long gi = c * fcs + (long long)b * NC + cell;
+            fine[gi] = accumulate ? fine[gi] + v : v;
+        }
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_prolong_dense_blk0(int nblk, const int *__restrict__ ijk, const int *__restrict__ prob_of,
+                     const DenseProbDev *__restrict__ dp, const int *__restrict__ active,
+                     const T *__restrict__ coarse, long long ccs, T *__restrict__ fine, long long fcs,
+                     int ncomp, int accumulate)
+{
+    const int b = xcd_block(blockIdx.x, nblk);
+    const int pr = prob_of[b];
+    if (active && !active[pr]) return;
+    const DenseProbDev q = dp[pr];
+    const int bi = ijk[3 * b], bj = ijk[3 * b + 1], bk = ijk[3 * b + 2];
+    for (int cell = threadIdx.x; cell < NC; cell += blockDim.x) {
+        const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
+        const int X = NB * bi + x, Y = NB * bj + y, Z = NB * bk + z;
+        const int i = X >> 1, j = Y >> 1, k = Z >> 1;
+        const int si = (X & 1) ? 1 : -1, sj = (Y & 1) ? 1 : -1, sk = (Z & 1) ? 1 : -1;
+        const int i1 = (i + si + q.nx) % q.nx, j1 = (j + sj + q.ny) % q.ny, k1 = (k + sk + q.nz) % q.nz;
+        auto at = [&](int a, int bb, int cc) { return q.off + a + (long long)q.nx * (bb + (long long)q.ny * cc); };
+        for (int c = 0; c < ncomp; ++c) {
+            const T *C = coarse + c * ccs;
+            T v = T(27) * C[at(i, j, k)] + T(9) * (C[at(i1, j, k)] + C[at(i, j1, k)] + C[at(i, j, k1)]) +
+                  T(3) * (C[at(i1, j1, k)] + C[at(i1, j, k1)] + C[at(i, j1, k1)]) + C[at(i1, j1, k1)];
+            v *= T(1.0 / 64.0);
+            long long gi = c * fcs + (long long)b * NC + cell;
+            fine[gi] = accumulate ? fine[gi] + v : v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// refluxing (section 4): one thread per coarse leaf cell with coarse-fine faces
+// ---------------------------------------------------------------------------
+// value of component c at local coordinates (x,y,z) in [-1, 8] of block b
+template <typename T>
+__device__ __forceinline__ T fetch(const T *f, const T *g, long long cs, long long gcs, const int *nbr_tab,
+                                   int b, int x, int y, int z, int c)
+{
+    int sx = side(x), sy = side(y), sz = side(z);
+    int n = b;
+    if (sx | sy | sz) n = nbr_tab[27 * (long long)b + (sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
+    int li = (x - NB * sx) + NB * ((y - NB * sy) + NB * (z - NB * sz));
+    if (n >= 0) return f[c * cs + (long long)n * NC + li];
+    return g[c * gcs + (long long)(-1 - n) * NC + li];
+}
+
+// flux F_d[c] times h through the face between cell q and q + e_d (q local to
+// block b, possibly one cell outside it)
+template <typename T>
+__device__ T face_flux_h(const T *Bf, const T *Bg, long long cs, long long gcs, const T *E, const T *Eg,
+                         const int *nbr_tab, int b, const int q[3], int d, int c)
+{
+    int a[3] = {q[0], q[1], q[2]};
+    int qd[3] = {q[0], q[1], q[2]};
+    qd[d] += 1;
+    auto F = [&](const int r[3], int comp) { return fetch<T>(Bf, Bg, cs, gcs, nbr_tab, b, r[0], r[1], r[2], comp); };
+    auto Ee = [&](const int r[3]) { return fetch<T>(E, Eg, 0, 0, nbr_tab, b, r[0], r[1], r[2], 0); };
+    T ef = (Ee(a) + Ee(qd)) * T(0.5);
+    int p1[3] = {a[0], a[1], a[2]}, p2[3] = {a[0], a[1], a[2]}, p3[3] = {qd[0], qd[1], qd[2]},
+        p4[3] = {qd[0], qd[1], qd[2]};
+    p1[c] += 1;
+    p2[c] -= 1;
+    p3[c] += 1;
+    p4[c] -= 1;
+    T tr = (F(p1, d) + F(p3, d) - F(p2, d) - F(p4, d)) * T(0.25);
+    return ef * (tr - (F(qd, c) - F(a, c)));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(128)
+k_reflux(int nrf, const int *__restrict__ rf, const int *__restrict__ active, const int *__restrict__ cnbr,
+         const int *__restrict__ fnbr, const double *__restrict__ inv_h_c, const double *__restrict__ coef_p,
+         const T *__restrict__ Bc, long long ccs, const T *__restrict__ Ec, const T *__restrict__ Bf,
+         long long fcs, const T *__restrict__ Bfg, long long fgcs, const T *__restrict__ Ef,
+         const T *__restrict__ Efg, T *__restrict__ out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nrf) return;
+    const int *ent = rf + RF_INTS * (long long)e;
+    const int pr = ent[15];
+    if (active && !active[pr]) return;
+    const int cb = ent[0], cell = ent[1], mask = ent[2];
+    const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
+    const T ih = T(inv_h_c[pr]);       // coarse 1/h; fine fluxes carry h_f = h/2
+    const T coef = T(coef_p[pr]);
+    T add[3] = {T(0), T(0), T(0)};
+    for (int f = 0; f < 6; ++f) {
+        if (!((mask >> f) & 1)) continue;
+        const int d = f >> 1;
+        const int sg = (f & 1) ? -1 : 1;
+        const int fb = ent[3 + f], fbase = ent[9 + f];
+        const int fx = fbase & 7, fy = (fbase >> 3) & 7, fz = fbase >> 6;
+        for (int c = 0; c < 3; ++c) {
+            if (c == d) continue;
+            // coarse flux on the face: after cell p (sg = +1) or after p - e_d
+            int qc[3] = {x, y, z};
+            if (sg < 0) qc[d] -= 1;
+            T Fc = face_flux_h<T>(Bc, Bc, ccs, ccs, Ec, Ec, cnbr, cb, qc, d, c) * ih;
+            // the 4 fine faces: the covered-side children start at fbase; the
+            // face is after the child (sg < 0) or after the child - e_d (sg > 0)
+            T Ff = T(0);
+            const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
+            for (int a1 = 0; a1 < 2; ++a1)
+                for (int a2 = 0; a2 < 2; ++a2) {
+                    int q[3] = {fx, fy, fz};
+                    q[t1] += a1;
+                    q[t2] += a2;
+                    if (sg > 0) q[d] -= 1;
+                    Ff += face_flux_h<T>(Bf, Bfg, fcs, fgcs, Ef, Efg, fnbr, fb, q, d, c);
+                }
+            Ff *= T(0.25) * (ih * T(2));
+            add[c] += T(sg) * (Ff - Fc) * ih;
+        }
+    }
+    const long long gi = (long long)cb * NC + cell;
+    for (int c = 0; c < 3; ++c)
+        if (add[c] != T(0)) out[c * ccs + gi] += coef * add[c];
+}
+
+template <typename T>
+__global__ void k_zero_covered(int nblk, const uint8_t *__restrict__ cov, T *__restrict__ out, long long cs,
+                               int ncomp)
+{
+    const int b = blockIdx.x;
+    const uint8_t m = cov[b];
+    if (!m) return;
+    for (int cell = threadIdx.x; cell < NC; cell += blockDim.x) {
+        const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
+        if ((m >> ((x >> 2) + 2 * (y >> 2) + 4 * (z >> 2))) & 1)
+            for (int c = 0; c < ncomp; ++c) out[c * cs + (long long)b * NC + cell] = T(0);
+    }
+}
+
+// per-problem reduction of per-block partials (sums for k < ksum, max after),
+// fixed order: one thread per (problem, quantity) walks the problem's block
+// ranges (one range per AMR level) in order
+__global__ void k_reduce_blocks(int nprob, int nrange, const long long *__restrict__ range,
+                                const double *__restrict__ part, int k, int ksum, double *__restrict__ out)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nprob * k) return;
+    const int p = t / k, q = t % k;
+    double v = 0.0;
+    for (int r = 0; r < nrange; ++r) {
+        const long long b0 = range[2 * ((long long)p * nrange + r)], b1 = range[2 * ((long long)p * nrange + r) + 1];
+        for (long long b = b0; b < b1; ++b) {
+            double x = part[b * k + q];
+            v = (q < ksum) ? v + x : fmax(v, x);
+        }
+    }
+    out[t] = v;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+ohm_status launch_blk_stencil(const ohm_hier *h, int level, int mode, const T *B, const T *Bg, long long cs,
+                              long long gcs, const T *S, const T *eta, const T *etag, const double *coef_dev,
+                              T *out, int colour, double *partials, const uint8_t *cov_zero, const int *active,
+                              hipStream_t s)
+{
+    const AmrLevelDev &L = h->amr[level];
+    if (L.nb == 0) return OHM_OK;
+    dim3 grid(L.nb), blk(256);
+    switch (mode) {
+    case MODE_APPLY:
+        k_blk_stencil<T, MODE_APPLY><<<grid, blk, 0, s>>>(L.nb, L.nbr, L.prob, cov_zero, active, L.inv_h2, coef_dev,
+                                                          B, Bg, cs, gcs, S, eta, etag, out, colour, partials);
+        break;
+    case MODE_RESID:
+        k_blk_stencil<T, MODE_RESID><<<grid, blk, 0, s>>>(L.nb, L.nbr, L.prob, cov_zero, active, L.inv_h2, coef_dev,
+                                                          B, Bg, cs, gcs, S, eta, etag, out, colour, partials);
+        break;
+    default:
+        k_blk_stencil<T, MODE_SMOOTH><<<grid, blk, 0, s>>>(L.nb, L.nbr, L.prob, cov_zero, active, L.inv_h2, coef_dev,
+                                                           B, Bg, cs, gcs, S, eta, etag, out, colour, partials);
+    }
+    return check_launch("block stencil");
+}
+
+template <typename T>
+ohm_status launch_restrict_blk(const ohm_hier *h, int fine_level, const T *fine, long long fcs, T *coarse,
+                               long long ccs, int ncomp, const int *active, hipStream_t s)
+{
+    if (fine_level >= 1) {
+        const AmrLevelDev &L = h->amr[fine_level];
+        if (L.nb == 0) return OHM_OK;
+        k_restrict_blk<T><<<L.nb, 64, 0, s>>>(L.nb, L.parent, L.octant, L.prob, active, fine, fcs, coarse, ccs,
+                                              ncomp);
+        return check_launch("restrict");
+    }
+    const AmrLevelDev &L = h->amr[0];
+    k_restrict_blk0_dense<T><<<L.nb, 64, 0, s>>>(L.nb, L.dense_map, L.prob, h->dense[1].probs, active, fine, fcs,
+                                                 coarse, ccs, ncomp);
+    return check_launch("restrict to dense");
+}
+
+template <typename T>
+ohm_status launch_prolong_blk(const ohm_hier *h, int coarse_level, const T *coarse, long long ccs, T *fine,
+                              long long fcs, int ncomp, int accumulate, const int *active, hipStream_t s)
+{
+    if (coarse_level >= 0) {
+        const AmrLevelDev &F = h->amr[coarse_level + 1];
+        if (F.nb == 0) return OHM_OK;
+        k_prolong_blk<T><<<F.nb, 256, 0, s>>>(F.nb, F.parent, F.octant, F.prob, active, h->amr[coarse_level].nbr,
+                                              coarse, ccs, fine, fcs, ncomp, accumulate);
+        return check_launch("prolong");
+    }
+    const AmrLevelDev &L = h->amr[0];
+    k_prolong_dense_blk0<T><<<L.nb, 256, 0, s>>>(L.nb, L.ijk, L.prob, h->dense[1].probs, active, coarse, ccs, fine,
+                                                 fcs, ncomp, accumulate);
+    return check_launch("prolong from dense");
+}
+
+template <typename T>
+ohm_status launch_fill_ghosts(const ohm_hier *h, int level, const T *coarse, long long ccs, T *ghost,
+                              long long gcs, int ncomp, const int *active, hipStream_t s)
+{
+    const AmrLevelDev &L = h->amr[level];
+    if (level < 1 || L.ng == 0) return OHM_OK;
+    k_prolong_blk<T><<<L.ng, 256, 0, s>>>(L.ng, L.gparent, L.goctant, L.gprob, active, h->amr[level - 1].nbr,
+                                          coarse, ccs, ghost, gcs, ncomp, 0);
+    return check_launch("fill ghosts");
+}
+
+template <typename T>
+ohm_status launch_reflux(const ohm_hier *h, int level, const T *Bc, long long ccs, const T *etac, const T *Bf,
+                         long long fcs, const T *Bfg, long long fgcs, const T *etaf, const T *etafg,
+                         const double *coef_dev, T *out, const int *active, hipStream_t s)
+{
+    const AmrLevelDev &L = h->amr[level];
+    if (L.nrf == 0) return OHM_OK;
+    k_reflux<T><<<(L.nrf + 127) / 128, 128, 0, s>>>(L.nrf, L.rf, active, L.nbr, h->amr[level + 1].nbr, L.inv_h,
+                                                     coef_dev, Bc, ccs, etac, Bf, fcs, Bfg, fgcs, etaf, etafg, out);
+    return check_launch("reflux");
+}
+
+template <typename T>
+ohm_status launch_zero_covered(const ohm_hier *h, int level, T *out, long long cs, int ncomp, hipStream_t s)
+{
+    const AmrLevelDev &L = h->amr[level];
+    if (L.nb == 0) return OHM_OK;
+    k_zero_covered<T><<<L.nb, 256, 0, s>>>(L.nb, L.cov, out, cs, ncomp);
+    return check_launch("zero covered");
+}
+
+ohm_status launch_reduce_problem(int nprob, int nrange, const long long *range_dev, const double *part, int k,
+                                 int ksum, double *out, hipStream_t s)
+{
+    int n = nprob * k;
+    k_reduce_blocks<<<(n + 63) / 64, 64, 0, s>>>(nprob, nrange, range_dev, part, k, ksum, out);
+    return check_launch("reduce");
+}
+
+#define INST(T)                                                                                                 \
+    template ohm_status launch_blk_stencil<T>(const ohm_hier *, int, int, const T *, const T *, long long,      \
+                                              long long, const T *, const T *, const T *, const double *, T *,  \
+                                              int, double *, const uint8_t *, const int *, hipStream_t);        \
+    template ohm_status launch_restrict_blk<T>(const ohm_hier *, int, const T *, long long, T *, long long, int, \
+                                               const int *, hipStream_t);                                       \
+    template ohm_status launch_prolong_blk<T>(const ohm_hier *, int, const T *, long long, T *, long long, int,  \
+                                              int, const int *, hipStream_t);                                   \
+    template ohm_status launch_fill_ghosts<T>(const ohm_hier *, int, const T *, long long, T *, long long, int,  \
+                                              const int *, hipStream_t);                                        \
+    template ohm_status launch_reflux<T>(const ohm_hier *, int, const T *, long long, const T *, const T *,      \
+                                         long long, const T *, long long, const T *, const T *, const double *, \
+                                         T *, const int *, hipStream_t);                                        \
+    template ohm_status launch_zero_covered<T>(const ohm_hier *, int, T *, long long, int, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace ohm

@@ -1,0 +1,408 @@
+// Kernels on the dense multigrid levels below the base grid (one thread per
+// cell, 256-cell tiles that never straddle two problems) and the coarsest-grid
+// solve (per-problem dense FP64 inverse built on the device).
+#include "common.h"
+#include "stencil.h"
+
+namespace ohm {
+
+namespace {
+
+__device__ __forceinline__ int wrapd(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// gather the 3x3x3 neighbourhood (corners skipped) of cell (i,j,k)
+template <typename T, typename Get>
+__device__ __forceinline__ void gather(const DenseProbDev &q, int i, int j, int k, T *v, Get get)
+{
+#pragma unroll
+    for (int dz = -1; dz <= 1; ++dz)
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy)
+#pragma unroll
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int t = (dx + 1) + 3 * (dy + 1) + 9 * (dz + 1);
+                if (dx != 0 && dy != 0 && dz != 0) {
+                    v[t] = T(0);
+                    continue;
+                }
+                const long long idx =
+                    q.off + wrapd(i + dx, q.nx) + (long long)q.nx * (wrapd(j + dy, q.ny) + (long long)q.ny * wrapd(k + dz, q.nz));
+                v[t] = get(idx);
+            }
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(256)
+k_dense_stencil(const int *__restrict__ tiles, const DenseProbDev *__restrict__ dp, const int *__restrict__ active,
+                const double *__restrict__ coef_p, const T *__restrict__ B, const T *__restrict__ S,
+                const T *__restrict__ eta, T *__restrict__ out, long long cs, int colour)
+{
+    const int pr = tiles[2 * blockIdx.x], start = tiles[2 * blockIdx.x + 1];
+    if (active && !active[pr]) return;
+    const DenseProbDev q = dp[pr];
+    const int n = q.nx * q.ny * q.nz;
+    const int cell = start + threadIdx.x;
+    if (cell >= n) return;
+    const int i = cell % q.nx, j = (cell / q.nx) % q.ny, k = cell / (q.nx * q.ny);
+    T b0[27], b1[27], b2[27], e[27];
+    gather<T>(q, i, j, k, b0, [&](long long x) { return B[x]; });
+    gather<T>(q, i, j, k, b1, [&](long long x) { return B[cs + x]; });
+    gather<T>(q, i, j, k, b2, [&](long long x) { return B[2 * cs + x]; });
+    gather<T>(q, i, j, k, e, [&](long long x) { return eta[x]; });
+    const T ih2 = T(q.inv_h2), coef = T(coef_p[pr]);
+    const long long gi = q.off + cell;
+    const T *bc[3] = {b0, b1, b2};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        T LB = bc[c][13] + coef * ih2 * divF_cube<T, 3>(b0, b1, b2, e, 13, c);
+        if (MODE == MODE_APPLY) {
+            out[c * cs + gi] = LB;
+        } else if (MODE == MODE_RESID) {
+            out[c * cs + gi] = S[c * cs + gi] - LB;
+        } else {
+            T v = bc[c][13];
+            if (((i + j + k) & 1) == colour)
+                v += (S[c * cs + gi] - LB) / (T(1) + coef * ih2 * alpha_cube<T, 3>(e, 13, c));
+            out[c * cs + gi] = v;
+        }
+    }
+}
+
+// dense level -d -> -(d+1): mean of 8 children; one thread per coarse cell
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_dense_restrict(const int *__restrict__ ctiles, const DenseProbDev *__restrict__ cdp,
+                 const DenseProbDev *__restrict__ fdp, const int *__restrict__ active, const T *__restrict__ fine,
+                 long long fcs, T *__restrict__ coarse, long long ccs, int ncomp)
+{
+    const int pr = ctiles[2 * blockIdx.x], start = ctiles[2 * blockIdx.x + 1];
+    if (active && !active[pr]) return;
+    const DenseProbDev c = cdp[pr], f = fdp[pr];
+    const int cell = start + threadIdx.x;
+    if (cell >= c.nx * c.ny * c.nz) return;
+    const int i = cell % c.nx, j = (cell / c.nx) % c.ny, k = cell / (c.nx * c.ny);
+    for (int m = 0; m < ncomp; ++m) {
+        T s = T(0);
+        for (int dz = 0; dz < 2; ++dz)
+            for (int dy = 0; dy < 2; ++dy)
+                for (int dx = 0; dx < 2; ++dx)
+                    s += fine[m * fcs + f.off + (2 * i + dx) + (long long)f.nx * ((2 * j + dy) + (long long)f.ny * (2 * k + dz))];
+        coarse[m * ccs + c.off + cell] = s * T(0.125);
+    }
+}
+
+// dense -(d+1) -> -d trilinear prolongation; one thread per fine cell
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_dense_prolong(const int *__restrict__ ftiles, const DenseProbDev *__restrict__ fdp,
+                const DenseProbDev *__restrict__ cdp, const int *__restrict__ active, const T *__restrict__ coarse,
+                long long ccs, T *__restrict__ fine, long long fcs, int ncomp, int accumulate)
+{
+    const int pr = ftiles[2 * blockIdx.x], start = ftiles[2 * blockIdx.x + 1];
+    if (active && !active[pr]) return;
+    const DenseProbDev f = fdp[pr], c = cdp[pr];
+    const int cell = start + threadIdx.x;
+    if (cell >= f.nx * f.ny * f.nz) return;
+    const int X = cell % f.nx, Y = (cell / f.nx) % f.ny, Z = cell / (f.nx * f.ny);
+    const int i = X >> 1, j = Y >> 1, k = Z >> 1;
+    const int i1 = wrapd(i + ((X & 1) ? 1 : -1), c.nx), j1 = wrapd(j + ((Y & 1) ? 1 : -1), c.ny),
+              k1 = wrapd(k + ((Z & 1) ? 1 : -1), c.nz);
+    auto at = [&](int a, int b, int d) { return c.off + a + (long long)c.nx * (b + (long long)c.ny * d); };
+    for (int m = 0; m < ncomp; ++m) {
+        const T *C = coarse + m * ccs;
+        T v = T(27) * C[at(i, j, k)] + T(9) * (C[at(i1, j, k)] + C[at(i, j1, k)] + C[at(i, j, k1)]) +
+              T(3) * (C[at(i1, j1, k)] + C[at(i1, j, k1)] + C[at(i, j1, k1)]) + C[at(i1, j1, k1)];
+        v *= T(1.0 / 64.0);
+        const long long gi = m * fcs + f.off + cell;
+        fine[gi] = accumulate ? fine[gi] + v : v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// coarsest grid: assemble L (FP64) column by column, invert by Gauss-Jordan
+// with partial pivoting (one workgroup per problem), apply as a mat-vec
+// ---------------------------------------------------------------------------
+constexpr int COARSE_MAX_DEV = 768;
+
+struct CoarseJob {
+    int prob;
+    int n3;              // unknowns = 3 * cells
+    long long inv_off;   // element offset of the inverse
+    long long aug_off;   // element offset of the [n3][2 n3] augmented matrix (scratch)
+    DenseProbDev q;
+    double lam_dt;
+};
+
+__global__ void __launch_bounds__(256)
+k_coarse_assemble(const CoarseJob *__restrict__ jobs, const double *__restrict__ eta, double *__restrict__ aug)
+{
+    const CoarseJob J = jobs[blockIdx.y];
+    const int col = blockIdx.x;
+    if (col >= J.n3) return;
+    const int cells = J.n3 / 3;
+    const int cj = col / cells, qj = col % cells;
+    double *A = aug + J.aug_off;
+    for (int row = threadIdx.x; row < J.n3; row += blockDim.x) {
+        const int cr = row / cells, qr = row % cells;
+        const int i = qr % J.q.nx, j = (qr / J.q.nx) % J.q.ny, k = qr / (J.q.nx * J.q.ny);
+        double b[3][27], e[27];
+        for (int m = 0; m < 3; ++m)
+            gather<double>(J.q, i, j, k, b[m], [&](long long x) { return (m == cj && x == J.q.off + qj) ? 1.0 : 0.0; });
+        gather<double>(J.q, i, j, k, e, [&](long long x) { return eta[x]; });
+        double v = b[cr][13] + J.lam_dt * J.q.inv_h2 * divF_cube<double, 3>(b[0], b[1], b[2], e, 13, cr);
+        A[(long long)row * 2 * J.n3 + col] = v;
+        A[(long long)row * 2 * J.n3 + J.n3 + col] = (row == col) ? 1.0 : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(256)
+k_coarse_invert(const CoarseJob *__restrict__ jobs, double *__restrict__ aug, double *__restrict__ inv)
+{
+    const CoarseJob J = jobs[blockIdx.x];
+    const int n = J.n3, w = 2 * n;
+    double *A = aug + J.aug_off;
+    __shared__ double sval[256];
+    __shared__ int sidx[256];
+    __shared__ int piv;
+    __shared__ double sfac[COARSE_MAX_DEV];
+    for (int k = 0; k < n; ++k) {
+        // pivot search in column k, rows k..n-1 (fixed reduction order)
+        double best = -1.0;
+        int bi = k;
+        for (int r = k + threadIdx.x; r < n; r += blockDim.x) {
+            double a = fabs(A[(long long)r * w + k]);
+            if (a > best) { best = a; bi = r; }
+        }
+        sval[threadIdx.x] = best;
+        sidx[threadIdx.x] = bi;
+        __syncthreads();
+        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+            if (threadIdx.x < s) {
+                double o = sval[threadIdx.x + s];
+                int oi = sidx[threadIdx.x + s];
+                if (o > sval[threadIdx.x] || (o == sval[threadIdx.x] && oi < sidx[threadIdx.x])) {
+                    sval[threadIdx.x] = o;
+                    sidx[threadIdx.x] = oi;
+                }
+            }
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) piv = sidx[0];
+        __syncthreads();
+        const int p = piv;
+        if (p != k)
+            for (int c = threadIdx.x; c < w; c += blockDim.x) {
+                double t = A[(long long)k * w + c];
+                A[(long long)k * w + c] = A[(long long)p * w + c];
+                A[(long long)p * w + c] = t;
+            }
+        __syncthreads();
+        const double d = 1.0 / A[(long long)k * w + k];
+        __syncthreads();
+        for (int c = threadIdx.x; c < w; c += blockDim.x) A[(long long)k * w + c] *= d;
+        // eliminate column k from every other row at once
+        for (int r = threadIdx.x; r < n; r += blockDim.x) sfac[r] = (r == k) ? 0.0 : A[(long long)r * w + k];
+        __syncthreads();
+        for (long long t = threadIdx.x; t < (long long)n * w; t += blockDim.x) {
+            const int r = (int)(t / w), c = (int)(t % w);
+            const double f = sfac[r];
+            if (f != 0.0) A[t] -= f * A[(long long)k * w + c];
+        }
+        __syncthreads();
+    }
+    double *X = inv + J.inv_off;
+    for (long long t = threadIdx.x; t < (long long)n * n; t += blockDim.x) {
+        const long long r = t / n, c = t % n;
+        X[t] = A[r * w + n + c];
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_coarse_apply(const CoarseJob *__restrict__ jobs, const int *__restrict__ active, const double *__restrict__ inv,
+               const T *__restrict__ r, T *__restrict__ e, long long cs)
+{
+    const CoarseJob J = jobs[blockIdx.x];
+    if (active && !active[J.prob]) return;
+    const int n = J.n3, cells = n / 3;
+    const double *X = inv + J.inv_off;
+    __shared__ double sr[768];
+    for (int t = threadIdx.x; t < n; t += blockDim.x) sr[t] = (double)r[(t / cells) * cs + J.q.off + t % cells];
+    __syncthreads();
+    for (int row = threadIdx.x; row < n; row += blockDim.x) {
+        double s = 0.0;
+        const double *xr = X + (long long)row * n;
+        for (int c = 0; c < n; ++c) s += xr[c] * sr[c];
+        e[(row / cells) * cs + J.q.off + row % cells] = (T)s;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T>
+ohm_status launch_dense_stencil(const ohm_hier *h, int level, int mode, const T *B, const T *S, const T *eta,
+                                const double *coef_dev, T *out, int colour, bool coarsest_too, const int *active,
+                                hipStream_t s)
+{
+    const DenseLevelDev &D = h->dense[-level];
+    const int nt = coarsest_too ? D.ntile_all : D.ntile;
+    const int *tl = coarsest_too ? D.tiles_all : D.tiles;
+    if (nt == 0) return OHM_OK;
+    const long long cs = D.ncells;
+    switch (mode) {
+    case MODE_APPLY:
+        k_dense_stencil<T, MODE_APPLY><<<nt, 256, 0, s>>>(tl, D.probs, active, coef_dev, B, S, eta, out, cs, colour);
+        break;
+    case MODE_RESID:
+        k_dense_stencil<T, MODE_RESID><<<nt, 256, 0, s>>>(tl, D.probs, active, coef_dev, B, S, eta, out, cs, colour);
+        break;
+    default:
+        k_dense_stencil<T, MODE_SMOOTH><<<nt, 256, 0, s>>>(tl, D.probs, active, coef_dev, B, S, eta, out, cs, colour);
+    }
+    return check_launch("dense stencil");
+}
+
+template <typename T>
+ohm_status launch_dense_restrict(const ohm_hier *h, int fine_level, const T *fine, T *coarse, int ncomp,
+                                 const int *active, hipStream_t s)
+{
+    const DenseLevelDev &F = h->dense[-fine_level], &C = h->dense[-fine_level + 1];
+    if (C.ntile_all == 0) return OHM_OK;
+    k_dense_restrict<T><<<C.ntile_all, 256, 0, s>>>(C.tiles_all, C.probs, F.probs, active, fine, F.ncells, coarse,
+                                                    C.ncells, ncomp);
+    return check_launch("dense restrict");
+}
+
+template <typename T>
+ohm_status launch_dense_prolong(const ohm_hier *h, int coarse_level, const T *coarse, T *fine, int ncomp,
+                                int accumulate, const int *active, hipStream_t s)
+{
+    const DenseLevelDev &F = h->dense[-coarse_level - 1], &C = h->dense[-coarse_level];
+    if (F.ntile == 0) return OHM_OK;
+    k_dense_prolong<T><<<F.ntile, 256, 0, s>>>(F.tiles, F.probs, C.probs, active, coarse, C.ncells, fine, F.ncells,
+                                               ncomp, accumulate);
+    return check_launch("dense prolong");
+}
+
+// Coarsest-grid inverses for every problem whose coarsest grid has at most
+// OHM_COARSE_MAX unknowns.  eta_dense[d] points at FP64 resistivity of dense
+// level -d.  Scratch `aug` must hold sum 2 n3^2 doubles.
+ohm_status build_coarse_inverses(ohm_hier *h, const double *const *eta_dense, const double *lam_dt_host,
+                                 double *inv, double *aug, void *jobs_dev, hipStream_t s);
+ohm_status coarse_sizes(const ohm_hier *h, size_t *inv_elems, size_t *aug_elems);
+
+constexpr int COARSE_MAX = 768;
+
+ohm_status coarse_sizes(const ohm_hier *h, size_t *inv_elems, size_t *aug_elems)
+{
+    size_t a = 0, b = 0;
+    for (const auto &P : h->probs) {
+        const int *d = P.dims[-P.min_level];
+        long long n3 = 3LL * d[0] * d[1] * d[2];
+        if (n3 <= COARSE_MAX) {
+            a += (size_t)(n3 * n3);
+            b += (size_t)(2 * n3 * n3);
+        }
+    }
+    *inv_elems = a;
+    *aug_elems = b;
+    return OHM_OK;
+}
+
+// Host-side job list, one per problem with a dense coarsest solve.
+static std::vector<CoarseJob> coarse_jobs(const ohm_hier *h, const double *lam_dt_host, int depth_filter)
+{
+    std::vector<CoarseJob> jobs;
+    long long io = 0, ao = 0;
+    for (int p = 0; p < h->nprob; ++p) {
+        const auto &P = h->probs[p];
+        const int dd = -P.min_level;
+        const int *d = P.dims[dd];
+        const int n3 = 3 * d[0] * d[1] * d[2];
+        if (n3 > COARSE_MAX) continue;
+        CoarseJob J;
+        J.prob = p;
+        J.n3 = n3;
+        J.inv_off = io;
+        J.aug_off = ao;
+        io += (long long)n3 * n3;
+        ao += 2LL * n3 * n3;
+        J.q.nx = d[0];
+        J.q.ny = d[1];
+        J.q.nz = d[2];
+        J.q.active = 0;
+        J.q.off = P.doff[dd];
+        const double hh = P.dx0 * (double)(1 << dd);
+        J.q.inv_h2 = 1.0 / (hh * hh);
+        J.lam_dt = lam_dt_host ? lam_dt_host[p] : 0.0;
+        if (depth_filter == 0 || depth_filter == dd) jobs.push_back(J);
+    }
+    return jobs;
+}
+
+size_t coarse_job_count(const ohm_hier *h, int depth)
+{
+    return coarse_jobs(h, nullptr, depth).size();
+}
+
+ohm_status build_coarse_inverses(ohm_hier *h, const double *const *eta_dense, const double *lam_dt_host,
+                                 double *inv, double *aug, void *jobs_dev, hipStream_t s)
+{
+    // one launch per depth (each problem's coarsest grid lives at its own depth)
+    for (int dd = 1; dd <= -h->min_level; ++dd) {
+        std::vector<CoarseJob> jobs = coarse_jobs(h, lam_dt_host, dd);
+        if (jobs.empty()) continue;
+        CoarseJob *jd = (CoarseJob *)jobs_dev;
+        OHM_HIP(hipMemcpyAsync(jd, jobs.data(), sizeof(CoarseJob) * jobs.size(), hipMemcpyHostToDevice, s));
+        int maxn = 0;
+        for (auto &J : jobs) maxn = std::max(maxn, J.n3);
+        dim3 g(maxn, (unsigned)jobs.size());
+        k_coarse_assemble<<<g, 256, 0, s>>>(jd, eta_dense[dd], aug);
+        OHM_TRY(check_launch("coarse assemble"));
+        k_coarse_invert<<<(unsigned)jobs.size(), 256, 0, s>>>(jd, aug, inv);
+        OHM_TRY(check_launch("coarse invert"));
+        OHM_HIP(hipStreamSynchronize(s));   // the job table is reused per depth
+    }
+    return OHM_OK;
+}
+
+// x = inverse * r on the coarsest grid of every problem whose coarsest level is
+// -depth (jobs_dev filled by upload_coarse_jobs for that depth)
+template <typename T>
+ohm_status launch_coarse_apply(const ohm_hier *h, int depth, const void *jobs_dev, int njobs, const double *inv,
+                               const T *r, T *e, const int *active, hipStream_t s)
+{
+    if (njobs == 0) return OHM_OK;
+    k_coarse_apply<T><<<njobs, 256, 0, s>>>((const CoarseJob *)jobs_dev, active, inv, r, e,
+                                            h->dense[depth].ncells);
+    return check_launch("coarse apply");
+}
+
+ohm_status upload_coarse_jobs(const ohm_hier *h, int depth, void *jobs_dev, int *njobs, hipStream_t s)
+{
+    std::vector<CoarseJob> jobs = coarse_jobs(h, nullptr, depth);
+    *njobs = (int)jobs.size();
+    if (!jobs.empty())
+        OHM_HIP(hipMemcpyAsync(jobs_dev, jobs.data(), sizeof(CoarseJob) * jobs.size(), hipMemcpyHostToDevice, s));
+    return OHM_OK;
+}
+
+size_t coarse_job_bytes() { return sizeof(CoarseJob); }
+
+#define INST(T)                                                                                                \
+    template ohm_status launch_dense_stencil<T>(const ohm_hier *, int, int, const T *, const T *, const T *,   \
+                                                const double *, T *, int, bool, const int *, hipStream_t);     \
+    template ohm_status launch_dense_restrict<T>(const ohm_hier *, int, const T *, T *, int, const int *,      \
+                                                 hipStream_t);                                                 \
+    template ohm_status launch_dense_prolong<T>(const ohm_hier *, int, const T *, T *, int, int, const int *,  \
+                                                hipStream_t);                                                  \
+    template ohm_status launch_coarse_apply<T>(const ohm_hier *, int, const void *, int, const double *,       \
+                                               const T *, T *, const int *, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace ohm

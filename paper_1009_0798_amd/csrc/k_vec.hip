@@ -1,0 +1,334 @@
+// Vector kernels of the outer Krylov / refinement iteration on multi-level
+// block vectors [3][blocks of every AMR level][512]: fills, conversions,
+// per-block partial dot products (reduced per problem in fixed order) and the
+// BiCGStab updates with per-problem device scalars.
+#include "common.h"
+
+namespace ohm {
+
+namespace {
+
+__device__ __forceinline__ int xcd_block2(int w, int n)
+{
+    int q = n / NXCD, r = n % NXCD;
+    int x = w % NXCD, i = w / NXCD;
+    return x * q + min(x, r) + i;
+}
+
+template <typename T>
+__global__ void k_fill(T *__restrict__ a, long long n, T v)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        a[i] = v;
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S *__restrict__ a, D *__restrict__ b, long long n)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        b[i] = (D)a[i];
+}
+
+// strided copy of one level (per-component strides differ between the user's
+// per-level arrays and the multi-level vectors)
+template <typename S, typename D>
+__global__ void k_copy_level(const S *__restrict__ a, long long acs, D *__restrict__ b, long long bcs, long long n,
+                             int ncomp)
+{
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+        for (int c = 0; c < ncomp; ++c) b[c * bcs + i] = (D)a[c * acs + i];
+}
+
+// per-block partial dots: q-th product is sum over the block of x[q] . y[q]
+struct DotArgs {
+    const double *x[3];
+    const double *y[3];
+};
+
+__global__ void __launch_bounds__(256)
+k_dot(int nblk, const int *__restrict__ prob_of, const int *__restrict__ active, long long cs, DotArgs a, int nq,
+      double *__restrict__ part)
+{
+    __shared__ double sred[3][4];
+    const int b = xcd_block2(blockIdx.x, nblk);
+    if (active && !active[prob_of[b]]) {
+        if (threadIdx.x < nq) part[(long long)b * nq + threadIdx.x] = 0.0;
+        return;
+    }
+    double acc[3] = {0, 0, 0};
+    for (int t = threadIdx.x; t < 3 * NC; t += 256) {
+        const int c = t / NC, cell = t % NC;
+        const long long gi = c * cs + (long long)b * NC + cell;
+        for (int q = 0; q < nq; ++q) acc[q] += a.x[q][gi] * a.y[q][gi];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int q = 0; q < nq; ++q) {
+        double v = acc[q];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+        if (lane == 0) sred[q][wv] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < nq) {
+        const int q = threadIdx.x;
+        part[(long long)b * nq + q] = ((sred[q][0] + sred[q][1]) + sred[q][2]) + sred[q][3];
+    }
+}
+
+// per-block sum of squares and max |x| per component -> part[b][6]
+__global__ void __launch_bounds__(256)
+k_norms(int nblk, const int *__restrict__ prob_of, const int *__restrict__ active, long long cs,
+        const double *__restrict__ x, double *__restrict__ part)
+{
+    __shared__ double sred[6][4];
+    const int b = xcd_block2(blockIdx.x, nblk);
+    double ss[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+    if (!(active && !active[prob_of[b]])) {
+        for (int t = threadIdx.x; t < 3 * NC; t += 256) {
+            const int c = t / NC;
+            const double v = x[c * cs + (long long)b * NC + t % NC];
+            ss[c] += v * v;
+            mx[c] = fmax(mx[c], fabs(v));
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int c = 0; c < 3; ++c) {
+        double a = ss[c], m = mx[c];
+        for (int o = 32; o > 0; o >>= 1) {
+            a += __shfl_down(a, o, 64);
+            m = fmax(m, __shfl_down(m, o, 64));
+        }
+        if (lane == 0) {
+            sred[c][wv] = a;
+            sred[3 + c][wv] = m;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+        const int k = threadIdx.x;
+        double v = sred[k][0];
+        for (int w = 1; w < 4; ++w) v = (k < 3) ? v + sred[k][w] : fmax(v, sred[k][w]);
+        part[6 * (long long)b + k] = v;
+    }
+}
+
+// Scalars per problem (double[SC_N]):
+enum { SC_RHO = 0, SC_ALPHA, SC_OMEGA, SC_BETA, SC_RHONEW, SC_RR, SC_SS, SC_N = 16 };
+
+// p = r + beta (p - omega v)
+__global__ void __launch_bounds__(256)
+k_bicg_p(int nblk, const int *__restrict__ prob_of, const int *__restrict__ active, long long cs,
+         const double *__restrict__ scal, const double *__restrict__ r, const double *__restrict__ v,
+         double *__restrict__ p)
+{
+    const int b = xcd_block2(blockIdx.x, nblk);
+    const int pr = prob_of[b];
+    if (active && !active[pr]) return;
+    const double beta = scal[SC_N * pr + SC_BETA], omega = scal[SC_N * pr + SC_OMEGA];
+    for (int t = threadIdx.x; t < 3 * NC; t += 256) {
+        const long long gi = (t / NC) * cs + (long long)b * NC + t % NC;
+        p[gi] = r[gi] + beta * (p[gi] - omega * v[gi]);
+    }
+}
+
+// s = r - alpha v
+__global__ void __launch_bounds__(256)
+k_bicg_s(int nblk, const int *__restrict__ prob_of, const int *__restrict__ active, long long cs,
+         const double *__restrict__ scal, const double *__restrict__ r, const double *__restrict__ v,
+         double *__restrict__ s)
+{
+    const int b = xcd_block2(blockIdx.x, nblk);
+    const int pr = prob_of[b];
+    if (active && !active[pr]) return;
+    const double alpha = scal[SC_N * pr + SC_ALPHA];
+    for (int t = threadIdx.x; t < 3 * NC; t += 256) {
+        const long long gi = (t / NC) * cs + (long long)b * NC + t % NC;
+        s[gi] = r[gi] - alpha * v[gi];
+    }
+}
+
+// x += alpha ph + omega sh;  r = s - omega t;  partial (r, r) and (rhat, r)
+__global__ void __launch_bounds__(256)
+k_bicg_xr(int nblk, const int *__restrict__ prob_of, const int *__restrict__ active, long long cs,
+          const double *__restrict__ scal, double *__restrict__ x, const double *__restrict__ ph,
+          const double *__restrict__ sh, const double *__restrict__ s, const double *__restrict__ t_,
+          double *__restrict__ r, const double *__restrict__ rhat, double *__restrict__ part)
+{
+    __shared__ double sred[2][4];
+    const int b = xcd_block2(blockIdx.x, nblk);
+    const int pr = prob_of[b];
+    if (active && !active[pr]) {
+        if (threadIdx.x < 2) part[2 * (long long)b + threadIdx.x] = 0.0;
+        return;
+    }
+    const double alpha = scal[SC_N * pr + SC_ALPHA], omega = scal[SC_N * pr + SC_OMEGA];
+    double rr = 0.0, rh = 0.0;
+    for (int t = threadIdx.x; t < 3 * NC; t += 256) {
+        const long long gi = (t / NC) * cs + (long long)b * NC + t % NC;
+        x[gi] += alpha * ph[gi] + omega * sh[gi];
+        const double rn = s[gi] - omega * t_[gi];
+        r[gi] = rn;
+        rr += rn * rn;
+        rh += rhat[gi] * rn;
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) {
+        rr += __shfl_down(rr, o, 64);
+        rh += __shfl_down(rh, o, 64);
+    }
+    if (lane == 0) {
+        sred[0][wv] = rr;
+        sred[1][wv] = rh;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2)
+        part[2 * (long long)b + threadIdx.x] =
+            ((sred[threadIdx.x][0] + sred[threadIdx.x][1]) + sred[threadIdx.x][2]) + sred[threadIdx.x][3];
+}
+
+// x += y (iterative refinement update)
+__global__ void __launch_bounds__(256)
+k_axpy1(int nblk, const int *__restrict__ prob_of, const int *__restrict__ active, long long cs,
+        double *__restrict__ x, const double *__restrict__ y)
+{
+    const int b = xcd_block2(blockIdx.x, nblk);
+    if (active && !active[prob_of[b]]) return;
+    for (int t = threadIdx.x; t < 3 * NC; t += 256) {
+        const long long gi = (t / NC) * cs + (long long)b * NC + t % NC;
+        x[gi] += y[gi];
+    }
+}
+
+// per-problem scalar updates (one thread per problem); `dots` holds the
+// reduced per-problem products of the preceding dot kernel
+__global__ void k_scal(int nprob, int stage, const int *__restrict__ active, const double *__restrict__ dots, int nq,
+                       double *__restrict__ scal)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob) return;
+    if (active && !active[p]) return;
+    double *S = scal + SC_N * p;
+    const double *d = dots + (long long)nq * p;
+    switch (stage) {
+    case 0:  // restart: rho = alpha = omega = 1, rho_new = (rhat, r) = (r, r)
+        S[SC_RHO] = 1.0;
+        S[SC_ALPHA] = 1.0;
+        S[SC_OMEGA] = 1.0;
+        S[SC_RHONEW] = d[0];
+        S[SC_RR] = d[0];
+        break;
+    case 1: {  // beta from rho_new; rho <- rho_new
+        const double rn = S[SC_RHONEW];
+        S[SC_BETA] = (rn / S[SC_RHO]) * (S[SC_ALPHA] / S[SC_OMEGA]);
+        S[SC_RHO] = rn;
+        break;
+    }
+    case 2:  // alpha = rho / (rhat, v)
+        S[SC_ALPHA] = (d[0] != 0.0) ? S[SC_RHO] / d[0] : 0.0;
+        break;
+    case 3:  // omega = (t, s) / (t, t)
+        S[SC_OMEGA] = (d[1] > 0.0) ? d[0] / d[1] : 0.0;
+        break;
+    case 4:  // after x/r update: d = {(r, r), (rhat, r)}
+        S[SC_RR] = d[0];
+        S[SC_RHONEW] = d[1];
+        break;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+static inline int grid_for(long long n) { return (int)std::min<long long>((n + 255) / 256, 8192); }
+
+template <typename T>
+ohm_status vfill(T *a, long long n, T v, hipStream_t s)
+{
+    if (n <= 0) return OHM_OK;
+    k_fill<T><<<grid_for(n), 256, 0, s>>>(a, n, v);
+    return check_launch("fill");
+}
+
+template <typename S, typename D>
+ohm_status vconvert(const S *a, D *b, long long n, hipStream_t s)
+{
+    if (n <= 0) return OHM_OK;
+    k_convert<S, D><<<grid_for(n), 256, 0, s>>>(a, b, n);
+    return check_launch("convert");
+}
+
+template <typename S, typename D>
+ohm_status vcopy_level(const S *a, long long acs, D *b, long long bcs, long long n, int ncomp, hipStream_t s)
+{
+    if (n <= 0) return OHM_OK;
+    k_copy_level<S, D><<<grid_for(n), 256, 0, s>>>(a, acs, b, bcs, n, ncomp);
+    return check_launch("copy level");
+}
+
+ohm_status vdot(int nblk, const int *prob_of, const int *active, long long cs, const double *const *x,
+                const double *const *y, int nq, double *part, hipStream_t s)
+{
+    DotArgs a;
+    for (int q = 0; q < 3; ++q) {
+        a.x[q] = q < nq ? x[q] : nullptr;
+        a.y[q] = q < nq ? y[q] : nullptr;
+    }
+    k_dot<<<nblk, 256, 0, s>>>(nblk, prob_of, active, cs, a, nq, part);
+    return check_launch("dot");
+}
+
+ohm_status vbicg_p(int nblk, const int *prob_of, const int *active, long long cs, const double *scal, const double *r,
+                   const double *v, double *p, hipStream_t s)
+{
+    k_bicg_p<<<nblk, 256, 0, s>>>(nblk, prob_of, active, cs, scal, r, v, p);
+    return check_launch("bicg p");
+}
+
+ohm_status vbicg_s(int nblk, const int *prob_of, const int *active, long long cs, const double *scal, const double *r,
+                   const double *v, double *sv, hipStream_t s)
+{
+    k_bicg_s<<<nblk, 256, 0, s>>>(nblk, prob_of, active, cs, scal, r, v, sv);
+    return check_launch("bicg s");
+}
+
+ohm_status vbicg_xr(int nblk, const int *prob_of, const int *active, long long cs, const double *scal, double *x,
+                    const double *ph, const double *sh, const double *sv, const double *t, double *r,
+                    const double *rhat, double *part, hipStream_t s)
+{
+    k_bicg_xr<<<nblk, 256, 0, s>>>(nblk, prob_of, active, cs, scal, x, ph, sh, sv, t, r, rhat, part);
+    return check_launch("bicg xr");
+}
+
+ohm_status vaxpy1(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,
+                  hipStream_t s)
+{
+    k_axpy1<<<nblk, 256, 0, s>>>(nblk, prob_of, active, cs, x, y);
+    return check_launch("axpy");
+}
+
+ohm_status vscal(int nprob, int stage, const int *active, const double *dots, int nq, double *scal, hipStream_t s)
+{
+    k_scal<<<(nprob + 63) / 64, 64, 0, s>>>(nprob, stage, active, dots, nq, scal);
+    return check_launch("scalars");
+}
+
+ohm_status vnorms(int nblk, const int *prob_of, const int *active, long long cs, const double *x, double *part,
+                  hipStream_t s)
+{
+    k_norms<<<nblk, 256, 0, s>>>(nblk, prob_of, active, cs, x, part);
+    return check_launch("norms");
+}
+
+int scal_stride() { return SC_N; }
+
+template ohm_status vfill<double>(double *, long long, double, hipStream_t);
+template ohm_status vfill<float>(float *, long long, float, hipStream_t);
+template ohm_status vfill<int>(int *, long long, int, hipStream_t);
+template ohm_status vconvert<double, float>(const double *, float *, long long, hipStream_t);
+template ohm_status vconvert<float, double>(const float *, double *, long long, hipStream_t);
+template ohm_status vconvert<double, double>(const double *, double *, long long, hipStream_t);
+template ohm_status vcopy_level<double, double>(const double *, long long, double *, long long, long long, int,
+                                                hipStream_t);
+template ohm_status vcopy_level<double, float>(const double *, long long, float *, long long, long long, int,
+                                               hipStream_t);
+
+}  // namespace ohm

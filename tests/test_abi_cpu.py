@@ -1,0 +1,98 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+call of include/ohm.h, and rejects bad hierarchies on the host before any
+device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import ohm_inputs as gen
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_calls():
+    src = open(os.path.join(ROOT, "include", "ohm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ohm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_seven_calls():
+    calls = _header_calls()
+    for name in ["ohm_apply", "ohm_residual", "ohm_smooth", "ohm_restrict", "ohm_prolong", "ohm_fill_ghosts",
+                 "ohm_cn_step"]:
+        assert name in calls
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1009_0798_amd import _lib
+    L = _lib.lib()
+    for name in _header_calls():
+        assert hasattr(L, name), name
+    assert sorted(_lib.EXPORTS) == sorted(_header_calls())
+
+
+def _create(problems):
+    from paper_1009_0798_amd import _lib
+    L = _lib.lib()
+    descs = (_lib.ProblemDesc * len(problems))()
+    keep = []
+    for d, (bb, dx0, levels) in zip(descs, problems):
+        d.nlevels = len(levels)
+        for a in range(3):
+            d.base_blocks[a] = bb[a]
+        d.dx0 = dx0
+        for l, blk in enumerate(levels):
+            arr = np.ascontiguousarray(np.asarray(blk, dtype=np.int32).reshape(-1, 3))
+            keep.append(arr)
+            d.nblocks[l] = len(arr)
+            d.block_ijk[l] = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    h = ctypes.c_void_p()
+    st = L.ohm_hier_create(descs, len(problems), None, ctypes.byref(h))
+    return st, L.ohm_last_error().decode()
+
+
+def test_rejects_incomplete_base_level():
+    lev0 = gen.full_level((2, 2, 2))[:-1]
+    st, msg = _create([((2, 2, 2), 0.1, [lev0])])
+    assert st == 2 and "level 0" in msg
+
+
+def test_rejects_duplicate_and_outside_blocks():
+    lev0 = gen.full_level((2, 2, 1))
+    dup = np.concatenate([lev0[:-1], lev0[:1]])
+    st, msg = _create([((2, 2, 1), 0.1, [dup])])
+    assert st == 2 and "duplicate" in msg
+    bad = lev0.copy()
+    bad[0] = (5, 0, 0)
+    st, msg = _create([((2, 2, 1), 0.1, [bad])])
+    assert st == 2 and "outside" in msg
+
+
+def test_rejects_improper_nesting():
+    """A level-2 block at the edge of level 1 has coarse-fine ghosts whose
+    interpolation would need level-1 cells that do not exist."""
+    lev0 = gen.full_level((4, 4, 4))
+    lev1 = gen.children_of(np.array([[1, 1, 1]], dtype=np.int32))   # 8 blocks over base block (1,1,1)
+    lev2 = gen.children_of(np.array([[2, 2, 2]], dtype=np.int32))   # at the corner of level 1
+    st, msg = _create([((4, 4, 4), 0.1, [lev0, lev1, lev2])])
+    assert st == 2 and "nested" in msg
+
+
+def test_rejects_bad_arguments():
+    st, msg = _create([((0, 1, 1), 0.1, [gen.full_level((1, 1, 1))])])
+    assert st == 1
+    st, msg = _create([((1, 1, 1), -1.0, [gen.full_level((1, 1, 1))])])
+    assert st == 1 and "dx0" in msg
+
+
+def test_null_handle_errors():
+    from paper_1009_0798_amd import _lib
+    L = _lib.lib()
+    assert L.ohm_hier_level_info(None, 0, None, None, None) == 1
+    assert "NULL" in L.ohm_last_error().decode()
+    o = _lib.CnOpts()
+    L.ohm_cn_default_opts(ctypes.byref(o))
+    assert o.lambda_ == 0.5 and o.rtol == 1e-10

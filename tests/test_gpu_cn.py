@@ -1,0 +1,169 @@
+"""Whole-step parity: one Crank-Nicolson step on the GPU against the oracle.
+
+Bound: the GPU stops when |S - L B|_2 <= rtol |S|_2 (rtol = 1e-10, FP64
+residual); with sigma_min(L) >= 1 the error is at most rtol |S|_2, and the
+oracle is solved to 1e-13.  Assertion: |B_gpu - B_oracle|_2 <= 1.5 rtol |S|_2
++ 1e-12 |B_oracle|_2.  Mixed precision meets the same bound because its final
+residual is FP64; its measured error is printed."""
+import numpy as np
+import pytest
+
+import ohm_inputs as gen
+from oracle import amr, closed, mg, ref
+
+from gpu_util import announce, blocks_to_dense, cuda, dense_to_blocks, hier, host
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+
+
+def _bound(S_norm, ex):
+    return 1.5 * RTOL * S_norm + 1e-12 * np.linalg.norm(ex)
+
+
+def _gpu_step(spec, B, eta, dt, **opts):
+    import paper_1009_0798_amd as ohm
+    H = hier(spec)
+    ijk = spec.levels[0]
+    Bt = [cuda(dense_to_blocks(B, ijk))]
+    Et = [cuda(dense_to_blocks(eta, ijk)[None])]
+    st, stats = ohm.ohm_cn_step(H, Bt, Et, dt, ohm.default_opts(rtol=RTOL, **opts))
+    return st, stats, blocks_to_dense(host(Bt[0]), ijk, spec.cells(0))
+
+
+def test_fourier32_against_closed_form():
+    announce("cn fourier32 f64")
+    cfg = gen.config_fourier32()
+    spec, h = cfg["spec"], cfg["spec"].dx0
+    st, stats, got = _gpu_step(spec, cfg["B"], cfg["eta"], cfg["dt"])
+    ex = closed.cn_exact(cfg["B"], 1.0, h, cfg["dt"])
+    S = ref.source(cfg["B"], cfg["eta"], h, cfg["dt"])
+    print(stats, np.linalg.norm(got - ex) / np.linalg.norm(ex))
+    assert st == 0 and stats[0]["rel_res"] <= RTOL
+    assert np.linalg.norm(got - ex) <= _bound(np.linalg.norm(S), ex)
+
+
+@pytest.mark.parametrize("precision,outer,cycle", [(0, 1, 0), (1, 1, 0), (0, 0, 0), (0, 1, 1), (1, 0, 1)])
+def test_lognormal32_against_oracle(precision, outer, cycle):
+    announce(f"cn lognormal32 precision={precision} outer={outer} cycle={cycle}")
+    n = 32
+    spec = gen.uniform_spec(n)
+    h = spec.dx0
+    eta = gen.lognormal_eta(n, 4.0, seed=21)
+    B = gen.divfree(n, 2.0, seed=22)
+    dt = gen.explicit_dt(h, 1.0, 100.0)
+    st, stats, got = _gpu_step(spec, B, eta, dt, precision=precision, outer=outer, cycle=cycle, max_iters=400)
+    ex, hist = mg.cn_step(B, eta, h, dt, rtol=1e-13)
+    S = ref.source(B, eta, h, dt)
+    err = np.linalg.norm(got - ex) / np.linalg.norm(ex)
+    print("stats", stats, "rel err vs oracle", err)
+    assert st == 0 and stats[0]["rel_res"] <= RTOL
+    assert np.linalg.norm(got - ex) <= _bound(np.linalg.norm(S), ex)
+    # the residual the library reports is the oracle's residual of its answer
+    R = ref.residual(got, S, eta, h, 0.5 * dt)
+    assert np.linalg.norm(R) <= 1.01 * RTOL * np.linalg.norm(S)
+
+
+def test_ragged_box_variable_eta():
+    """24 x 16 x 32 box: coarsenings 12x8x16, 6x4x8, 3x2x4 (odd coarsest)."""
+    announce("cn ragged box")
+    spec = gen.HierSpec((3, 2, 4), 0.05, [gen.full_level((3, 2, 4))])
+    nx, ny, nz = spec.cells(0)
+    rng = np.random.default_rng(31)
+    B = rng.standard_normal((3, nz, ny, nx))
+    eta = np.exp(rng.uniform(-3, 0, (nz, ny, nx)))
+    h = spec.dx0
+    dt = gen.explicit_dt(h, 1.0, 30.0)
+    st, stats, got = _gpu_step(spec, B, eta, dt, max_iters=300)
+    S = ref.source(B, eta, h, dt)
+    ex, _ = mg.cn_step(B, eta, h, dt, rtol=1e-13, maxit=400)
+    print(stats)
+    assert st == 0
+    assert np.linalg.norm(got - ex) <= _bound(np.linalg.norm(S), ex)
+
+
+def test_amr_two_levels_against_oracle():
+    announce("cn amr 2 levels")
+    spec = gen.config_amr2(n_base=32, extra_frac=0.2, seed=4)
+    C = amr.Composite(spec)
+    Bb, eb = gen.amr_fields(spec, p=2.0, seed=5)
+    Bs = C.average_down([C.to_dense(l, Bb[l]) for l in range(2)])
+    es = [C.to_dense(l, eb[l]) for l in range(2)]
+    dt = 20.0 * spec.dx(1) ** 2 / (6 * 10.0)
+    import paper_1009_0798_amd as ohm
+    H = hier(spec)
+    Bt = [cuda(dense_to_blocks(Bs[l], spec.levels[l])) for l in range(2)]
+    Et = [cuda(dense_to_blocks(es[l], spec.levels[l])[None]) for l in range(2)]
+    st, stats = ohm.ohm_cn_step(H, Bt, Et, dt, ohm.default_opts(rtol=RTOL, max_iters=300))
+    print(stats)
+    assert st == 0 and stats[0]["rel_res"] <= RTOL
+    ex, hist = C.cn_step(Bs, es, dt, rtol=1e-13)
+    Ss = C.source(Bs, es, dt)
+    nS = np.linalg.norm(C.pack(Ss))
+    got = [blocks_to_dense(host(Bt[l]), spec.levels[l], spec.cells(l)) for l in range(2)]
+    diff = np.concatenate([(got[l] - ex[l])[:, C.leaf[l]].ravel() for l in range(2)])
+    exv = C.pack(ex)
+    print("rel err", np.linalg.norm(diff) / np.linalg.norm(exv))
+    assert np.linalg.norm(diff) <= 1.5 * RTOL * nS + 1e-12 * np.linalg.norm(exv)
+
+
+def test_batched_equals_alone():
+    """Three problems of different sizes in one handle give the same answer as
+    each solved alone (per-problem reductions in a fixed order)."""
+    import paper_1009_0798_amd as ohm
+    announce("cn batched vs alone")
+    sizes = [16, 24, 32]
+    probs, Bs, Es, dts = [], [], [], []
+    for i, n in enumerate(sizes):
+        spec = gen.uniform_spec(n)
+        probs.append(spec)
+        Bs.append(gen.divfree(n, 2.0, seed=40 + i))
+        Es.append(gen.lognormal_eta(n, 2.0, seed=50 + i))
+        dts.append(gen.explicit_dt(spec.dx0, 1.0, [20.0, 60.0, 150.0][i]))
+    Hb = ohm.Hierarchy([(s.base_blocks, s.dx0, s.levels) for s in probs])
+    Bcat = np.concatenate([dense_to_blocks(B, s.levels[0]) for B, s in zip(Bs, probs)], axis=1)
+    Ecat = np.concatenate([dense_to_blocks(E, s.levels[0])[None] for E, s in zip(Es, probs)], axis=1)
+    Bt, Et = [cuda(Bcat)], [cuda(Ecat)]
+    st, stats = ohm.ohm_cn_step(Hb, Bt, Et, dts, ohm.default_opts(rtol=RTOL))
+    assert st == 0
+    out = host(Bt[0])
+    o = 0
+    for i, s in enumerate(probs):
+        nb = len(s.levels[0])
+        st1, stats1, alone = _gpu_step(s, Bs[i], Es[i], dts[i])
+        mine = blocks_to_dense(out[:, o:o + nb], s.levels[0], s.cells(0))
+        o += nb
+        assert stats1[0]["iters"] == stats[i]["iters"]
+        assert np.array_equal(mine, alone), i
+
+
+def test_noconv_reports_and_keeps_last_iterate():
+    import paper_1009_0798_amd as ohm
+    announce("cn noconv")
+    n = 16
+    spec = gen.uniform_spec(n)
+    B = gen.divfree(n, 2.0, seed=61)
+    eta = gen.lognormal_eta(n, 3.0, seed=62)
+    dt = gen.explicit_dt(spec.dx0, 1.0, 100.0)
+    st, stats, got = _gpu_step(spec, B, eta, dt, max_iters=1, rtol=1e-14)
+    assert st == ohm._lib.OHM_ERR_NOCONV
+    assert stats[0]["iters"] == 1 and stats[0]["rel_res"] > 1e-14
+    S = ref.source(B, eta, spec.dx0, dt)
+    R = ref.residual(got, S, eta, spec.dx0, 0.5 * dt)
+    assert abs(np.linalg.norm(R) / np.linalg.norm(S) - stats[0]["rel_res"]) <= 1e-6 * stats[0]["rel_res"] + 1e-15
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_full_size_lognormal128_residual(precision):
+    """128^3, eta over 4 decades, dt = 100x explicit: the GPU answer satisfies
+    the oracle's own L B = S to the tolerance (a property at any size)."""
+    announce(f"cn 128^3 precision={precision}")
+    cfg = gen.config_lognormal128()
+    spec, h = cfg["spec"], cfg["spec"].dx0
+    st, stats, got = _gpu_step(spec, cfg["B"], cfg["eta"], cfg["dt"], precision=precision)
+    print(stats)
+    assert st == 0
+    S = ref.source(cfg["B"], cfg["eta"], h, cfg["dt"])
+    R = ref.residual(got, S, cfg["eta"], h, 0.5 * cfg["dt"])
+    assert np.linalg.norm(R) <= 1.01 * RTOL * np.linalg.norm(S)
