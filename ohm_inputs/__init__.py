@@ -311,3 +311,113 @@ def refine_random(rng, parent_blocks: np.ndarray, parent_cells, frac: float,
                                 for d in range(3)))
     chosen = np.array(cand[:target], dtype=np.int32)
     return morton_order(children_of(chosen))
+
+
+def config_batched(nprob=256, seed=6, sizes=(16, 24, 32, 48, 64), decades=2.0, m_range=(10.0, 200.0)):
+    """Independent uniform problems of uneven size: edge drawn uniformly from
+    ``sizes``, log-normal eta over ``decades``, div-free k^-2 B, dt a
+    log-uniform multiple in ``m_range`` of each problem's explicit limit."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(nprob):
+        n = int(rng.choice(sizes))
+        m = float(np.exp(rng.uniform(np.log(m_range[0]), np.log(m_range[1]))))
+        s1, s2 = int(rng.integers(1 << 30)), int(rng.integers(1 << 30))
+        spec = uniform_spec(n)
+        eta = lognormal_eta(n, decades, seed=s1)
+        B = divfree(n, 2.0, seed=s2)
+        out.append(dict(spec=spec, B=B, eta=eta, dt=explicit_dt(spec.dx0, float(eta.max()), m), m=m))
+    return out
+
+
+def trilinear_up(coarse):
+    """Cell-centred trilinear interpolation of a periodic (ncomp, z, y, x)
+    array to twice the resolution (used only to sample smooth inputs on fine
+    AMR levels cheaply)."""
+    c = coarse[None] if coarse.ndim == 3 else coarse
+    out = np.zeros((c.shape[0],) + tuple(2 * s for s in c.shape[1:]))
+    for oz in (0, 1):
+        for oy in (0, 1):
+            for ox in (0, 1):
+                acc = 0.0
+                for cz in (0, 1):
+                    for cy in (0, 1):
+                        for cx in (0, 1):
+                            w = (0.25 if cz else 0.75) * (0.25 if cy else 0.75) * (0.25 if cx else 0.75)
+                            sh = (-(2 * oz - 1) * cz, -(2 * oy - 1) * cy, -(2 * ox - 1) * cx)
+                            acc = acc + w * np.roll(c, shift=sh, axis=(1, 2, 3))
+                out[:, oz::2, oy::2, ox::2] = acc
+    return out[0] if coarse.ndim == 3 else out
+
+
+class FourierField:
+    """A few random Fourier modes on the unit periodic box, evaluated at any
+    points: B = sum_j a_j |k_j|^-p sin(2 pi k_j.x + phi_j) with polarisation a_j
+    perpendicular to the integer wavevector k_j (continuously div-free), and a
+    scalar g of the same kind for the resistivity."""
+
+    def __init__(self, rng, nmodes=12, kmax=4, p=2.0):
+        ks = []
+        while len(ks) < nmodes:
+            k = rng.integers(-kmax, kmax + 1, size=3)
+            if np.any(k != 0):
+                ks.append(k)
+        self.k = np.array(ks, dtype=float)
+        kn = np.linalg.norm(self.k, axis=1)
+        a = rng.standard_normal((nmodes, 3))
+        a -= (a * self.k).sum(1, keepdims=True) * self.k / (kn ** 2)[:, None]
+        self.a = a * (kn ** -p)[:, None]
+        self.phi = rng.uniform(0, 2 * np.pi, nmodes)
+        self.g = rng.standard_normal(nmodes) * kn ** -p
+
+    def _phase(self, x, y, z):
+        shape = np.broadcast(x, y, z).shape
+        X = np.stack([np.broadcast_to(v, shape).ravel() for v in (x, y, z)], axis=1).astype(float)
+        return 2 * np.pi * (X @ self.k.T) + self.phi, shape
+
+    def vector(self, x, y, z):
+        ph, shape = self._phase(x, y, z)
+        return np.ascontiguousarray((np.sin(ph) @ self.a).T.reshape((3,) + shape))
+
+    def scalar(self, x, y, z):
+        ph, shape = self._phase(x, y, z)
+        return (np.cos(ph) @ self.g).reshape(shape)
+
+
+def amr_request(rng, n0, nlevels, decades, m, frac=0.125):
+    """One serving request on the unit periodic box: n0^3 base cells (n0 a
+    multiple of 8), ``nlevels`` levels, each finer level covering about
+    ``frac`` of its parent level as one compact patch with a one-block nesting
+    margin.  B and eta are smooth random Fourier fields sampled at every
+    level's cell centres (covered coarse B = mean of its children); eta spans
+    ``decades`` decades with max 1; dt = m x the explicit limit of the finest
+    level.  Returns dict(spec, B (list of [3, nb, 8,8,8]), eta (list of
+    [nb, 8,8,8]), dt)."""
+    bb = (n0 // BLOCK,) * 3
+    levels = [full_level(bb)]
+    for l in range(1, nlevels):
+        kids = refine_random(rng, levels[-1], tuple(BLOCK * b * (1 << (l - 1)) for b in bb), frac, margin=1)
+        if len(kids) == 0:
+            break
+        levels.append(kids)
+    spec = HierSpec(bb, 1.0 / n0, levels)
+    F = FourierField(rng)
+    Bs, gs = [], []
+    for l in range(spec.nlevels):
+        x, y, z = level_centres(spec, l, origin=0.0)
+        Bs.append(F.vector(x, y, z))
+        gs.append(F.scalar(x, y, z))
+    lo = min(float(g.min()) for g in gs)
+    hi = max(float(g.max()) for g in gs)
+    es = [10.0 ** (decades * ((g - lo) / max(hi - lo, 1e-300) - 1.0)) for g in gs]
+    # covered coarse cells hold the mean of their children
+    for l in range(spec.nlevels - 1, 0, -1):
+        par = {tuple(b): i for i, b in enumerate(spec.levels[l - 1])}
+        for i, (bi, bj, bk) in enumerate(spec.levels[l]):
+            pi_ = par[(bi >> 1, bj >> 1, bk >> 1)]
+            ox, oy, oz = 4 * (bi & 1), 4 * (bj & 1), 4 * (bk & 1)
+            f = Bs[l][:, i].reshape(3, 4, 2, 4, 2, 4, 2).mean(axis=(2, 4, 6))
+            Bs[l - 1][:, pi_, oz:oz + 4, oy:oy + 4, ox:ox + 4] = f
+    hf = spec.dx(spec.nlevels - 1)
+    dt = explicit_dt(hf, 1.0, m)
+    return dict(spec=spec, B=[np.ascontiguousarray(b) for b in Bs], eta=[np.ascontiguousarray(e) for e in es], dt=dt)

@@ -1,6 +1,7 @@
 // C ABI entry points of the building blocks: argument checks on the host, then
 // launches of the block-level or dense-level kernels.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "common.h"
@@ -182,6 +183,23 @@ ohm_status ohm_smooth(ohm_hier *h, int32_t level, void *B, const void *B_ghost, 
     double *cd;
     int slot;
     OHM_TRY(coef_slot(h, lam_dt, stream, &cd, &slot));
+    if (level >= 0 && h->amr[level].complete27) {
+        const long long cs = level_cs(h, level);
+        for (int k = 0; k < nsweeps; ++k) {
+            const void *src = (k & 1) ? tmp : B;
+            void *dst = (k & 1) ? B : tmp;
+            ohm_status st =
+                dtype == OHM_F64
+                    ? launch_blk_sweep<double>(h, level, (const double *)src, cs, (const double *)S,
+                                               (const double *)eta, cd, (double *)dst, nullptr, stream)
+                    : launch_blk_sweep<float>(h, level, (const float *)src, cs, (const float *)S, (const float *)eta,
+                                              cd, (float *)dst, nullptr, stream);
+            OHM_TRY(st);
+        }
+        if (nsweeps & 1) OHM_HIP(hipMemcpyAsync(B, tmp, (size_t)(3 * cs) * (dtype == OHM_F64 ? 8 : 4),
+                                                hipMemcpyDeviceToDevice, stream));
+        return coef_done(h, slot, stream);
+    }
     for (int k = 0; k < nsweeps; ++k) {
         for (int colour = 0; colour < 2; ++colour) {
             const void *src = colour == 0 ? B : tmp;

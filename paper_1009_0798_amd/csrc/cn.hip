@@ -122,7 +122,12 @@ struct Solver {
 
     template <typename U> U *at(size_t off) const { return (U *)(ws + off); }
     double *vec(size_t off, int l) const { return at<double>(off) + P.LB[l] * NC; }
-    T *mg(size_t off, int l) const { return at<T>(off) + P.LB[l] * NC; }
+    T *mg(size_t off, int l) const
+    {
+        T *base = (off == P.rhs && rhs_b) ? rhs_b : (off == P.e && e_b) ? e_b : at<T>(off);
+        return base + P.LB[l] * NC;
+    }
+    T *rhs_b = nullptr, *e_b = nullptr;   // multigrid right-hand side / correction of this cycle
     const double *eta64(int l) const { return (const double *)Euser[l]; }
     const T *etaT(int l) const
     {
@@ -170,6 +175,18 @@ struct Solver {
     // ---- multigrid cycle (precision T) ----------------------------------------
     ohm_status smooth_blk(int l, int n)
     {
+        if (h->amr[l].complete27 && n > 0) {
+            // fused sweeps, ping-pong e <-> tmp; an odd count ends with a copy
+            for (int k = 0; k < n; ++k) {
+                T *src = (k & 1) ? mg(P.tmp, l) : mg(P.e, l);
+                T *dst = (k & 1) ? mg(P.e, l) : mg(P.tmp, l);
+                OHM_TRY(launch_blk_sweep<T>(h, l, src, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st));
+            }
+            if (n & 1)
+                for (int c = 0; c < 3; ++c)
+                    OHM_TRY(vconvert<T, T>(mg(P.tmp, l) + c * VN, mg(P.e, l) + c * VN, (long long)h->nb_host[l] * NC, st));
+            return OHM_OK;
+        }
         for (int k = 0; k < n; ++k)
             for (int c = 0; c < 2; ++c) {
                 T *src = c == 0 ? mg(P.e, l) : mg(P.tmp, l);
@@ -275,8 +292,17 @@ struct Solver {
     ohm_status precond(size_t ro, size_t zo)
     {
         const long long n = 3 * P.NBt * NC;
-        OHM_TRY(vconvert<double, T>(at<double>(ro), at<T>(P.rhs), n, st));
         const int L = nlev();
+        // FP64 single-level problems run the cycle directly on the Krylov
+        // vectors (the cycle only reads r and only writes z); otherwise copy
+        const bool alias = !P.T32 && L == 1;
+        if (alias) {
+            rhs_b = (T *)at<double>(ro);
+            e_b = (T *)at<double>(zo);
+        } else {
+            rhs_b = e_b = nullptr;
+            OHM_TRY(vconvert<double, T>(at<double>(ro), at<T>(P.rhs), n, st));
+        }
         // AMR levels, finest first: smooth with zero coarse-fine ghosts,
         // restrict the level residual under the finer blocks
         if (L > 1 && P.NGt > 0) OHM_TRY(vfill<T>(at<T>(P.mg_g), 3 * P.NGt * NC, T(0), st));
@@ -297,7 +323,8 @@ struct Solver {
             OHM_TRY(launch_fill_ghosts<T>(h, l, mg(P.e, l - 1), VN, at<T>(P.mg_g) + P.LG[l] * NC, GN, 3, active, st));
             OHM_TRY(smooth_blk(l, o->nu_post));
         }
-        OHM_TRY(vconvert<T, double>(at<T>(P.e), at<double>(zo), n, st));
+        if (!alias) OHM_TRY(vconvert<T, double>(at<T>(P.e), at<double>(zo), n, st));
+        rhs_b = e_b = nullptr;
         return OHM_OK;
     }
 

@@ -47,6 +47,7 @@ constexpr int NBR_NONE = -(1 << 30);
 struct AmrLevelDev {
     int nb = 0;                // blocks
     int ng = 0;                // coarse-fine ghost blocks
+    bool complete27 = false;   // every block has all 26 neighbours as level blocks
     int *nbr = nullptr;        // [nb][27] neighbour entries, index (dx+1)+3(dy+1)+9(dz+1)
     int *prob = nullptr;       // [nb] problem of each block
     int *ijk = nullptr;        // [nb][3] block coordinates at this level
@@ -140,6 +141,10 @@ ohm_status launch_blk_stencil(const ohm_hier *h, int level, int mode, const T *B
                               const double *coef_dev, T *out, int colour, double *partials,
                               const uint8_t *cov_zero, const int *active, hipStream_t s);
 enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_SMOOTH = 2 };
+// one fused red-black sweep B -> out (levels whose blocks have every neighbour)
+template <typename T>
+ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long cs, const T *S, const T *eta,
+                            const double *coef_dev, T *out, const int *active, hipStream_t s);
 
 template <typename T>
 ohm_status launch_dense_stencil(const ohm_hier *h, int level, int mode, const T *B, const T *S,

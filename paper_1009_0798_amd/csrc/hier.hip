@@ -260,6 +260,7 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
         }
         L.ng = ng;
         H->ng_host[l] = ng;
+        L.complete27 = std::all_of(nbr.begin(), nbr.end(), [](int v) { return v >= 0; });
         std::vector<double> ih2(nprob, 0.0), ih(nprob, 0.0);
         for (int p = 0; p < nprob; ++p)
             if (l < H->probs[p].nlevels) {

@@ -128,6 +128,114 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
 }
 
 // ---------------------------------------------------------------------------
+// Fused red-black sweep: one launch per sweep.  The block and a two-cell halo
+// are staged in LDS; the red half-sweep is computed on the block and,
+// redundantly, on the red cells of the first halo layer that face the block
+// (their neighbours' values come from the second layer), then the black
+// half-sweep on the block reads those updated red values.  Same arithmetic as
+// two launches of k_blk_stencil<SMOOTH>; needs every face, edge and corner
+// neighbour to be a level block (levels without coarse-fine ghosts).
+// ---------------------------------------------------------------------------
+constexpr int TW2 = NB + 4;              // tile edge with a two-cell halo
+constexpr int TC2 = TW2 * TW2 * TW2;
+
+template <typename T>
+__device__ __forceinline__ int tix2(int x, int y, int z) { return (x + 2) + TW2 * ((y + 2) + TW2 * (z + 2)); }
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ prob_of,
+            const int *__restrict__ active, const double *__restrict__ inv_h2_p, const double *__restrict__ coef_p,
+            const T *__restrict__ B, long long cs, const T *__restrict__ S, const T *__restrict__ eta,
+            T *__restrict__ out)
+{
+    __shared__ T sB[3][TC2];
+    __shared__ T sE[TC2];
+    __shared__ int snbr[27];
+    const int b = xcd_block(blockIdx.x, nblk);
+    const int pr = prob_of[b];
+    if (active && !active[pr]) return;
+    if (threadIdx.x < 27) snbr[threadIdx.x] = nbr_tab[27 * (long long)b + threadIdx.x];
+    __syncthreads();
+    for (int t = threadIdx.x; t < TC2; t += blockDim.x) {
+        const int x = t % TW2 - 2, y = (t / TW2) % TW2 - 2, z = t / (TW2 * TW2) - 2;
+        const int sx = side(x), sy = side(y), sz = side(z);
+        const int n = snbr[(sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
+        const int li = (x - NB * sx) + NB * ((y - NB * sy) + NB * (z - NB * sz));
+        const long long gi = (long long)n * NC + li;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sB[c][t] = B[c * cs + gi];
+        sE[t] = eta[gi];
+    }
+    __syncthreads();
+    const T ih2 = T(inv_h2_p[pr]);
+    const T coef = T(coef_p[pr]);
+    const T cih2 = coef * ih2;
+    // red half-sweep: 256 block cells + 192 first-layer face cells
+    T red[2][3];
+    int rp[2];
+#pragma unroll
+    for (int round = 0; round < 2; ++round) {
+        const int u = threadIdx.x + 256 * round;
+        rp[round] = -1;
+        if (u >= 448) continue;
+        int x, y, z;
+        if (u < 256) {
+            z = u >> 5;
+            y = (u >> 2) & 7;
+            x = 2 * (u & 3) + ((y + z) & 1);
+        } else {
+            const int v = u - 256, f = v >> 5, w = v & 31;
+            const int d = f >> 1, s = (f & 1) ? NB : -1;
+            const int bb = w >> 2, a = 2 * (w & 3) + ((s + bb) & 1);
+            if (d == 0) { x = s; y = a; z = bb; }
+            else if (d == 1) { x = a; y = s; z = bb; }
+            else { x = a; y = bb; z = s; }
+        }
+        const int p = tix2<T>(x, y, z);
+        rp[round] = p;
+        const int sx = side(x), sy = side(y), sz = side(z);
+        const int n = snbr[(sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
+        const long long gi = (long long)n * NC + (x - NB * sx) + NB * ((y - NB * sy) + NB * (z - NB * sz));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T LB = sB[c][p] + cih2 * divF_cube<T, TW2>(sB[0], sB[1], sB[2], sE, p, c);
+            red[round][c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * alpha_cube<T, TW2>(sE, p, c));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int round = 0; round < 2; ++round)
+        if (rp[round] >= 0)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sB[c][rp[round]] = red[round][c];
+    __syncthreads();
+    // black half-sweep on the block cells
+    {
+        const int u = threadIdx.x;
+        const int z = u >> 5, y = (u >> 2) & 7, x = 2 * (u & 3) + (1 - ((y + z) & 1));
+        const int p = tix2<T>(x, y, z);
+        const long long gi = (long long)b * NC + x + NB * (y + NB * z);
+        T blk[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const T LB = sB[c][p] + cih2 * divF_cube<T, TW2>(sB[0], sB[1], sB[2], sE, p, c);
+            blk[c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * alpha_cube<T, TW2>(sE, p, c));
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sB[c][p] = blk[c];
+    }
+    __syncthreads();
+    for (int cell = threadIdx.x; cell < NC; cell += blockDim.x) {
+        const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
+        const int p = tix2<T>(x, y, z);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[c * cs + (long long)b * NC + cell] = sB[c][p];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // restriction: fine block -> the octant of its parent block (AMR levels), and
 // level-0 block -> the first dense level
 // ---------------------------------------------------------------------------
@@ -415,6 +523,17 @@ ohm_status launch_blk_stencil(const ohm_hier *h, int level, int mode, const T *B
 }
 
 template <typename T>
+ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long cs, const T *S, const T *eta,
+                            const double *coef_dev, T *out, const int *active, hipStream_t s)
+{
+    const AmrLevelDev &L = h->amr[level];
+    if (L.nb == 0) return OHM_OK;
+    if (!L.complete27) return fail(OHM_ERR_ARG, "fused sweep needs every neighbour block of level %d", level);
+    k_blk_sweep<T><<<L.nb, 256, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta, out);
+    return check_launch("fused sweep");
+}
+
+template <typename T>
 ohm_status launch_restrict_blk(const ohm_hier *h, int fine_level, const T *fine, long long fcs, T *coarse,
                                long long ccs, int ncomp, const int *active, hipStream_t s)
 {
@@ -489,6 +608,8 @@ ohm_status launch_reduce_problem(int nprob, int nrange, const long long *range_d
 }
 
 #define INST(T)                                                                                                 \
+    template ohm_status launch_blk_sweep<T>(const ohm_hier *, int, const T *, long long, const T *, const T *,   \
+                                            const double *, T *, const int *, hipStream_t);                      \
     template ohm_status launch_blk_stencil<T>(const ohm_hier *, int, int, const T *, const T *, long long,      \
                                               long long, const T *, const T *, const T *, const double *, T *,  \
                                               int, double *, const uint8_t *, const int *, hipStream_t);        \

@@ -326,6 +326,7 @@ template ohm_status vfill<int>(int *, long long, int, hipStream_t);
 template ohm_status vconvert<double, float>(const double *, float *, long long, hipStream_t);
 template ohm_status vconvert<float, double>(const float *, double *, long long, hipStream_t);
 template ohm_status vconvert<double, double>(const double *, double *, long long, hipStream_t);
+template ohm_status vconvert<float, float>(const float *, float *, long long, hipStream_t);
 template ohm_status vcopy_level<double, double>(const double *, long long, double *, long long, long long, int,
                                                 hipStream_t);
 template ohm_status vcopy_level<double, float>(const double *, long long, float *, long long, long long, int,

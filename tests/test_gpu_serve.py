@@ -1,0 +1,74 @@
+"""Serving: requests of mixed sizes and 1-2 AMR levels arriving over time are
+admitted by footprint, batched across two streams, and each served result
+equals the same request solved alone (bitwise: per-problem reductions in a
+fixed order), and meets the FP64 residual tolerance."""
+import numpy as np
+import pytest
+
+import ohm_inputs as gen
+
+from gpu_util import announce
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests(n, seed):
+    from paper_1009_0798_amd.serve import Request
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        n0 = int(rng.choice([16, 24, 32]))
+        L = int(rng.choice([1, 2]))
+        d = gen.amr_request(rng, n0, L, float(rng.uniform(0, 3)), float(np.exp(rng.uniform(np.log(10), np.log(60)))))
+        s = d["spec"]
+        out.append(Request(rid=i, arrival=0.0, base_blocks=s.base_blocks, dx0=s.dx0, levels=s.levels, B=d["B"],
+                           eta=d["eta"], dt=d["dt"]))
+    return out
+
+
+def _alone(r, precision):
+    import torch
+    import paper_1009_0798_amd as ohm
+    h = ohm.Hierarchy([(r.base_blocks, r.dx0, r.levels)])
+    B = [torch.from_numpy(b).cuda() for b in r.B]
+    E = [torch.from_numpy(e[None]).cuda() for e in r.eta]
+    st, stats = ohm.ohm_cn_step(h, B, E, r.dt, ohm.default_opts(rtol=1e-10, precision=precision, max_iters=300))
+    return st, stats, [b.cpu().numpy() for b in B]
+
+
+@pytest.mark.parametrize("precision", [1])
+def test_served_equals_alone(precision):
+    from paper_1009_0798_amd.serve import Server, latency_report, poisson_arrivals
+    announce("serve: served == alone")
+    reqs = _requests(10, seed=71)
+    srv = Server(hbm_budget=2 << 30, n_streams=2, max_batch=4, precision=precision)
+    done = srv.serve(reqs, poisson_arrivals(200.0, len(reqs), seed=7))
+    rep = latency_report(done)
+    print(rep)
+    assert rep["completed"] == len(reqs)
+    for r in done:
+        assert r.status == 0 and r.stats["rel_res"] <= 1e-10
+        st, stats, alone = _alone(r, precision)
+        assert st == 0
+        for l in range(len(r.levels)):
+            assert np.array_equal(alone[l], r.result[l]), (r.rid, l)
+
+
+def test_admission_by_footprint():
+    """A budget that fits one request at a time serialises them; a request
+    larger than the whole budget is rejected."""
+    from paper_1009_0798_amd.serve import Server, footprint
+    announce("serve: admission")
+    reqs = _requests(3, seed=72)
+    srv = Server(hbm_budget=1, n_streams=2)
+    fps = [footprint(r, srv.opts) for r in reqs]
+    srv = Server(hbm_budget=max(fps), n_streams=2)
+    done = srv.serve(reqs, [0.0, 0.0, 0.0])
+    assert all(r.status == 0 for r in done)
+    # never two requests resident together: admissions follow completions
+    ev = sorted([(r.admitted, r.done) for r in done])
+    for (a0, d0), (a1, d1) in zip(ev, ev[1:]):
+        assert a1 >= d0 - 1e-6
+    tiny = Server(hbm_budget=min(fps) - 1, n_streams=1)
+    done = tiny.serve(reqs[:1], [0.0])
+    assert done[0].status != 0
