@@ -42,8 +42,9 @@ def run_steps(ohm, H, B0, E, dt, K, precision, ws):
 
 
 def smoother_rate(ohm, H, B, S, E, lam_dt, dtype, nsweeps=10):
-    """Average duration of one red-black half-sweep launch on the level-0
-    blocks, measured with HIP events on the stream the library launches on."""
+    """Average duration of one smoother launch on the level-0 blocks (one
+    fused red-black sweep per launch on a complete periodic level), measured
+    with HIP events on the stream the library launches on."""
     import torch
     Bt = B.to(dtype).clone()
     St = S.to(dtype).contiguous()
@@ -56,7 +57,7 @@ def smoother_rate(ohm, H, B, S, E, lam_dt, dtype, nsweeps=10):
     ohm.ohm_smooth(H, 0, Bt, St, Et, lam_dt, nsweeps, tmp)
     ev1.record()
     torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / 1e3 / (2 * nsweeps)
+    return ev0.elapsed_time(ev1) / 1e3 / nsweeps
 
 
 def cpu_baseline(cfg, n_sample):
@@ -73,6 +74,72 @@ def cpu_baseline(cfg, n_sample):
                       f"FP64 V(2,2)-BiCGStab to 1e-10, {len(hist) - 1} iterations, {t:.2f} s"}
 
 
+def bench_batched(args):
+    """256 independent problems of uneven size in one handle (one launch per
+    kernel covers every problem); mixed precision; schedule from the tuner."""
+    import torch
+    import ohm_inputs as gen
+    import paper_1009_0798_amd as ohm
+    from paper_1009_0798_amd import tune
+    probs = gen.config_batched(nprob=args.nprob)
+    H = ohm.Hierarchy([(p["spec"].base_blocks, p["spec"].dx0, p["spec"].levels) for p in probs])
+    B0 = torch.cat([ohm.to_blocks(torch.from_numpy(p["B"]), p["spec"].levels[0]) for p in probs], dim=1).cuda()
+    E = torch.cat([ohm.to_blocks(torch.from_numpy(p["eta"])[None], p["spec"].levels[0]) for p in probs], dim=1).cuda()
+    dts = [p["dt"] for p in probs]
+    cells = sum(p["spec"].cells(0)[0] ** 3 for p in probs)
+    best, table = tune.tune(H, [B0], [E], dts, finest_dx=min(p["spec"].dx0 for p in probs), precisions=(1,),
+                            use_cache=False, log=_log)
+    ws = ohm.Workspace()
+    opts = ohm.default_opts(rtol=1e-10, max_iters=200, **best)
+    for _ in range(args.warmup):
+        ohm.ohm_cn_step(H, [B0.clone()], [E], dts, opts, ws)
+    Bs = [B0.clone() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        st, stats = ohm.ohm_cn_step(H, [Bs[k]], [E], dts, opts, ws)
+        assert st == 0, st
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    worst = max(s["rel_res"] for s in stats)
+    return {"metric": METRIC, "value": cells * args.steps / t, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": t / args.steps * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32 multigrid + f64 outer", "data": "synthetic",
+            "config": {"workload": f"batched{args.nprob}: {args.nprob} independent CN solves, edges from "
+                                   "{16,24,32,48,64}, eta log-normal 2 decades, dt 10-200x explicit",
+                       "cells": cells, "schedule": best, "worst_rel_res": worst}}
+
+
+def bench_serve(args):
+    """Poisson arrivals of 1-3 level AMR requests, continuous batching."""
+    import numpy as np
+    import ohm_inputs as gen
+    from paper_1009_0798_amd.serve import Request, Server, latency_report, poisson_arrivals
+    rng = np.random.default_rng(7)
+    pool = []
+    for i in range(args.pool):
+        n0 = int(rng.choice(np.arange(32, 193, 8)))
+        L = int(rng.choice([1, 2, 3]))
+        d = gen.amr_request(rng, n0, L, float(rng.uniform(0, 4)), float(np.exp(rng.uniform(np.log(10), np.log(100)))))
+        pool.append(d)
+        _log(f"request template {i}: base {n0}^3, levels {d['spec'].nlevels}, leaf cells {d['spec'].leaf_cells()}")
+    reqs = []
+    for i in range(args.requests):
+        d = pool[i % len(pool)]
+        s = d["spec"]
+        reqs.append(Request(rid=i, arrival=0.0, base_blocks=s.base_blocks, dx0=s.dx0, levels=s.levels, B=d["B"],
+                            eta=d["eta"], dt=d["dt"]))
+    srv = Server(hbm_budget=int(args.hbm_gb * (1 << 30)), n_streams=args.streams, max_batch=args.max_batch)
+    done = srv.serve(reqs, poisson_arrivals(args.rate, len(reqs), seed=7))
+    rep = latency_report(done)
+    return {"metric": METRIC, "value": rep["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": len(reqs),
+            "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32 multigrid + f64 outer", "data": "synthetic",
+            "config": {"workload": f"serve: Poisson {args.rate}/s, {len(reqs)} requests of 1-3 level AMR, base "
+                                   "32-192^3", "streams": args.streams, "max_batch": args.max_batch},
+            "latency": rep}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +148,14 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--cpu-sample", type=int, default=64, help="grid edge of the oracle sample (0: skip)")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--workload", default="lognormal128", choices=["lognormal128", "batched", "serve"])
+    ap.add_argument("--nprob", type=int, default=256)
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--pool", type=int, default=8)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--streams", type=int, default=2)
+    ap.add_argument("--max-batch", type=int, default=8)
+    ap.add_argument("--hbm-gb", type=float, default=64.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see the sharding design notes)",
@@ -90,6 +165,12 @@ def main():
     import ohm_inputs as gen
     import paper_1009_0798_amd as ohm
 
+    if args.workload == "batched":
+        print(json.dumps(bench_batched(args)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args)), flush=True)
+        return
     n = args.n
     cfg = gen.config_lognormal128(n)
     spec = cfg["spec"]
@@ -124,7 +205,7 @@ def main():
                                f"dt = 100x explicit limit, consecutive CN steps to rel. residual 1e-10",
                    "cells": cells, "outer": "BiCGStab", "cycle": "V(2,2)",
                    "iterations_per_step": f64["iters"]},
-        "roofline": {"kernel": "k_blk_stencil<double, smooth> (one red-black half-sweep, level 0)",
+        "roofline": {"kernel": "k_blk_sweep<double> (one fused red-black sweep, level 0)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "us_per_launch": t_sw * 1e6, "bytes_per_launch": bytes_sw},

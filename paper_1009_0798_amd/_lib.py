@@ -35,7 +35,7 @@ class CnOpts(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iters", ctypes.c_int32),
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("n_vcycles", ctypes.c_int32),
                 ("cycle", ctypes.c_int32), ("outer", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("coarse_sweeps", ctypes.c_int32)]
+                ("coarse_sweeps", ctypes.c_int32), ("graph", ctypes.c_int32)]
 
 
 class CnStats(ctypes.Structure):
@@ -56,6 +56,10 @@ def lib() -> ctypes.CDLL:
     """Load libohm.so; raise if it has not been built (there is no fallback)."""
     global _lib
     if _lib is None:
+        # torch carries its own HIP runtime with the same soname as the system
+        # one; load it first so that libohm.so binds to that single runtime
+        # (two runtimes in one process cannot share devices, memory or streams)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1009_0798_amd.build`")
         L = ctypes.CDLL(LIB_PATH)

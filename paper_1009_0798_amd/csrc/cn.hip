@@ -99,7 +99,8 @@ bool valid_opts(const ohm_cn_opts *o)
 {
     return o && o->lambda > 0.0 && o->lambda <= 1.0 && o->rtol > 0.0 && o->max_iters >= 1 && o->nu_pre >= 0 &&
            o->nu_post >= 0 && o->nu_pre + o->nu_post >= 1 && o->n_vcycles >= 1 && (o->cycle == 0 || o->cycle == 1) &&
-           (o->outer == 0 || o->outer == 1) && (o->precision == 0 || o->precision == 1) && o->coarse_sweeps >= 0;
+           (o->outer == 0 || o->outer == 1) && (o->precision == 0 || o->precision == 1) && o->coarse_sweeps >= 0 &&
+           (o->graph == 0 || o->graph == 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -221,7 +222,7 @@ struct Solver {
     {
         void *jobs = at<char>(P.jobs) + coarse_job_bytes() * (size_t)h->nprob * d;
         if (njobs[d] > 0)
-            OHM_TRY(launch_coarse_apply<T>(h, d, jobs, njobs[d], at<double>(P.inv), dv(P.d_rhs, d), dv(P.d_e, d),
+            OHM_TRY(launch_coarse_apply<T>(h, d, jobs, njobs[d], h->d_coarse_inv, dv(P.d_rhs, d), dv(P.d_e, d),
                                            active, st));
         if (has_big[d] && o->coarse_sweeps > 0)
             OHM_TRY(smooth_dense(d, o->coarse_sweeps, at<int>(P.cmask) + (size_t)h->nprob * d, true));
@@ -389,10 +390,8 @@ struct Solver {
                                                       1, nullptr, st));
             OHM_TRY(vconvert<double, T>(at<double>(P.d_eta64[d]), at<T>(P.d_eta[d]), h->dense_cells[d], st));
         }
-        // coarsest grids: dense inverses (rebuilt when lam_dt changes)
-        bool rebuild = false;
-        for (int p = 0; p < np; ++p)
-            if (h->cinv_lamdt[p] != coefs[p]) rebuild = true;
+        // coarsest grids: dense inverses (kept in the handle, rebuilt when
+        // lam_dt or the coarsest resistivity changes)
         njobs.assign(17, 0);
         has_big.assign(17, 0);
         std::vector<int> cmask((size_t)np * 17, 0);
@@ -412,16 +411,11 @@ struct Solver {
             OHM_TRY(upload_coarse_jobs(h, d, jobs, &nj, st));
             njobs[d] = nj;
         }
-        // the inverse depends on eta too: rebuild every step (cheap next to the
-        // solve for the small grids it is used on)
-        rebuild = true;
-        if (rebuild && P.inv_elems > 0) {
+        if (P.inv_elems > 0) {
             std::vector<const double *> ed(17, nullptr);
             for (int d = 1; d <= D; ++d) ed[d] = at<double>(P.d_eta64[d]);
             void *jobs_tmp = at<char>(P.jobs);   // depth-0 slot is free for the build
-            OHM_TRY(build_coarse_inverses(h, ed.data(), coefs.data(), at<double>(P.inv), at<double>(P.aug), jobs_tmp,
-                                          st));
-            for (int p = 0; p < np; ++p) h->cinv_lamdt[p] = coefs[p];
+            OHM_TRY(build_coarse_inverses(h, ed.data(), coefs.data(), nullptr, at<double>(P.aug), jobs_tmp, st));
         }
         // x = b (user B), S = b - (1 - lambda) dt div F(b) on leaf cells
         for (int l = 0; l < L; ++l)
@@ -464,6 +458,102 @@ struct Solver {
         return OHM_OK;
     }
 
+    // one BiCGStab iteration (device work only; the host reads the norms)
+    ohm_status bicg_iter()
+    {
+        const int np = h->nprob;
+            OHM_TRY(vscal(np, 1, active, at<double>(P.dots), 1, at<double>(P.scal), st));
+            OHM_TRY(vbicg_p((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.r),
+                            at<double>(P.v), at<double>(P.p), st));
+            OHM_TRY(precond(P.p, P.ph));
+            OHM_TRY(composite(P.ph, P.v, MODE_APPLY, lam_dt, lam_dt, 0));
+            {
+                const double *xs[1] = {at<double>(P.rhat)}, *ys[1] = {at<double>(P.v)};
+                OHM_TRY(dots(xs, ys, 1));
+                OHM_TRY(vscal(np, 2, active, at<double>(P.dots), 1, at<double>(P.scal), st));
+            }
+            OHM_TRY(vbicg_s((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.r),
+                            at<double>(P.v), at<double>(P.s), st));
+            OHM_TRY(precond(P.s, P.sh));
+            OHM_TRY(composite(P.sh, P.t, MODE_APPLY, lam_dt, lam_dt, 0));
+            {
+                const double *xs[2] = {at<double>(P.t), at<double>(P.t)},
+                             *ys[2] = {at<double>(P.s), at<double>(P.t)};
+                OHM_TRY(dots(xs, ys, 2));
+                OHM_TRY(vscal(np, 3, active, at<double>(P.dots), 2, at<double>(P.scal), st));
+            }
+            OHM_TRY(vbicg_xr((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.x),
+                             at<double>(P.ph), at<double>(P.sh), at<double>(P.s), at<double>(P.t),
+                             at<double>(P.r), at<double>(P.rhat), at<double>(P.part), st));
+            OHM_TRY(reduce(2, 2, at<double>(P.dots)));
+            OHM_TRY(vscal(np, 4, active, at<double>(P.dots), 2, at<double>(P.scal), st));
+        return OHM_OK;
+    }
+
+    // one iteration of eqs. (16)-(18): B += M(R); R = S - L B; |R|^2 per problem
+    ohm_status ir_iter()
+    {
+        OHM_TRY(precond(P.r, P.ph));
+        OHM_TRY(vaxpy1((int)P.NBt, mlprob, active, VN, at<double>(P.x), at<double>(P.ph), st));
+        OHM_TRY(composite(P.x, P.r, MODE_RESID, lam_dt, neg_lam_dt, P.S));
+        const double *xs[1] = {at<double>(P.r)};
+        return dots(xs, xs, 1);
+    }
+
+    ohm_status read_dots(int nq, std::vector<double> &out)
+    {
+        std::vector<double> d((size_t)h->nprob * nq);
+        OHM_HIP(hipMemcpyAsync(d.data(), at<double>(P.dots), sizeof(double) * d.size(), hipMemcpyDeviceToHost, st));
+        OHM_HIP(hipStreamSynchronize(st));
+        out.assign(h->nprob, 0.0);
+        for (int p = 0; p < h->nprob; ++p) out[p] = d[(size_t)p * nq];
+        return OHM_OK;
+    }
+
+    // run `body` directly, or as a HIP graph captured once and replayed while
+    // the workspace, the resistivity pointers and the options are unchanged
+    template <typename F>
+    ohm_status replay(int kind, F body)
+    {
+        if (!o->graph) return body();
+        std::vector<const void *> key = {ws};
+        for (int l = 0; l < nlev(); ++l) key.push_back(Euser[l]);
+        std::vector<char> ob((const char *)o, (const char *)o + sizeof(*o));
+        if (!h->graph_exec || h->graph_kind != kind || h->graph_key != key || h->graph_opts != ob) {
+            if (h->graph_exec) {
+                OHM_HIP(hipGraphExecDestroy(h->graph_exec));
+                h->graph_exec = nullptr;
+            }
+            // record on the handle's own stream (the caller's may be the null
+            // stream, which cannot be captured); replay on the caller's stream
+            std::lock_guard<std::mutex> lock(capture_mutex());
+            if (!h->cap_stream) OHM_HIP(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+            hipStream_t user = st;
+            st = h->cap_stream;
+            OHM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            ohm_status s = body();
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(st, &g);
+            st = user;
+            if (s != OHM_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return s;
+            }
+            if (e != hipSuccess) return fail(OHM_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e != hipSuccess) {
+                h->graph_exec = nullptr;
+                return fail(OHM_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+            }
+            h->graph_kind = kind;
+            h->graph_key = key;
+            h->graph_opts = ob;
+        }
+        OHM_HIP(hipGraphLaunch(h->graph_exec, st));
+        return OHM_OK;
+    }
+
     ohm_status run(ohm_cn_stats *stats)
     {
         const int np = h->nprob;
@@ -493,9 +583,8 @@ struct Solver {
         if (o->outer == 0) {
             // eqs. (16)-(18): R = S - L B; B <- B + M(R)
             for (int it = 0; it < maxit && any(); ++it) {
-                OHM_TRY(precond(P.r, P.ph));
-                OHM_TRY(vaxpy1((int)P.NBt, mlprob, active, VN, at<double>(P.x), at<double>(P.ph), st));
-                OHM_TRY(true_residual(r2));
+                OHM_TRY(replay(0, [&]() { return ir_iter(); }));
+                OHM_TRY(read_dots(1, r2));
                 for (int p = 0; p < np; ++p)
                     if (act[p]) {
                         ++iters[p];
@@ -522,31 +611,7 @@ struct Solver {
                 }
                 std::vector<int> inner(act);
                 while (it_total < maxit) {
-                    OHM_TRY(vscal(np, 1, active, at<double>(P.dots), 1, at<double>(P.scal), st));
-                    OHM_TRY(vbicg_p((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.r),
-                                    at<double>(P.v), at<double>(P.p), st));
-                    OHM_TRY(precond(P.p, P.ph));
-                    OHM_TRY(composite(P.ph, P.v, MODE_APPLY, lam_dt, lam_dt, 0));
-                    {
-                        const double *xs[1] = {at<double>(P.rhat)}, *ys[1] = {at<double>(P.v)};
-                        OHM_TRY(dots(xs, ys, 1));
-                        OHM_TRY(vscal(np, 2, active, at<double>(P.dots), 1, at<double>(P.scal), st));
-                    }
-                    OHM_TRY(vbicg_s((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.r),
-                                    at<double>(P.v), at<double>(P.s), st));
-                    OHM_TRY(precond(P.s, P.sh));
-                    OHM_TRY(composite(P.sh, P.t, MODE_APPLY, lam_dt, lam_dt, 0));
-                    {
-                        const double *xs[2] = {at<double>(P.t), at<double>(P.t)},
-                                     *ys[2] = {at<double>(P.s), at<double>(P.t)};
-                        OHM_TRY(dots(xs, ys, 2));
-                        OHM_TRY(vscal(np, 3, active, at<double>(P.dots), 2, at<double>(P.scal), st));
-                    }
-                    OHM_TRY(vbicg_xr((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.x),
-                                     at<double>(P.ph), at<double>(P.sh), at<double>(P.s), at<double>(P.t),
-                                     at<double>(P.r), at<double>(P.rhat), at<double>(P.part), st));
-                    OHM_TRY(reduce(2, 2, at<double>(P.dots)));
-                    OHM_TRY(vscal(np, 4, active, at<double>(P.dots), 2, at<double>(P.scal), st));
+                    OHM_TRY(replay(1, [&]() { return bicg_iter(); }));
                     ++it_total;
                     std::vector<double> d((size_t)np * 2);
                     OHM_HIP(hipMemcpyAsync(d.data(), at<double>(P.dots), sizeof(double) * 2 * np, hipMemcpyDeviceToHost,
@@ -624,6 +689,7 @@ void ohm_cn_default_opts(ohm_cn_opts *o)
     o->outer = 1;
     o->precision = 0;
     o->coarse_sweeps = 16;
+    o->graph = 1;
 }
 
 ohm_status ohm_cn_workspace_size(const ohm_hier *h, const ohm_cn_opts *opts, size_t *bytes)

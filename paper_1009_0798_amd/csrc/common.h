@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -36,6 +37,10 @@ ohm_status fail(ohm_status st, const char *fmt, ...);
     } while (0)
 
 ohm_status check_launch(const char *what);
+
+// serialises graph capture against handle creation/destruction (which touch the
+// device outside any stream) when several host threads share the library
+std::mutex &capture_mutex();
 
 // ---------------------------------------------------------------------------
 // device-side tables of one AMR level (all problems of a handle)
@@ -124,8 +129,16 @@ struct ohm_hier {
     hipEvent_t ring_ev[64] = {};
     bool ring_live[64] = {};
     int ring_pos = 0;
+    // captured outer iteration of ohm_cn_step, reused while its key matches
+    hipGraphExec_t graph_exec = nullptr;
+    hipStream_t cap_stream = nullptr;    // capture stream (the null stream cannot be captured)
+    std::vector<const void *> graph_key;
+    std::vector<char> graph_opts;
+    int graph_kind = -1;
     // solver state cache
     double *d_coarse_inv = nullptr;  // per-problem dense inverse of the coarsest grid
+    double *d_coarse_eta = nullptr;  // coarsest resistivity each inverse was built from
+    int *d_coarse_flags = nullptr;   // rebuild flags / forced rebuilds per job
     std::vector<long long> cinv_off; // element offset per problem, -1 if none
     std::vector<int> cinv_n;         // unknowns per problem
     std::vector<double> cinv_lamdt;  // lam_dt the inverse was built for

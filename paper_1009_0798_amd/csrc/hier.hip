@@ -26,6 +26,12 @@ ohm_status fail(ohm_status st, const char *fmt, ...)
     return st;
 }
 
+std::mutex &capture_mutex()
+{
+    static std::mutex m;
+    return m;
+}
+
 ohm_status check_launch(const char *what)
 {
     hipError_t e = hipGetLastError();
@@ -62,13 +68,17 @@ bool coarsen_ok(const int n[3])
            n[2] >= 4 && (long long)n[0] * n[1] * n[2] > 64;
 }
 
+// stream of the handle being built (uploads are ordered on it, then synchronised)
+thread_local hipStream_t g_up_stream = nullptr;
+
 template <typename V>
 ohm_status upload(V **dptr, const std::vector<V> &h)
 {
     *dptr = nullptr;
     if (h.empty()) return OHM_OK;
     OHM_HIP(hipMalloc((void **)dptr, sizeof(V) * h.size()));
-    OHM_HIP(hipMemcpy(*dptr, h.data(), sizeof(V) * h.size(), hipMemcpyHostToDevice));
+    OHM_HIP(hipMemcpyAsync(*dptr, h.data(), sizeof(V) * h.size(), hipMemcpyHostToDevice, g_up_stream));
+    OHM_HIP(hipStreamSynchronize(g_up_stream));
     return OHM_OK;
 }
 
@@ -400,11 +410,13 @@ static void free_all(ohm_hier *H)
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
     }
-    void *ptrs[] = {H->d_scal, H->d_part, H->d_norms, H->d_coarse_inv, H->d_ring};
+    void *ptrs[] = {H->d_scal, H->d_part, H->d_norms, H->d_coarse_inv, H->d_ring, H->d_coarse_eta, H->d_coarse_flags};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (int i = 0; i < 64; ++i)
         if (H->ring_ev[i]) (void)hipEventDestroy(H->ring_ev[i]);
+    if (H->graph_exec) (void)hipGraphExecDestroy(H->graph_exec);
+    if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
 }
 
 }  // namespace ohm
@@ -418,13 +430,15 @@ const char *ohm_last_error(void) { return g_err.c_str(); }
 ohm_status ohm_hier_create(const ohm_problem_desc *probs, int32_t nprob, hipStream_t stream,
                            ohm_hier **out)
 {
-    (void)stream;
     if (!out) return fail(OHM_ERR_ARG, "out is NULL");
     *out = nullptr;
     if (!probs || nprob < 1) return fail(OHM_ERR_ARG, "need at least one problem");
     ohm_hier *H = new (std::nothrow) ohm_hier();
     if (!H) return fail(OHM_ERR_NOMEM, "host allocation failed");
+    std::lock_guard<std::mutex> lock(capture_mutex());
+    g_up_stream = stream;
     ohm_status st = build(H, probs, nprob);
+    g_up_stream = nullptr;
     if (st != OHM_OK) {
         free_all(H);
         delete H;
@@ -437,6 +451,7 @@ ohm_status ohm_hier_create(const ohm_problem_desc *probs, int32_t nprob, hipStre
 ohm_status ohm_hier_destroy(ohm_hier *h)
 {
     if (!h) return OHM_OK;
+    std::lock_guard<std::mutex> lock(capture_mutex());
     free_all(h);
     delete h;
     return OHM_OK;

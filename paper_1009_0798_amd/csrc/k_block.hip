@@ -472,24 +472,42 @@ __global__ void k_zero_covered(int nblk, const uint8_t *__restrict__ cov, T *__r
     }
 }
 
-// per-problem reduction of per-block partials (sums for k < ksum, max after),
-// fixed order: one thread per (problem, quantity) walks the problem's block
-// ranges (one range per AMR level) in order
-__global__ void k_reduce_blocks(int nprob, int nrange, const long long *__restrict__ range,
-                                const double *__restrict__ part, int k, int ksum, double *__restrict__ out)
+// per-problem reduction of per-block partials (sums for k < ksum, max after):
+// one workgroup per (problem, quantity); each thread walks a fixed strided
+// subset of the problem's blocks (ranges per AMR level, in order), then a
+// fixed-shape tree combines the threads -- the result depends only on the
+// problem's own blocks, never on the other problems of the handle
+__global__ void __launch_bounds__(256)
+k_reduce_blocks(int nprob, int nrange, const long long *__restrict__ range, const double *__restrict__ part, int k,
+                int ksum, double *__restrict__ out)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nprob * k) return;
-    const int p = t / k, q = t % k;
+    __shared__ double sred[4];
+    const int p = blockIdx.x / k, q = blockIdx.x % k;
+    const bool sum = q < ksum;
     double v = 0.0;
+    long long base = 0;   // running block count of the problem (thread striding is global over its ranges)
     for (int r = 0; r < nrange; ++r) {
         const long long b0 = range[2 * ((long long)p * nrange + r)], b1 = range[2 * ((long long)p * nrange + r) + 1];
-        for (long long b = b0; b < b1; ++b) {
-            double x = part[b * k + q];
-            v = (q < ksum) ? v + x : fmax(v, x);
+        const long long n = b1 - b0;
+        // element i of this range has problem-local index base + i; thread t owns indices = t mod 256
+        long long first = ((threadIdx.x - base) % 256 + 256) % 256;
+        for (long long i = first; i < n; i += 256) {
+            const double x = part[(b0 + i) * k + q];
+            v = sum ? v + x : fmax(v, x);
         }
+        base += n;
     }
-    out[t] = v;
+    for (int o = 32; o > 0; o >>= 1) {
+        const double w = __shfl_down(v, o, 64);
+        v = sum ? v + w : fmax(v, w);
+    }
+    if ((threadIdx.x & 63) == 0) sred[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = sred[0];
+        for (int w = 1; w < 4; ++w) t = sum ? t + sred[w] : fmax(t, sred[w]);
+        out[(long long)p * k + q] = t;
+    }
 }
 
 }  // namespace
@@ -602,8 +620,7 @@ ohm_status launch_zero_covered(const ohm_hier *h, int level, T *out, long long c
 ohm_status launch_reduce_problem(int nprob, int nrange, const long long *range_dev, const double *part, int k,
                                  int ksum, double *out, hipStream_t s)
 {
-    int n = nprob * k;
-    k_reduce_blocks<<<(n + 63) / 64, 64, 0, s>>>(nprob, nrange, range_dev, part, k, ksum, out);
+    k_reduce_blocks<<<nprob * k, 256, 0, s>>>(nprob, nrange, range_dev, part, k, ksum, out);
     return check_launch("reduce");
 }
 

@@ -129,13 +129,16 @@ struct CoarseJob {
     int n3;              // unknowns = 3 * cells
     long long inv_off;   // element offset of the inverse
     long long aug_off;   // element offset of the [n3][2 n3] augmented matrix (scratch)
+    long long eta_off;   // offset of the job's saved coarsest resistivity (cells)
     DenseProbDev q;
     double lam_dt;
 };
 
 __global__ void __launch_bounds__(256)
-k_coarse_assemble(const CoarseJob *__restrict__ jobs, const double *__restrict__ eta, double *__restrict__ aug)
+k_coarse_assemble(const CoarseJob *__restrict__ jobs, const int *__restrict__ flags, const double *__restrict__ eta,
+                  double *__restrict__ aug)
 {
+    if (!flags[blockIdx.y]) return;
     const CoarseJob J = jobs[blockIdx.y];
     const int col = blockIdx.x;
     if (col >= J.n3) return;
@@ -155,66 +158,85 @@ k_coarse_assemble(const CoarseJob *__restrict__ jobs, const double *__restrict__
     }
 }
 
+// does the coarsest resistivity of a job differ from the one its inverse was
+// built with?  (flag = 1 also when the host forces a rebuild)
 __global__ void __launch_bounds__(256)
-k_coarse_invert(const CoarseJob *__restrict__ jobs, double *__restrict__ aug, double *__restrict__ inv)
+k_coarse_check(const CoarseJob *__restrict__ jobs, const int *__restrict__ force, const double *__restrict__ eta,
+               double *__restrict__ saved, int *__restrict__ flags)
 {
+    const CoarseJob J = jobs[blockIdx.x];
+    const int cells = J.n3 / 3;
+    __shared__ int diff;
+    if (threadIdx.x == 0) diff = force[blockIdx.x];
+    __syncthreads();
+    double *sv = saved + J.eta_off;
+    for (int t = threadIdx.x; t < cells; t += blockDim.x)
+        if (sv[t] != eta[J.q.off + t]) diff = 1;
+    __syncthreads();
+    if (diff)
+        for (int t = threadIdx.x; t < cells; t += blockDim.x) sv[t] = eta[J.q.off + t];
+    if (threadIdx.x == 0) flags[blockIdx.x] = diff;
+}
+
+// Gauss-Jordan inversion with partial pivoting, one 32x32 workgroup per job.
+// Step k only touches columns k .. n+k of the augmented matrix [A | I].
+__global__ void __launch_bounds__(1024)
+k_coarse_invert(const CoarseJob *__restrict__ jobs, const int *__restrict__ flags, double *__restrict__ aug,
+                double *__restrict__ inv)
+{
+    if (!flags[blockIdx.x]) return;
     const CoarseJob J = jobs[blockIdx.x];
     const int n = J.n3, w = 2 * n;
     double *A = aug + J.aug_off;
-    __shared__ double sval[256];
-    __shared__ int sidx[256];
-    __shared__ int piv;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 32 + tx;
+    __shared__ double sval[1024];
+    __shared__ int sidx[1024];
     __shared__ double sfac[COARSE_MAX_DEV];
+    __shared__ double srow[COARSE_MAX_DEV + 1];
     for (int k = 0; k < n; ++k) {
-        // pivot search in column k, rows k..n-1 (fixed reduction order)
         double best = -1.0;
         int bi = k;
-        for (int r = k + threadIdx.x; r < n; r += blockDim.x) {
-            double a = fabs(A[(long long)r * w + k]);
+        for (int r = k + tid; r < n; r += 1024) {
+            const double a = fabs(A[r * w + k]);
             if (a > best) { best = a; bi = r; }
         }
-        sval[threadIdx.x] = best;
-        sidx[threadIdx.x] = bi;
+        sval[tid] = best;
+        sidx[tid] = bi;
         __syncthreads();
-        for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-            if (threadIdx.x < s) {
-                double o = sval[threadIdx.x + s];
-                int oi = sidx[threadIdx.x + s];
-                if (o > sval[threadIdx.x] || (o == sval[threadIdx.x] && oi < sidx[threadIdx.x])) {
-                    sval[threadIdx.x] = o;
-                    sidx[threadIdx.x] = oi;
+        for (int st = 512; st > 0; st >>= 1) {
+            if (tid < st) {
+                const double o = sval[tid + st];
+                const int oi = sidx[tid + st];
+                if (o > sval[tid] || (o == sval[tid] && oi < sidx[tid])) {
+                    sval[tid] = o;
+                    sidx[tid] = oi;
                 }
             }
             __syncthreads();
         }
-        if (threadIdx.x == 0) piv = sidx[0];
+        const int p = sidx[0];
+        // swap rows k and p over the live columns, scale the pivot row
+        const double d = 1.0 / A[p * w + k];
+        for (int cc = tid; cc <= n; cc += 1024) {
+            const int c = k + cc;
+            const double vk = A[k * w + c], vp = A[p * w + c];
+            srow[cc] = vp * d;
+            if (p != k) A[p * w + c] = vk;
+        }
         __syncthreads();
-        const int p = piv;
-        if (p != k)
-            for (int c = threadIdx.x; c < w; c += blockDim.x) {
-                double t = A[(long long)k * w + c];
-                A[(long long)k * w + c] = A[(long long)p * w + c];
-                A[(long long)p * w + c] = t;
-            }
+        for (int cc = tid; cc <= n; cc += 1024) A[k * w + k + cc] = srow[cc];
+        for (int r = tid; r < n; r += 1024) sfac[r] = (r == k) ? 0.0 : A[r * w + k];
         __syncthreads();
-        const double d = 1.0 / A[(long long)k * w + k];
-        __syncthreads();
-        for (int c = threadIdx.x; c < w; c += blockDim.x) A[(long long)k * w + c] *= d;
-        // eliminate column k from every other row at once
-        for (int r = threadIdx.x; r < n; r += blockDim.x) sfac[r] = (r == k) ? 0.0 : A[(long long)r * w + k];
-        __syncthreads();
-        for (long long t = threadIdx.x; t < (long long)n * w; t += blockDim.x) {
-            const int r = (int)(t / w), c = (int)(t % w);
+        for (int r = ty; r < n; r += 32) {
             const double f = sfac[r];
-            if (f != 0.0) A[t] -= f * A[(long long)k * w + c];
+            if (f == 0.0) continue;
+            for (int cc = tx; cc <= n; cc += 32) A[r * w + k + cc] -= f * srow[cc];
         }
         __syncthreads();
     }
     double *X = inv + J.inv_off;
-    for (long long t = threadIdx.x; t < (long long)n * n; t += blockDim.x) {
-        const long long r = t / n, c = t % n;
-        X[t] = A[r * w + n + c];
-    }
+    for (int r = ty; r < n; r += 32)
+        for (int c = tx; c < n; c += 32) X[r * n + c] = A[r * w + n + c];
 }
 
 template <typename T>
@@ -316,7 +338,7 @@ ohm_status coarse_sizes(const ohm_hier *h, size_t *inv_elems, size_t *aug_elems)
 static std::vector<CoarseJob> coarse_jobs(const ohm_hier *h, const double *lam_dt_host, int depth_filter)
 {
     std::vector<CoarseJob> jobs;
-    long long io = 0, ao = 0;
+    long long io = 0, ao = 0, eo = 0;
     for (int p = 0; p < h->nprob; ++p) {
         const auto &P = h->probs[p];
         const int dd = -P.min_level;
@@ -328,8 +350,10 @@ static std::vector<CoarseJob> coarse_jobs(const ohm_hier *h, const double *lam_d
         J.n3 = n3;
         J.inv_off = io;
         J.aug_off = ao;
+        J.eta_off = eo;
         io += (long long)n3 * n3;
         ao += 2LL * n3 * n3;
+        eo += n3 / 3;
         J.q.nx = d[0];
         J.q.ny = d[1];
         J.q.nz = d[2];
@@ -351,18 +375,40 @@ size_t coarse_job_count(const ohm_hier *h, int depth)
 ohm_status build_coarse_inverses(ohm_hier *h, const double *const *eta_dense, const double *lam_dt_host,
                                  double *inv, double *aug, void *jobs_dev, hipStream_t s)
 {
-    // one launch per depth (each problem's coarsest grid lives at its own depth)
+    // inverses live in the handle and are rebuilt only for problems whose
+    // lam_dt or coarsest resistivity changed since the last build
+    size_t inv_elems = 0, aug_elems = 0;
+    coarse_sizes(h, &inv_elems, &aug_elems);
+    (void)inv;
+    if (inv_elems == 0) return OHM_OK;
+    if (!h->d_coarse_inv) {
+        OHM_HIP(hipMalloc((void **)&h->d_coarse_inv, sizeof(double) * inv_elems));
+        // saved resistivity: one cells-sized slot at inv_off / n3 per job
+        OHM_HIP(hipMalloc((void **)&h->d_coarse_eta, sizeof(double) * inv_elems));
+        OHM_HIP(hipMalloc((void **)&h->d_coarse_flags, sizeof(int) * 2 * (size_t)h->nprob));
+        h->cinv_lamdt.assign(h->nprob, -1.0);
+    }
     for (int dd = 1; dd <= -h->min_level; ++dd) {
         std::vector<CoarseJob> jobs = coarse_jobs(h, lam_dt_host, dd);
         if (jobs.empty()) continue;
+        std::vector<int> force(jobs.size());
+        for (size_t j = 0; j < jobs.size(); ++j) {
+            const int p = jobs[j].prob;
+            force[j] = (h->cinv_lamdt[p] != lam_dt_host[p]) ? 1 : 0;
+            h->cinv_lamdt[p] = lam_dt_host[p];
+        }
         CoarseJob *jd = (CoarseJob *)jobs_dev;
+        int *fl = h->d_coarse_flags, *fo = h->d_coarse_flags + h->nprob;
         OHM_HIP(hipMemcpyAsync(jd, jobs.data(), sizeof(CoarseJob) * jobs.size(), hipMemcpyHostToDevice, s));
+        OHM_HIP(hipMemcpyAsync(fo, force.data(), sizeof(int) * force.size(), hipMemcpyHostToDevice, s));
+        k_coarse_check<<<(unsigned)jobs.size(), 256, 0, s>>>(jd, fo, eta_dense[dd], h->d_coarse_eta, fl);
+        OHM_TRY(check_launch("coarse check"));
         int maxn = 0;
         for (auto &J : jobs) maxn = std::max(maxn, J.n3);
         dim3 g(maxn, (unsigned)jobs.size());
-        k_coarse_assemble<<<g, 256, 0, s>>>(jd, eta_dense[dd], aug);
+        k_coarse_assemble<<<g, 256, 0, s>>>(jd, fl, eta_dense[dd], aug);
         OHM_TRY(check_launch("coarse assemble"));
-        k_coarse_invert<<<(unsigned)jobs.size(), 256, 0, s>>>(jd, aug, inv);
+        k_coarse_invert<<<(unsigned)jobs.size(), dim3(32, 32), 0, s>>>(jd, fl, aug, h->d_coarse_inv);
         OHM_TRY(check_launch("coarse invert"));
         OHM_HIP(hipStreamSynchronize(s));   // the job table is reused per depth
     }

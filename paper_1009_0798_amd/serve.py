@@ -58,7 +58,8 @@ class Request:
 def footprint(req: Request, opts) -> int:
     """Device bytes of one request solved alone: B and eta per level plus the
     solver workspace."""
-    h = Hierarchy([(req.base_blocks, req.dx0, req.levels)])
+    import torch
+    h = Hierarchy([(req.base_blocks, req.dx0, req.levels)], torch.cuda.current_stream())
     nb = ctypes.c_size_t()
     _lib.check(_lib.lib().ohm_cn_workspace_size(h.h, ctypes.byref(opts), ctypes.byref(nb)))
     h.close()
@@ -142,7 +143,7 @@ class Server:
         for r in batch:
             r.started = t_start
         with torch.cuda.stream(stream):
-            h = Hierarchy([(r.base_blocks, r.dx0, r.levels) for r in batch])
+            h = Hierarchy([(r.base_blocks, r.dx0, r.levels) for r in batch], stream)
             nlev = max(len(r.levels) for r in batch)
             B, E = [], []
             for l in range(nlev):

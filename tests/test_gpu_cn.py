@@ -28,7 +28,9 @@ def _gpu_step(spec, B, eta, dt, **opts):
     ijk = spec.levels[0]
     Bt = [cuda(dense_to_blocks(B, ijk))]
     Et = [cuda(dense_to_blocks(eta, ijk)[None])]
-    st, stats = ohm.ohm_cn_step(H, Bt, Et, dt, ohm.default_opts(rtol=RTOL, **opts))
+    kw = dict(rtol=RTOL)
+    kw.update(opts)
+    st, stats = ohm.ohm_cn_step(H, Bt, Et, dt, ohm.default_opts(**kw))
     return st, stats, blocks_to_dense(host(Bt[0]), ijk, spec.cells(0))
 
 
@@ -167,3 +169,63 @@ def test_full_size_lognormal128_residual(precision):
     S = ref.source(cfg["B"], cfg["eta"], h, cfg["dt"])
     R = ref.residual(got, S, cfg["eta"], h, 0.5 * cfg["dt"])
     assert np.linalg.norm(R) <= 1.01 * RTOL * np.linalg.norm(S)
+
+
+@pytest.mark.parametrize("outer", [1, 0])
+def test_graph_replay_matches_eager(outer):
+    """The captured outer iteration is replayed many times per step and across
+    steps, with eager setup work and host synchronisation between replays:
+    every step must equal the eager run bitwise."""
+    import torch
+    import paper_1009_0798_amd as ohm
+    announce(f"graph vs eager outer={outer}")
+    n = 32
+    spec = gen.uniform_spec(n)
+    B0 = gen.divfree(n, 2.0, seed=81)
+    eta = gen.lognormal_eta(n, 3.0, seed=82)
+    dt = gen.explicit_dt(spec.dx0, 1.0, 50.0)
+    ijk = spec.levels[0]
+    res = {}
+    for graph in (0, 1):
+        H = hier(spec)
+        Bt = [cuda(dense_to_blocks(B0, ijk))]
+        Et = [cuda(dense_to_blocks(eta, ijk)[None])]
+        ws = ohm.Workspace()
+        outs = []
+        for step in range(3):
+            st, stats = ohm.ohm_cn_step(H, Bt, Et, dt, ohm.default_opts(rtol=RTOL, outer=outer, graph=graph,
+                                                                       max_iters=300), ws)
+            assert st == 0
+            torch.cuda.synchronize()
+            outs.append(Bt[0].cpu().numpy().copy())
+        res[graph] = outs
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
+
+
+def test_coarse_inverse_cache_follows_eta_and_dt():
+    """The coarsest-grid inverse kept in the handle is rebuilt when the
+    resistivity changes in place or dt changes: results equal a fresh handle."""
+    import torch
+    import paper_1009_0798_amd as ohm
+    announce("coarse inverse cache")
+    n = 16
+    spec = gen.uniform_spec(n)
+    ijk = spec.levels[0]
+    B0 = gen.divfree(n, 2.0, seed=91)
+    e1 = gen.lognormal_eta(n, 3.0, seed=92)
+    e2 = gen.lognormal_eta(n, 3.0, seed=93)
+    dt1 = gen.explicit_dt(spec.dx0, 1.0, 40.0)
+    dt2 = 2.5 * dt1
+    H = hier(spec)
+    Et = [cuda(dense_to_blocks(e1, ijk)[None])]
+    ws = ohm.Workspace()
+    opts = ohm.default_opts(rtol=RTOL)
+    for eta, dt in ((e1, dt1), (e2, dt1), (e2, dt2)):
+        Et[0].copy_(cuda(dense_to_blocks(eta, ijk)[None]))
+        Bt = [cuda(dense_to_blocks(B0, ijk))]
+        st, _ = ohm.ohm_cn_step(H, Bt, Et, dt, opts, ws)
+        st2, _, fresh = _gpu_step(spec, B0, eta, dt)
+        assert st == 0 and st2 == 0
+        got = blocks_to_dense(host(Bt[0]), ijk, spec.cells(0))
+        assert np.array_equal(got, fresh)

@@ -65,10 +65,16 @@ def test_admission_by_footprint():
     srv = Server(hbm_budget=max(fps), n_streams=2)
     done = srv.serve(reqs, [0.0, 0.0, 0.0])
     assert all(r.status == 0 for r in done)
-    # never two requests resident together: admissions follow completions
-    ev = sorted([(r.admitted, r.done) for r in done])
-    for (a0, d0), (a1, d1) in zip(ev, ev[1:]):
-        assert a1 >= d0 - 1e-6
+    # at every admission the footprints of the resident requests fit the budget
+    fp = {r.rid: f for r, f in zip(reqs, fps)}
+    for r in done:
+        t = r.admitted
+        resident = [q for q in done if q.admitted <= t < q.done]
+        assert sum(fp[q.rid] for q in resident) <= max(fps)
+    # and the largest request was never resident with another one
+    big = max(done, key=lambda q: fp[q.rid])
+    others = [q for q in done if q is not big]
+    assert all(q.done <= big.admitted + 1e-9 or q.admitted >= big.done - 1e-9 for q in others)
     tiny = Server(hbm_budget=min(fps) - 1, n_streams=1)
     done = tiny.serve(reqs[:1], [0.0])
     assert done[0].status != 0
