@@ -19,6 +19,32 @@ import numpy as np
 
 METRIC = "solved cells/s per CN step at rel. residual 1e-10 (FP64 vs mixed); HBM GB/s"
 HBM_PEAK_GBS = 8000.0
+NU = 3          # V(3,3): the schedule the autotuner picks for this workload on MI355X
+
+
+def sweep_source_hash() -> str:
+    """Hash of the fused-sweep kernel source (and the stencil it uses); the
+    counter traffic recorded under profiles/ is valid only for that source."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    src = open(os.path.join(root, "paper_1009_0798_amd", "csrc", "k_block.hip")).read()
+    a = src.index("template <typename T>\n__global__ void __launch_bounds__(SWEEP_THREADS)\nk_blk_sweep(")
+    b = src.index("\n}\n", a) + 3
+    body = src[a:b] + open(os.path.join(root, "paper_1009_0798_amd", "csrc", "stencil.h")).read()
+    return hashlib.sha256(body.encode()).hexdigest()[:16]
+
+
+def counter_traffic(tag: str):
+    """HBM bytes per launch from the committed counter runs (FETCH_SIZE and
+    WRITE_SIZE, calibrated on a 256 MiB device copy), or None if the kernel
+    changed since they were taken."""
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        with open(os.path.join(root, "profiles", "roofline_counters.json")) as f:
+            rec = json.load(f)["kernels"][tag]
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["hbm_bytes"] if rec["source_sha256_16"] == sweep_source_hash() else None
 
 
 def _log(msg):
@@ -28,7 +54,7 @@ def _log(msg):
 def run_steps(ohm, H, B0, E, dt, K, precision, ws):
     import torch
     B = [B0.clone()]
-    opts = ohm.default_opts(rtol=1e-10, precision=precision, max_iters=200)
+    opts = ohm.default_opts(rtol=1e-10, precision=precision, max_iters=200, nu_pre=NU, nu_post=NU)
     iters = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -110,6 +136,43 @@ def bench_batched(args):
                        "cells": cells, "schedule": best, "worst_rel_res": worst}}
 
 
+def bench_amr(args):
+    """Two-level hierarchy: 64^3 base, central 1/8 plus a seeded 20% of the
+    other base blocks refined; dense-core eta; FP64 and mixed."""
+    import torch
+    import ohm_inputs as gen
+    import paper_1009_0798_amd as ohm
+    spec = gen.config_amr2(n_base=64, extra_frac=0.2, seed=4)
+    Bb, eb = gen.amr_fields_fourier(spec, seed=5)
+    dt = 20.0 * spec.dx(1) ** 2 / (6 * 10.0)
+    H = ohm.Hierarchy([(spec.base_blocks, spec.dx0, spec.levels)])
+    B0 = [torch.from_numpy(b).cuda() for b in Bb]
+    E = [torch.from_numpy(e[None]).cuda() for e in eb]
+    cells = spec.leaf_cells()
+    out = {}
+    for prec in (0, 1):
+        ws = ohm.Workspace()
+        opts = ohm.default_opts(rtol=1e-10, max_iters=300, precision=prec, nu_pre=args.nu, nu_post=args.nu)
+        for _ in range(args.warmup):
+            ohm.ohm_cn_step(H, [b.clone() for b in B0], E, dt, opts, ws)
+        Bs = [[b.clone() for b in B0] for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            st, stats = ohm.ohm_cn_step(H, Bs[k], E, dt, opts, ws)
+            assert st == 0, st
+        torch.cuda.synchronize()
+        out[prec] = ((time.perf_counter() - t0) / args.steps, stats[0])
+    t, stats = out[0]
+    return {"metric": METRIC, "value": cells / t, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "amr2: 64^3 base + level 1 over the central 1/8 and 20% of other base blocks, "
+                                   "dense-core eta, dt = 20x explicit on the fine level", "leaf_cells": cells,
+                       "iterations": stats["iters"], "V": args.nu},
+            "mixed": {"value": cells / out[1][0], "ms_per_step": out[1][0] * 1e3, "iterations": out[1][1]["iters"]}}
+
+
 def bench_serve(args):
     """Poisson arrivals of 1-3 level AMR requests, continuous batching."""
     import numpy as np
@@ -140,6 +203,29 @@ def bench_serve(args):
             "latency": rep}
 
 
+def roofline_probe(args):
+    """A plain device copy of 256 MiB (calibrates the HBM byte counters) and
+    ten smoother launches on the level-0 blocks of the 128^3 workload."""
+    import torch
+    import ohm_inputs as gen
+    import paper_1009_0798_amd as ohm
+    src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    cfg = gen.config_lognormal128(args.n)
+    spec = cfg["spec"]
+    ijk = spec.levels[0]
+    H = ohm.Hierarchy([(spec.base_blocks, spec.dx0, spec.levels)])
+    B0 = ohm.to_blocks(torch.from_numpy(cfg["B"]), ijk).cuda()
+    E = ohm.to_blocks(torch.from_numpy(cfg["eta"])[None], ijk).cuda()
+    S = torch.randn_like(B0)
+    for dt in (torch.float64, torch.float32):
+        t = smoother_rate(ohm, H, B0, S, E, 0.5 * cfg["dt"], dt, nsweeps=10)
+        _log(f"smoother {dt}: {t * 1e6:.2f} us per launch")
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -148,7 +234,8 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--cpu-sample", type=int, default=64, help="grid edge of the oracle sample (0: skip)")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--workload", default="lognormal128", choices=["lognormal128", "batched", "serve"])
+    ap.add_argument("--workload", default="lognormal128", choices=["lognormal128", "batched", "serve", "amr"])
+    ap.add_argument("--nu", type=int, default=3, help="pre/post sweeps of the multigrid cycle")
     ap.add_argument("--nprob", type=int, default=256)
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--pool", type=int, default=8)
@@ -156,6 +243,8 @@ def main():
     ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--hbm-gb", type=float, default=64.0)
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="run only a known-size copy and the level-0 smoother launches (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (see the sharding design notes)",
@@ -165,11 +254,17 @@ def main():
     import ohm_inputs as gen
     import paper_1009_0798_amd as ohm
 
+    if args.roofline_only:
+        roofline_probe(args)
+        return
     if args.workload == "batched":
         print(json.dumps(bench_batched(args)), flush=True)
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(args)), flush=True)
+        return
+    if args.workload == "amr":
+        print(json.dumps(bench_amr(args)), flush=True)
         return
     n = args.n
     cfg = gen.config_lognormal128(n)
@@ -203,11 +298,11 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"lognormal{n}: {n}^3 periodic, eta log-normal 4 decades, div-free k^-2 B, "
                                f"dt = 100x explicit limit, consecutive CN steps to rel. residual 1e-10",
-                   "cells": cells, "outer": "BiCGStab", "cycle": "V(2,2)",
+                   "cells": cells, "outer": "BiCGStab", "cycle": f"V({NU},{NU})",
                    "iterations_per_step": f64["iters"]},
         "roofline": {"kernel": "k_blk_sweep<double> (one fused red-black sweep, level 0)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic("f64"),
                      "us_per_launch": t_sw * 1e6, "bytes_per_launch": bytes_sw},
     }
     if "mixed" in res:

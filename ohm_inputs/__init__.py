@@ -421,3 +421,22 @@ def amr_request(rng, n0, nlevels, decades, m, frac=0.125):
     hf = spec.dx(spec.nlevels - 1)
     dt = explicit_dt(hf, 1.0, m)
     return dict(spec=spec, B=[np.ascontiguousarray(b) for b in Bs], eta=[np.ascontiguousarray(e) for e in es], dt=dt)
+
+
+def amr_fields_fourier(spec: HierSpec, seed=5, eta_fn=dense_core_eta, origin=-0.5, nmodes=16):
+    """Smooth div-free B (random Fourier modes on the unit box) and eta_fn at
+    the cell centres of every level; covered coarse B = mean of its children.
+    Returns per-level block arrays ([3, nb, 8, 8, 8], [nb, 8, 8, 8])."""
+    F = FourierField(np.random.default_rng(seed), nmodes=nmodes)
+    Bs, es = [], []
+    for l in range(spec.nlevels):
+        x, y, z = level_centres(spec, l, origin)
+        Bs.append(F.vector(x - origin, y - origin, z - origin))
+        es.append(np.ascontiguousarray(eta_fn(x, y, z)))
+    for l in range(spec.nlevels - 1, 0, -1):
+        par = {tuple(b): i for i, b in enumerate(spec.levels[l - 1])}
+        for i, (bi, bj, bk) in enumerate(spec.levels[l]):
+            pi_ = par[(bi >> 1, bj >> 1, bk >> 1)]
+            ox, oy, oz = 4 * (bi & 1), 4 * (bj & 1), 4 * (bk & 1)
+            Bs[l - 1][:, pi_, oz:oz + 4, oy:oy + 4, ox:ox + 4] = Bs[l][:, i].reshape(3, 4, 2, 4, 2, 4, 2).mean(axis=(2, 4, 6))
+    return [np.ascontiguousarray(b) for b in Bs], es

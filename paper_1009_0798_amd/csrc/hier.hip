@@ -301,36 +301,65 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
             if (l + 1 >= P.nlevels) continue;
             const LevelMap &M = maps[p][l], &F = maps[p][l + 1];
             int box[3] = {M.box[0] * NB, M.box[1] * NB, M.box[2] * NB};
-            auto covered = [&](int X, int Y, int Z) {   // level-l global cell
-                X = wrapi(X, box[0]); Y = wrapi(Y, box[1]); Z = wrapi(Z, box[2]);
-                return F.has(X >> 2, Y >> 2, Z >> 2);    // fine block covering the cell
-            };
+            // covered octants of every level-l block of the problem
+            std::vector<uint8_t> cm(P.nb[l], 0);
             for (int b = 0; b < P.nb[l]; ++b) {
                 const int *q = &P.blocks[l][3 * b];
+                for (int o = 0; o < 8; ++o)
+                    if (F.has(2 * q[0] + (o & 1), 2 * q[1] + ((o >> 1) & 1), 2 * q[2] + (o >> 2)))
+                        cm[b] |= (uint8_t)(1u << o);
+            }
+            for (int b = 0; b < P.nb[l]; ++b) {
+                const int *q = &P.blocks[l][3 * b];
+                // masks of the block and its 6 face neighbours (0 if absent)
+                uint8_t fm[3][2];
+                bool any = cm[b] != 0;
+                for (int d = 0; d < 3; ++d)
+                    for (int s = 0; s < 2; ++s) {
+                        int n[3] = {q[0], q[1], q[2]};
+                        n[d] += s ? -1 : 1;
+                        const int nb_ = M.get(n[0], n[1], n[2]);
+                        fm[d][s] = nb_ >= 0 ? cm[nb_] : 0;
+                        any |= fm[d][s] != 0;
+                    }
+                if (!any) continue;
+                // is local cell (x,y,z), at most one coordinate outside 0..7, covered?
+                auto covered = [&](int x, int y, int z) {
+                    const int c[3] = {x, y, z};
+                    uint8_t m = cm[b];
+                    int l3[3] = {x, y, z};
+                    for (int d = 0; d < 3; ++d) {
+                        if (c[d] < 0) { m = fm[d][1]; l3[d] = c[d] + NB; }
+                        else if (c[d] >= NB) { m = fm[d][0]; l3[d] = c[d] - NB; }
+                    }
+                    const int o = (l3[0] >> 2) + 2 * (l3[1] >> 2) + 4 * (l3[2] >> 2);
+                    return ((m >> o) & 1) != 0;
+                };
                 for (int z = 0; z < NB; ++z)
                 for (int y = 0; y < NB; ++y)
                 for (int x = 0; x < NB; ++x) {
-                    int X = q[0] * NB + x, Y = q[1] * NB + y, Z = q[2] * NB + z;
-                    if (covered(X, Y, Z)) continue;
+                    if (covered(x, y, z)) continue;
                     int ent[RF_INTS];
                     for (int t = 0; t < RF_INTS; ++t) ent[t] = -1;
                     int mask = 0;
                     for (int d = 0; d < 3; ++d)
                         for (int s = 0; s < 2; ++s) {
-                            int sg = s ? -1 : 1;
-                            int Q[3] = {X, Y, Z};
-                            Q[d] += sg;
-                            if (!covered(Q[0], Q[1], Q[2])) continue;
-                            int f = 2 * d + s;
+                            const int sg = s ? -1 : 1;
+                            int lc[3] = {x, y, z};
+                            lc[d] += sg;
+                            if (!covered(lc[0], lc[1], lc[2])) continue;
+                            const int f = 2 * d + s;
                             mask |= 1 << f;
+                            // covered coarse cell Q (level-l global, wrapped)
+                            int Q[3] = {q[0] * NB + x, q[1] * NB + y, q[2] * NB + z};
+                            Q[d] += sg;
                             for (int a = 0; a < 3; ++a) Q[a] = wrapi(Q[a], box[a]);
-                            int fb = F.get(Q[0] >> 2, Q[1] >> 2, Q[2] >> 2);
+                            const int fb = F.get(Q[0] >> 2, Q[1] >> 2, Q[2] >> 2);
                             // fine children of Q next to the face: along d the
                             // low child (2Q) when Q is above, the high one (2Q+1)
                             // when below; transverse the low child 2Q_t
                             int fl[3];
-                            for (int a = 0; a < 3; ++a)
-                                fl[a] = 2 * Q[a] - NB * (Q[a] >> 2);   // local fine index
+                            for (int a = 0; a < 3; ++a) fl[a] = 2 * Q[a] - NB * (Q[a] >> 2);
                             if (sg < 0) fl[d] += 1;
                             ent[3 + f] = (int)P.boff[l + 1] + fb;
                             ent[9 + f] = fl[0] + NB * (fl[1] + NB * fl[2]);

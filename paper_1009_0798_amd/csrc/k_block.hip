@@ -142,8 +142,10 @@ constexpr int TC2 = TW2 * TW2 * TW2;
 template <typename T>
 __device__ __forceinline__ int tix2(int x, int y, int z) { return (x + 2) + TW2 * ((y + 2) + TW2 * (z + 2)); }
 
+constexpr int SWEEP_THREADS = 512;
+
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(SWEEP_THREADS)
 k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ prob_of,
             const int *__restrict__ active, const double *__restrict__ inv_h2_p, const double *__restrict__ coef_p,
             const T *__restrict__ B, long long cs, const T *__restrict__ S, const T *__restrict__ eta,
@@ -157,7 +159,7 @@ k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ p
     if (active && !active[pr]) return;
     if (threadIdx.x < 27) snbr[threadIdx.x] = nbr_tab[27 * (long long)b + threadIdx.x];
     __syncthreads();
-    for (int t = threadIdx.x; t < TC2; t += blockDim.x) {
+    for (int t = threadIdx.x; t < TC2; t += SWEEP_THREADS) {
         const int x = t % TW2 - 2, y = (t / TW2) % TW2 - 2, z = t / (TW2 * TW2) - 2;
         const int sx = side(x), sy = side(y), sz = side(z);
         const int n = snbr[(sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
@@ -171,63 +173,66 @@ k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ p
     const T ih2 = T(inv_h2_p[pr]);
     const T coef = T(coef_p[pr]);
     const T cih2 = coef * ih2;
-    // red half-sweep: 256 block cells + 192 first-layer face cells
-    T red[2][3];
-    int rp[2];
-#pragma unroll
-    for (int round = 0; round < 2; ++round) {
-        const int u = threadIdx.x + 256 * round;
-        rp[round] = -1;
-        if (u >= 448) continue;
-        int x, y, z;
-        if (u < 256) {
-            z = u >> 5;
-            y = (u >> 2) & 7;
-            x = 2 * (u & 3) + ((y + z) & 1);
-        } else {
-            const int v = u - 256, f = v >> 5, w = v & 31;
-            const int d = f >> 1, s = (f & 1) ? NB : -1;
-            const int bb = w >> 2, a = 2 * (w & 3) + ((s + bb) & 1);
-            if (d == 0) { x = s; y = a; z = bb; }
-            else if (d == 1) { x = a; y = s; z = bb; }
-            else { x = a; y = bb; z = s; }
-        }
-        const int p = tix2<T>(x, y, z);
-        rp[round] = p;
-        const int sx = side(x), sy = side(y), sz = side(z);
-        const int n = snbr[(sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
-        const long long gi = (long long)n * NC + (x - NB * sx) + NB * ((y - NB * sy) + NB * (z - NB * sz));
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const T LB = sB[c][p] + cih2 * divF_cube<T, TW2>(sB[0], sB[1], sB[2], sE, p, c);
-            red[round][c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * alpha_cube<T, TW2>(sE, p, c));
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int round = 0; round < 2; ++round)
-        if (rp[round] >= 0)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) sB[c][rp[round]] = red[round][c];
-    __syncthreads();
-    // black half-sweep on the block cells
+    // red half-sweep: thread u < 256 takes block cell u of the red colour,
+    // 256 <= u < 448 a red first-layer face cell
+    T red[3];
+    int rp = -1;
     {
         const int u = threadIdx.x;
-        const int z = u >> 5, y = (u >> 2) & 7, x = 2 * (u & 3) + (1 - ((y + z) & 1));
-        const int p = tix2<T>(x, y, z);
-        const long long gi = (long long)b * NC + x + NB * (y + NB * z);
-        T blk[3];
+        if (u < 448) {
+            int x, y, z;
+            if (u < 256) {
+                z = u >> 5;
+                y = (u >> 2) & 7;
+                x = 2 * (u & 3) + ((y + z) & 1);
+            } else {
+                const int v = u - 256, f = v >> 5, w = v & 31;
+                const int d = f >> 1, s = (f & 1) ? NB : -1;
+                const int bb = w >> 2, a = 2 * (w & 3) + ((s + bb) & 1);
+                if (d == 0) { x = s; y = a; z = bb; }
+                else if (d == 1) { x = a; y = s; z = bb; }
+                else { x = a; y = bb; z = s; }
+            }
+            const int p = tix2<T>(x, y, z);
+            rp = p;
+            const int sx = side(x), sy = side(y), sz = side(z);
+            const int n = snbr[(sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
+            const long long gi = (long long)n * NC + (x - NB * sx) + NB * ((y - NB * sy) + NB * (z - NB * sz));
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const T LB = sB[c][p] + cih2 * divF_cube<T, TW2>(sB[0], sB[1], sB[2], sE, p, c);
-            blk[c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * alpha_cube<T, TW2>(sE, p, c));
+            for (int c = 0; c < 3; ++c) {
+                const T LB = sB[c][p] + cih2 * divF_cube<T, TW2>(sB[0], sB[1], sB[2], sE, p, c);
+                red[c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * alpha_cube<T, TW2>(sE, p, c));
+            }
         }
-        __syncthreads();
-#pragma unroll
-        for (int c = 0; c < 3; ++c) sB[c][p] = blk[c];
     }
     __syncthreads();
-    for (int cell = threadIdx.x; cell < NC; cell += blockDim.x) {
+    if (rp >= 0)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sB[c][rp] = red[c];
+    __syncthreads();
+    // black half-sweep on the block cells (threads 0..255)
+    {
+        const int u = threadIdx.x;
+        T blk[3];
+        int p = -1;
+        if (u < 256) {
+            const int z = u >> 5, y = (u >> 2) & 7, x = 2 * (u & 3) + (1 - ((y + z) & 1));
+            p = tix2<T>(x, y, z);
+            const long long gi = (long long)b * NC + x + NB * (y + NB * z);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const T LB = sB[c][p] + cih2 * divF_cube<T, TW2>(sB[0], sB[1], sB[2], sE, p, c);
+                blk[c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * alpha_cube<T, TW2>(sE, p, c));
+            }
+        }
+        __syncthreads();
+        if (p >= 0)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sB[c][p] = blk[c];
+    }
+    __syncthreads();
+    {
+        const int cell = threadIdx.x;
         const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
         const int p = tix2<T>(x, y, z);
 #pragma unroll
@@ -547,7 +552,7 @@ ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long 
     const AmrLevelDev &L = h->amr[level];
     if (L.nb == 0) return OHM_OK;
     if (!L.complete27) return fail(OHM_ERR_ARG, "fused sweep needs every neighbour block of level %d", level);
-    k_blk_sweep<T><<<L.nb, 256, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta, out);
+    k_blk_sweep<T><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta, out);
     return check_launch("fused sweep");
 }
 
