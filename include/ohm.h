@@ -199,6 +199,8 @@ typedef struct {
     int32_t outer;        /* 0 = iterative multigrid of eqs. (16)-(18), 1 = BiCGStab */
     int32_t precision;    /* 0 = FP64 everywhere, 1 = FP32 multigrid inside FP64 outer */
     int32_t coarse_sweeps;/* sweeps on a coarsest grid too large for a dense solve  */
+    int32_t nu_coarse;    /* sweeps before and after on the levels below the base grid
+                             (0 = nu_pre / nu_post)                                  */
     int32_t graph;        /* 1 = replay each outer iteration as a captured HIP graph
                              (kept in the handle while workspace, eta pointers and
                              options stay the same)                                 */

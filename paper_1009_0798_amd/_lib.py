@@ -35,7 +35,8 @@ class CnOpts(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("rtol", ctypes.c_double), ("max_iters", ctypes.c_int32),
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("n_vcycles", ctypes.c_int32),
                 ("cycle", ctypes.c_int32), ("outer", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("coarse_sweeps", ctypes.c_int32), ("graph", ctypes.c_int32)]
+                ("coarse_sweeps", ctypes.c_int32), ("nu_coarse", ctypes.c_int32),
+                ("graph", ctypes.c_int32)]
 
 
 class CnStats(ctypes.Structure):

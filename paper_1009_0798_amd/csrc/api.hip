@@ -200,6 +200,15 @@ ohm_status ohm_smooth(ohm_hier *h, int32_t level, void *B, const void *B_ghost, 
                                                 hipMemcpyDeviceToDevice, stream));
         return coef_done(h, slot, stream);
     }
+    if (level < 0) {
+        ohm_status st = dtype == OHM_F64
+                            ? launch_dense_smooth<double>(h, level, (double *)B, (double *)tmp, (const double *)S,
+                                                          (const double *)eta, cd, nsweeps, true, nullptr, stream)
+                            : launch_dense_smooth<float>(h, level, (float *)B, (float *)tmp, (const float *)S,
+                                                         (const float *)eta, cd, nsweeps, true, nullptr, stream);
+        OHM_TRY(st);
+        return coef_done(h, slot, stream);
+    }
     for (int k = 0; k < nsweeps; ++k) {
         for (int colour = 0; colour < 2; ++colour) {
             const void *src = colour == 0 ? B : tmp;

@@ -100,7 +100,7 @@ bool valid_opts(const ohm_cn_opts *o)
     return o && o->lambda > 0.0 && o->lambda <= 1.0 && o->rtol > 0.0 && o->max_iters >= 1 && o->nu_pre >= 0 &&
            o->nu_post >= 0 && o->nu_pre + o->nu_post >= 1 && o->n_vcycles >= 1 && (o->cycle == 0 || o->cycle == 1) &&
            (o->outer == 0 || o->outer == 1) && (o->precision == 0 || o->precision == 1) && o->coarse_sweeps >= 0 &&
-           (o->graph == 0 || o->graph == 1);
+           o->nu_coarse >= 0 && (o->graph == 0 || o->graph == 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -207,14 +207,8 @@ struct Solver {
     T *dv(size_t const *arr, int d) const { return at<T>(arr[d]); }
     ohm_status smooth_dense(int d, int n, const int *filter, bool all)
     {
-        for (int k = 0; k < n; ++k)
-            for (int c = 0; c < 2; ++c) {
-                T *src = c == 0 ? dv(P.d_e, d) : dv(P.d_tmp, d);
-                T *dst = c == 0 ? dv(P.d_tmp, d) : dv(P.d_e, d);
-                OHM_TRY(launch_dense_stencil<T>(h, -d, MODE_SMOOTH, src, dv(P.d_rhs, d), dv(P.d_eta, d), lam_dt, dst,
-                                                c, all, filter, st));
-            }
-        return OHM_OK;
+        return launch_dense_smooth<T>(h, -d, dv(P.d_e, d), dv(P.d_tmp, d), dv(P.d_rhs, d), dv(P.d_eta, d), lam_dt, n,
+                                      all, filter, st);
     }
     // coarsest grids at depth d (e_d already zero): dense inverse for small
     // grids, FP-T smoothing sweeps for the others
@@ -250,13 +244,14 @@ struct Solver {
             return OHM_OK;
         }
         const int d = -lev;
-        OHM_TRY(smooth_dense(d, nu1, active, false));
+        const int nuc1 = o->nu_coarse > 0 ? o->nu_coarse : nu1, nuc2 = o->nu_coarse > 0 ? o->nu_coarse : nu2;
+        OHM_TRY(smooth_dense(d, nuc1, active, false));
         OHM_TRY(launch_dense_stencil<T>(h, -d, MODE_RESID, dv(P.d_e, d), dv(P.d_rhs, d), dv(P.d_eta, d), lam_dt,
                                         dv(P.d_res, d), 0, false, active, st));
         OHM_TRY(launch_dense_restrict<T>(h, -d, dv(P.d_res, d), dv(P.d_rhs, d + 1), 3, active, st));
         OHM_TRY(down_dense(d + 1));
         OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), dv(P.d_e, d + 1), dv(P.d_e, d), 3, 1, active, st));
-        OHM_TRY(smooth_dense(d, nu2, active, false));
+        OHM_TRY(smooth_dense(d, nuc2, active, false));
         return OHM_OK;
     }
     // enter dense depth d with its rhs set: zero guess, coarsest solves for the
@@ -689,6 +684,7 @@ void ohm_cn_default_opts(ohm_cn_opts *o)
     o->outer = 1;
     o->precision = 0;
     o->coarse_sweeps = 16;
+    o->nu_coarse = 0;
     o->graph = 1;
 }
 

@@ -86,6 +86,12 @@ struct DenseLevelDev {
     int *tiles = nullptr;      // [ntile][2]: problem, first cell
     int ntile_all = 0;         // tiles of every problem present
     int *tiles_all = nullptr;
+    // smoothing: 8^3 tiles (fused sweeps) of problems whose grid is a whole
+    // number of tiles, 256-cell tiles (two half-sweeps) of the others;
+    // "all" variants cover every problem present, the others the problems
+    // that are not coarsest here
+    int nftile = 0, nftile_all = 0, nptile = 0, nptile_all = 0;
+    int *ftiles = nullptr, *ftiles_all = nullptr, *ptiles = nullptr, *ptiles_all = nullptr;
     DenseProbDev *probs = nullptr;   // [nprob] (nx = 0 if the problem lacks the level)
 };
 
@@ -196,6 +202,9 @@ ohm_status launch_prolong_blk(const ohm_hier *h, int coarse_level, const T *coar
                               long long fcs, int ncomp, int accumulate, const int *active, hipStream_t s);
 
 // dense multigrid levels (k_dense.hip)
+template <typename T>
+ohm_status launch_dense_smooth(const ohm_hier *h, int level, T *B, T *tmp, const T *S, const T *eta,
+                               const double *coef_dev, int nsweeps, bool all, const int *active, hipStream_t s);
 template <typename T>
 ohm_status launch_dense_restrict(const ohm_hier *h, int fine_level, const T *fine, T *coarse, int ncomp,
                                  const int *active, hipStream_t s);

@@ -381,7 +381,7 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
         DenseLevelDev &D = H->dense[dd];
         D.ncells = (int)H->dense_cells[dd];
         std::vector<DenseProbDev> dp(nprob);
-        std::vector<int> tiles, tiles_all;
+        std::vector<int> tiles, tiles_all, ft, ft_all, pt, pt_all;
         for (int p = 0; p < nprob; ++p) {
             ohm_prob_host &P = H->probs[p];
             DenseProbDev &q = dp[p];
@@ -395,6 +395,7 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
             double h = P.dx0 * (double)(1 << dd);
             q.inv_h2 = 1.0 / (h * h);
             int nc = q.nx * q.ny * q.nz;
+            const bool tiled = q.nx % NB == 0 && q.ny % NB == 0 && q.nz % NB == 0;
             for (int s = 0; s < nc; s += 256) {
                 tiles_all.push_back(p);
                 tiles_all.push_back(s);
@@ -402,12 +403,37 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
                     tiles.push_back(p);
                     tiles.push_back(s);
                 }
+                if (!tiled) {
+                    pt_all.push_back(p);
+                    pt_all.push_back(s);
+                    if (q.active) {
+                        pt.push_back(p);
+                        pt.push_back(s);
+                    }
+                }
             }
+            if (tiled)
+                for (int t = 0; t < nc / NC; ++t) {
+                    ft_all.push_back(p);
+                    ft_all.push_back(t);
+                    if (q.active) {
+                        ft.push_back(p);
+                        ft.push_back(t);
+                    }
+                }
         }
         D.ntile = (int)tiles.size() / 2;
         D.ntile_all = (int)tiles_all.size() / 2;
         OHM_TRY(upload(&D.tiles, tiles));
         OHM_TRY(upload(&D.tiles_all, tiles_all));
+        D.nftile = (int)ft.size() / 2;
+        D.nftile_all = (int)ft_all.size() / 2;
+        D.nptile = (int)pt.size() / 2;
+        D.nptile_all = (int)pt_all.size() / 2;
+        OHM_TRY(upload(&D.ftiles, ft));
+        OHM_TRY(upload(&D.ftiles_all, ft_all));
+        OHM_TRY(upload(&D.ptiles, pt));
+        OHM_TRY(upload(&D.ptiles_all, pt_all));
         OHM_TRY(upload(&D.probs, dp));
     }
     // ---- scratch ---------------------------------------------------------------
@@ -435,7 +461,7 @@ static void free_all(ohm_hier *H)
     }
     for (int d = 0; d < 16; ++d) {
         DenseLevelDev &D = H->dense[d];
-        void *ptrs[] = {D.tiles, D.tiles_all, D.probs};
+        void *ptrs[] = {D.tiles, D.tiles_all, D.probs, D.ftiles, D.ftiles_all, D.ptiles, D.ptiles_all};
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
     }

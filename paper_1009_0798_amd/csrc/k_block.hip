@@ -4,6 +4,7 @@
 // refluxing and per-problem norm reductions.
 #include "common.h"
 #include "stencil.h"
+#include "sweep.h"
 
 namespace ohm {
 
@@ -128,21 +129,19 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Fused red-black sweep: one launch per sweep.  The block and a two-cell halo
-// are staged in LDS; the red half-sweep is computed on the block and,
-// redundantly, on the red cells of the first halo layer that face the block
-// (their neighbours' values come from the second layer), then the black
-// half-sweep on the block reads those updated red values.  Same arithmetic as
-// two launches of k_blk_stencil<SMOOTH>; needs every face, edge and corner
-// neighbour to be a level block (levels without coarse-fine ghosts).
+// Fused red-black sweep on the blocks of a level whose blocks have all 26
+// neighbours (the tile body is in sweep.h, shared with the dense levels)
 // ---------------------------------------------------------------------------
-constexpr int TW2 = NB + 4;              // tile edge with a two-cell halo
-constexpr int TC2 = TW2 * TW2 * TW2;
-
-template <typename T>
-__device__ __forceinline__ int tix2(int x, int y, int z) { return (x + 2) + TW2 * ((y + 2) + TW2 * (z + 2)); }
-
-constexpr int SWEEP_THREADS = 512;
+struct BlockAddr {
+    const int *nbr;   // 27 neighbour entries of the block (LDS)
+    int b;
+    __device__ __forceinline__ long long at(int x, int y, int z) const
+    {
+        const int sx = side(x), sy = side(y), sz = side(z);
+        const int n = nbr[(sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
+        return (long long)n * NC + (x - NB * sx) + NB * ((y - NB * sy) + NB * (z - NB * sz));
+    }
+};
 
 template <typename T>
 __global__ void __launch_bounds__(SWEEP_THREADS)
@@ -159,85 +158,8 @@ k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ p
     if (active && !active[pr]) return;
     if (threadIdx.x < 27) snbr[threadIdx.x] = nbr_tab[27 * (long long)b + threadIdx.x];
     __syncthreads();
-    for (int t = threadIdx.x; t < TC2; t += SWEEP_THREADS) {
-        const int x = t % TW2 - 2, y = (t / TW2) % TW2 - 2, z = t / (TW2 * TW2) - 2;
-        const int sx = side(x), sy = side(y), sz = side(z);
-        const int n = snbr[(sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
-        const int li = (x - NB * sx) + NB * ((y - NB * sy) + NB * (z - NB * sz));
-        const long long gi = (long long)n * NC + li;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) sB[c][t] = B[c * cs + gi];
-        sE[t] = eta[gi];
-    }
-    __syncthreads();
-    const T ih2 = T(inv_h2_p[pr]);
-    const T coef = T(coef_p[pr]);
-    const T cih2 = coef * ih2;
-    // red half-sweep: thread u < 256 takes block cell u of the red colour,
-    // 256 <= u < 448 a red first-layer face cell
-    T red[3];
-    int rp = -1;
-    {
-        const int u = threadIdx.x;
-        if (u < 448) {
-            int x, y, z;
-            if (u < 256) {
-                z = u >> 5;
-                y = (u >> 2) & 7;
-                x = 2 * (u & 3) + ((y + z) & 1);
-            } else {
-                const int v = u - 256, f = v >> 5, w = v & 31;
-                const int d = f >> 1, s = (f & 1) ? NB : -1;
-                const int bb = w >> 2, a = 2 * (w & 3) + ((s + bb) & 1);
-                if (d == 0) { x = s; y = a; z = bb; }
-                else if (d == 1) { x = a; y = s; z = bb; }
-                else { x = a; y = bb; z = s; }
-            }
-            const int p = tix2<T>(x, y, z);
-            rp = p;
-            const int sx = side(x), sy = side(y), sz = side(z);
-            const int n = snbr[(sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
-            const long long gi = (long long)n * NC + (x - NB * sx) + NB * ((y - NB * sy) + NB * (z - NB * sz));
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const T LB = sB[c][p] + cih2 * divF_cube<T, TW2>(sB[0], sB[1], sB[2], sE, p, c);
-                red[c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * alpha_cube<T, TW2>(sE, p, c));
-            }
-        }
-    }
-    __syncthreads();
-    if (rp >= 0)
-#pragma unroll
-        for (int c = 0; c < 3; ++c) sB[c][rp] = red[c];
-    __syncthreads();
-    // black half-sweep on the block cells (threads 0..255)
-    {
-        const int u = threadIdx.x;
-        T blk[3];
-        int p = -1;
-        if (u < 256) {
-            const int z = u >> 5, y = (u >> 2) & 7, x = 2 * (u & 3) + (1 - ((y + z) & 1));
-            p = tix2<T>(x, y, z);
-            const long long gi = (long long)b * NC + x + NB * (y + NB * z);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const T LB = sB[c][p] + cih2 * divF_cube<T, TW2>(sB[0], sB[1], sB[2], sE, p, c);
-                blk[c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * alpha_cube<T, TW2>(sE, p, c));
-            }
-        }
-        __syncthreads();
-        if (p >= 0)
-#pragma unroll
-            for (int c = 0; c < 3; ++c) sB[c][p] = blk[c];
-    }
-    __syncthreads();
-    {
-        const int cell = threadIdx.x;
-        const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
-        const int p = tix2<T>(x, y, z);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) out[c * cs + (long long)b * NC + cell] = sB[c][p];
-    }
+    const BlockAddr A{snbr, b};
+    fused_sweep_tile<T>(A, B, cs, S, eta, out, T(coef_p[pr]) * T(inv_h2_p[pr]), sB, sE);
 }
 
 // ---------------------------------------------------------------------------

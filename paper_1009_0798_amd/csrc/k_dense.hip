@@ -3,6 +3,7 @@
 // solve (per-problem dense FP64 inverse built on the device).
 #include "common.h"
 #include "stencil.h"
+#include "sweep.h"
 
 namespace ohm {
 
@@ -65,6 +66,56 @@ k_dense_stencil(const int *__restrict__ tiles, const DenseProbDev *__restrict__ 
                 v += (S[c * cs + gi] - LB) / (T(1) + coef * ih2 * alpha_cube<T, 3>(e, 13, c));
             out[c * cs + gi] = v;
         }
+    }
+}
+
+// fused red-black sweep on 8^3 tiles of a dense level (periodic wrap)
+struct DenseAddr {
+    DenseProbDev q;
+    int ox, oy, oz;
+    __device__ __forceinline__ long long at(int x, int y, int z) const
+    {
+        int i = ox + x, j = oy + y, k = oz + z;
+        i = i < 0 ? i + q.nx : (i >= q.nx ? i - q.nx : i);
+        j = j < 0 ? j + q.ny : (j >= q.ny ? j - q.ny : j);
+        k = k < 0 ? k + q.nz : (k >= q.nz ? k - q.nz : k);
+        return q.off + i + (long long)q.nx * (j + (long long)q.ny * k);
+    }
+};
+
+__device__ __forceinline__ DenseAddr dense_tile(const DenseProbDev &q, int t)
+{
+    const int tx = q.nx >> 3, ty = q.ny >> 3;
+    return DenseAddr{q, 8 * (t % tx), 8 * ((t / tx) % ty), 8 * (t / (tx * ty))};
+}
+
+template <typename T>
+__global__ void __launch_bounds__(SWEEP_THREADS)
+k_dense_sweep(const int *__restrict__ ftiles, const DenseProbDev *__restrict__ dp, const int *__restrict__ active,
+              const double *__restrict__ coef_p, const T *__restrict__ B, long long cs, const T *__restrict__ S,
+              const T *__restrict__ eta, T *__restrict__ out)
+{
+    __shared__ T sB[3][TC2];
+    __shared__ T sE[TC2];
+    const int pr = ftiles[2 * blockIdx.x], t = ftiles[2 * blockIdx.x + 1];
+    if (active && !active[pr]) return;
+    const DenseProbDev q = dp[pr];
+    const DenseAddr A = dense_tile(q, t);
+    fused_sweep_tile<T>(A, B, cs, S, eta, out, T(coef_p[pr]) * T(q.inv_h2), sB, sE);
+}
+
+// copy the cells of the listed 8^3 tiles (3 components)
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_dense_tile_copy(const int *__restrict__ ftiles, const DenseProbDev *__restrict__ dp, const int *__restrict__ active,
+                  const T *__restrict__ src, T *__restrict__ dst, long long cs)
+{
+    const int pr = ftiles[2 * blockIdx.x], t = ftiles[2 * blockIdx.x + 1];
+    if (active && !active[pr]) return;
+    const DenseAddr A = dense_tile(dp[pr], t);
+    for (int cell = threadIdx.x; cell < 512; cell += 256) {
+        const long long gi = A.at(cell & 7, (cell >> 3) & 7, cell >> 6);
+        for (int c = 0; c < 3; ++c) dst[c * cs + gi] = src[c * cs + gi];
     }
 }
 
@@ -234,9 +285,11 @@ k_coarse_invert(const CoarseJob *__restrict__ jobs, const int *__restrict__ flag
         }
         __syncthreads();
     }
+    // stored transposed: X[c][r] = inverse[r][c], so that the mat-vec reads
+    // consecutive rows with consecutive lanes
     double *X = inv + J.inv_off;
     for (int r = ty; r < n; r += 32)
-        for (int c = tx; c < n; c += 32) X[r * n + c] = A[r * w + n + c];
+        for (int c = tx; c < n; c += 32) X[c * n + r] = A[r * w + n + c];
 }
 
 template <typename T>
@@ -253,8 +306,7 @@ k_coarse_apply(const CoarseJob *__restrict__ jobs, const int *__restrict__ activ
     __syncthreads();
     for (int row = threadIdx.x; row < n; row += blockDim.x) {
         double s = 0.0;
-        const double *xr = X + (long long)row * n;
-        for (int c = 0; c < n; ++c) s += xr[c] * sr[c];
+        for (int c = 0; c < n; ++c) s += X[(long long)c * n + row] * sr[c];
         e[(row / cells) * cs + J.q.off + row % cells] = (T)s;
     }
 }
@@ -285,6 +337,41 @@ ohm_status launch_dense_stencil(const ohm_hier *h, int level, int mode, const T 
         k_dense_stencil<T, MODE_SMOOTH><<<nt, 256, 0, s>>>(tl, D.probs, active, coef_dev, B, S, eta, out, cs, colour);
     }
     return check_launch("dense stencil");
+}
+
+// nsweeps red-black sweeps of dense level `level`: B holds the start and the
+// result, tmp is scratch of the same size.  Problems whose grid is a whole
+// number of 8^3 tiles get one fused launch per sweep, the others two
+// half-sweep launches.  all = every problem present, else the problems that
+// are not coarsest at this level.
+template <typename T>
+ohm_status launch_dense_smooth(const ohm_hier *h, int level, T *B, T *tmp, const T *S, const T *eta,
+                               const double *coef_dev, int nsweeps, bool all, const int *active, hipStream_t s)
+{
+    const DenseLevelDev &D = h->dense[-level];
+    const long long cs = D.ncells;
+    const int nft = all ? D.nftile_all : D.nftile, npt = all ? D.nptile_all : D.nptile;
+    const int *ft = all ? D.ftiles_all : D.ftiles, *pt = all ? D.ptiles_all : D.ptiles;
+    if (nft > 0) {
+        for (int k = 0; k < nsweeps; ++k) {
+            const T *src = (k & 1) ? tmp : B;
+            T *dst = (k & 1) ? B : tmp;
+            k_dense_sweep<T><<<nft, SWEEP_THREADS, 0, s>>>(ft, D.probs, active, coef_dev, src, cs, S, eta, dst);
+            OHM_TRY(check_launch("dense fused sweep"));
+        }
+        if (nsweeps & 1) {
+            k_dense_tile_copy<T><<<nft, 256, 0, s>>>(ft, D.probs, active, tmp, B, cs);
+            OHM_TRY(check_launch("dense tile copy"));
+        }
+    }
+    if (npt > 0)
+        for (int k = 0; k < nsweeps; ++k) {
+            k_dense_stencil<T, MODE_SMOOTH><<<npt, 256, 0, s>>>(pt, D.probs, active, coef_dev, B, S, eta, tmp, cs, 0);
+            OHM_TRY(check_launch("dense half-sweep"));
+            k_dense_stencil<T, MODE_SMOOTH><<<npt, 256, 0, s>>>(pt, D.probs, active, coef_dev, tmp, S, eta, B, cs, 1);
+            OHM_TRY(check_launch("dense half-sweep"));
+        }
+    return OHM_OK;
 }
 
 template <typename T>
@@ -439,6 +526,8 @@ ohm_status upload_coarse_jobs(const ohm_hier *h, int depth, void *jobs_dev, int 
 size_t coarse_job_bytes() { return sizeof(CoarseJob); }
 
 #define INST(T)                                                                                                \
+    template ohm_status launch_dense_smooth<T>(const ohm_hier *, int, T *, T *, const T *, const T *,           \
+                                               const double *, int, bool, const int *, hipStream_t);           \
     template ohm_status launch_dense_stencil<T>(const ohm_hier *, int, int, const T *, const T *, const T *,   \
                                                 const double *, T *, int, bool, const int *, hipStream_t);     \
     template ohm_status launch_dense_restrict<T>(const ohm_hier *, int, const T *, T *, int, const int *,      \

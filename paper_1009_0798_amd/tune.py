@@ -20,7 +20,8 @@ from . import Workspace, default_opts, ohm_cn_step
 
 CACHE = os.environ.get("OHM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "ohm_tune.json"))
 
-SWEEPS = [(1, 1), (2, 2), (3, 3)]
+SWEEPS = [(1, 1), (2, 2), (3, 3), (4, 4), (5, 5), (6, 6)]
+COARSE = [0, 1, 2]          # sweeps on the levels below the base grid (0 = same as the base grid)
 CYCLES = [0, 1]
 OUTERS = [1, 0]
 
@@ -52,12 +53,20 @@ def _save(db):
     os.replace(tmp, CACHE)
 
 
-def candidates(precisions=(0, 1)):
-    for (n1, n2), cyc, outer, prec in itertools.product(SWEEPS, CYCLES, OUTERS, precisions):
-        yield dict(nu_pre=n1, nu_post=n2, cycle=cyc, outer=outer, precision=prec)
+def candidates(precisions=(0, 1), quick=False):
+    """Schedules to try.  quick: BiCGStab with V-cycles only (the iterative
+    multigrid of eqs. 16-18 and full multigrid are far slower on every
+    workload measured so far)."""
+    cycles = [0] if quick else CYCLES
+    outers = [1] if quick else OUTERS
+    for (n1, n2), nc, cyc, outer, prec in itertools.product(SWEEPS, COARSE, cycles, outers, precisions):
+        if nc >= n1:
+            continue
+        yield dict(nu_pre=n1, nu_post=n2, nu_coarse=nc, cycle=cyc, outer=outer, precision=prec)
 
 
-def tune(h, B, eta, dt, finest_dx, precisions=(0, 1), rtol=1e-10, use_cache=True, repeats=1, log=None):
+def tune(h, B, eta, dt, finest_dx, precisions=(0, 1), rtol=1e-10, use_cache=True, repeats=1, log=None,
+         quick=False):
     """Return (best option dict, table of (options, seconds, iterations)).
 
     ``B`` and ``eta`` are the per-level tensors of ``ohm_cn_step``; B is copied
@@ -69,7 +78,7 @@ def tune(h, B, eta, dt, finest_dx, precisions=(0, 1), rtol=1e-10, use_cache=True
         return db[key]["best"], db[key]["table"]
     ws = Workspace()
     table = []
-    for cand in candidates(precisions):
+    for cand in candidates(precisions, quick):
         opts = default_opts(rtol=rtol, max_iters=200, **cand)
         Bc = [b.clone() for b in B]
         st, stats = ohm_cn_step(h, Bc, eta, dt, opts, ws)      # warm (graph capture, coarse inverse)

@@ -72,23 +72,26 @@ def test_uniform_apply_residual_smooth(dtype):
         assert np.abs(gotS - exS).max() <= 4 * ns * tol * scale, ns
 
 
-@pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_dense_levels_and_transfers(dtype):
+@pytest.mark.parametrize("dtype,bb", [("f64", (3, 2, 4)), ("f32", (3, 2, 4)), ("f64", (4, 4, 2)), ("f32", (4, 4, 2))])
+def test_dense_levels_and_transfers(dtype, bb):
     """Restriction level 0 -> -1 -> -2, prolongation back, and the stencil
-    calls on the dense levels (box 24 x 16 x 32: coarsenings 12x8x16, 6x4x8,
-    3x2x4)."""
+    calls on the dense levels.  Box 24 x 16 x 32: coarsenings 12x8x16, 6x4x8,
+    3x2x4 (two half-sweep path); box 32 x 32 x 16: level -1 is 16x16x8, a whole
+    number of 8^3 tiles (fused-sweep path)."""
     import torch
     import paper_1009_0798_amd as ohm
-    announce(f"dense levels {dtype}")
-    spec, B, S, eta, h, lam_dt = _setup_uniform(seed=1)
+    announce(f"dense levels {dtype} {bb}")
+    spec, B, S, eta, h, lam_dt = _setup_uniform(bb=bb, seed=1)
     tdt = torch.float64 if dtype == "f64" else torch.float32
     if dtype == "f32":
         B, S, eta = (x.astype(np.float32).astype(np.float64) for x in (B, S, eta))
     tol = 5e-14 if dtype == "f64" else 2e-5
     ijk = spec.levels[0]
     H = hier(spec)
-    assert H.min_level == -3
-    assert H.problem_info(0, -1)[1] == (12, 8, 16) and H.problem_info(0, -3)[1] == (3, 2, 4)
+    n0 = spec.cells(0)
+    assert H.problem_info(0, -1)[1] == tuple(v // 2 for v in n0)
+    if bb == (3, 2, 4):
+        assert H.min_level == -3 and H.problem_info(0, -3)[1] == (3, 2, 4)
     Bt = cuda(dense_to_blocks(B, ijk), tdt)
     c1 = H.field(-1, 3, tdt)
     ohm.ohm_restrict(H, 0, Bt, c1)
