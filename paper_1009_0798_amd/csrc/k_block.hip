@@ -81,9 +81,11 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
         const int p = (x + 1) + TW * ((y + 1) + TW * (z + 1));
         const bool zero = (cov >> ((x >> 2) + 2 * (y >> 2) + 4 * (z >> 2))) & 1;
         const long long gi = (long long)b * NC + cell;
+        T dvs[3], als[3];
+        divF_all<T, TW>(sB[0], sB[1], sB[2], sE[0], p, dvs, als);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            T dv = divF_cube<T, TW>(sB[0], sB[1], sB[2], sE[0], p, c) * ih2;
+            T dv = dvs[c] * ih2;
             T LB = sB[c][p] + coef * dv;
             if (MODE == MODE_APPLY) {
                 out[c * cs + gi] = zero ? T(0) : LB;
@@ -97,7 +99,7 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
                 T v = sB[c][p];
                 if (((x + y + z) & 1) == colour) {
                     T r = S[c * cs + gi] - LB;
-                    v += r / (T(1) + coef * ih2 * alpha_cube<T, TW>(sE[0], p, c));
+                    v += r / (T(1) + coef * ih2 * als[c]);
                 }
                 out[c * cs + gi] = v;
             }

@@ -53,9 +53,11 @@ k_dense_stencil(const int *__restrict__ tiles, const DenseProbDev *__restrict__ 
     const T ih2 = T(q.inv_h2), coef = T(coef_p[pr]);
     const long long gi = q.off + cell;
     const T *bc[3] = {b0, b1, b2};
+    T dvs[3], als[3];
+    divF_all<T, 3>(b0, b1, b2, e, 13, dvs, als);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        T LB = bc[c][13] + coef * ih2 * divF_cube<T, 3>(b0, b1, b2, e, 13, c);
+        T LB = bc[c][13] + coef * ih2 * dvs[c];
         if (MODE == MODE_APPLY) {
             out[c * cs + gi] = LB;
         } else if (MODE == MODE_RESID) {
@@ -63,7 +65,7 @@ k_dense_stencil(const int *__restrict__ tiles, const DenseProbDev *__restrict__ 
         } else {
             T v = bc[c][13];
             if (((i + j + k) & 1) == colour)
-                v += (S[c * cs + gi] - LB) / (T(1) + coef * ih2 * alpha_cube<T, 3>(e, 13, c));
+                v += (S[c * cs + gi] - LB) / (T(1) + coef * ih2 * als[c]);
             out[c * cs + gi] = v;
         }
     }

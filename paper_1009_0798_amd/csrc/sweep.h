@@ -55,10 +55,12 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
             const int p = tix2(x, y, z);
             rp = p;
             const long long gi = A.at(x, y, z);
+            T dv[3], al[3];
+            divF_all<T, TW2>(sB[0], sB[1], sB[2], sE, p, dv, al);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const T LB = sB[c][p] + cih2 * divF_cube<T, TW2>(sB[0], sB[1], sB[2], sE, p, c);
-                red[c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * alpha_cube<T, TW2>(sE, p, c));
+                const T LB = sB[c][p] + cih2 * dv[c];
+                red[c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * al[c]);
             }
         }
     }
@@ -76,10 +78,12 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
             const int z = u >> 5, y = (u >> 2) & 7, x = 2 * (u & 3) + (1 - ((y + z) & 1));
             p = tix2(x, y, z);
             const long long gi = A.at(x, y, z);
+            T dv[3], al[3];
+            divF_all<T, TW2>(sB[0], sB[1], sB[2], sE, p, dv, al);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
-                const T LB = sB[c][p] + cih2 * divF_cube<T, TW2>(sB[0], sB[1], sB[2], sE, p, c);
-                blk[c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * alpha_cube<T, TW2>(sE, p, c));
+                const T LB = sB[c][p] + cih2 * dv[c];
+                blk[c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * al[c]);
             }
         }
         __syncthreads();
