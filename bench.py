@@ -24,14 +24,16 @@ NU_COARSE = 1   # the autotuner picks for this workload on MI355X
 
 
 def sweep_source_hash() -> str:
-    """Hash of the fused-sweep kernel source (and the stencil it uses); the
-    counter traffic recorded under profiles/ is valid only for that source."""
+    """Hash of the fused-sweep kernel source (the block kernel, the tile body
+    and the stencil it uses); the counter traffic recorded under profiles/ is
+    valid only for that source."""
     import hashlib
-    root = os.path.dirname(os.path.abspath(__file__))
-    src = open(os.path.join(root, "paper_1009_0798_amd", "csrc", "k_block.hip")).read()
-    a = src.index("template <typename T>\n__global__ void __launch_bounds__(SWEEP_THREADS)\nk_blk_sweep(")
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1009_0798_amd", "csrc")
+    src = open(os.path.join(csrc, "k_block.hip")).read()
+    a = src.index("k_blk_sweep(")
+    a = src.rindex("template <typename T", 0, a)
     b = src.index("\n}\n", a) + 3
-    body = src[a:b] + open(os.path.join(root, "paper_1009_0798_amd", "csrc", "stencil.h")).read()
+    body = src[a:b] + "".join(open(os.path.join(csrc, f)).read() for f in ("sweep.h", "stencil.h"))
     return hashlib.sha256(body.encode()).hexdigest()[:16]
 
 

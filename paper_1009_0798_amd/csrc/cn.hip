@@ -174,28 +174,40 @@ struct Solver {
     }
 
     // ---- multigrid cycle (precision T) ----------------------------------------
-    ohm_status smooth_blk(int l, int n)
+    // n sweeps on block level l, result in e.  flags as for dense levels:
+    // SMOOTH_ZERO (zero input, not read) or SMOOTH_FROM_TMP (input in tmp)
+    ohm_status smooth_blk(int l, int n, int flags = 0)
     {
+        const bool zero = flags & SMOOTH_ZERO, from_tmp = (flags & SMOOTH_FROM_TMP) && !zero;
+        T *e = mg(P.e, l), *tmp = mg(P.tmp, l);
+        T *cur = from_tmp ? tmp : e;
         if (h->amr[l].complete27 && n > 0) {
-            // fused sweeps, ping-pong e <-> tmp; an odd count ends with a copy
+            // fused sweeps ping-pong e <-> tmp; a zero input is not read, so
+            // the first sweep writes whichever buffer makes the last land in e
             for (int k = 0; k < n; ++k) {
-                T *src = (k & 1) ? mg(P.tmp, l) : mg(P.e, l);
-                T *dst = (k & 1) ? mg(P.e, l) : mg(P.tmp, l);
-                OHM_TRY(launch_blk_sweep<T>(h, l, src, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st));
+                T *dst;
+                if (k == 0 && zero) {
+                    dst = (n & 1) ? e : tmp;
+                    OHM_TRY(launch_blk_sweep<T>(h, l, nullptr, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st));
+                } else {
+                    dst = cur == e ? tmp : e;
+                    OHM_TRY(launch_blk_sweep<T>(h, l, cur, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st));
+                }
+                cur = dst;
             }
-            if (n & 1)
-                for (int c = 0; c < 3; ++c)
-                    OHM_TRY(vconvert<T, T>(mg(P.tmp, l) + c * VN, mg(P.e, l) + c * VN, (long long)h->nb_host[l] * NC, st));
-            return OHM_OK;
+        } else {
+            // two half-sweeps per sweep, each a full out-of-place pass
+            if (zero) OHM_TRY(zero_level(P.e, l));
+            T *oth = cur == e ? tmp : e;
+            for (int k = 0; k < n; ++k)
+                for (int c = 0; c < 2; ++c)
+                    OHM_TRY(launch_blk_stencil<T>(h, l, MODE_SMOOTH, c == 0 ? cur : oth, at<T>(P.mg_g) + P.LG[l] * NC,
+                                                  VN, GN, mg(P.rhs, l), etaT(l), etagT(l), lam_dt, c == 0 ? oth : cur,
+                                                  c, nullptr, nullptr, active, st));
         }
-        for (int k = 0; k < n; ++k)
-            for (int c = 0; c < 2; ++c) {
-                T *src = c == 0 ? mg(P.e, l) : mg(P.tmp, l);
-                T *dst = c == 0 ? mg(P.tmp, l) : mg(P.e, l);
-                OHM_TRY(launch_blk_stencil<T>(h, l, MODE_SMOOTH, src, at<T>(P.mg_g) + P.LG[l] * NC, VN, GN,
-                                              mg(P.rhs, l), etaT(l), etagT(l), lam_dt, dst, c, nullptr, nullptr,
-                                              active, st));
-            }
+        if (cur != e)
+            for (int c = 0; c < 3; ++c)
+                OHM_TRY(vconvert<T, T>(cur + c * VN, e + c * VN, (long long)h->nb_host[l] * NC, st));
         return OHM_OK;
     }
     ohm_status resid_blk(int l)
@@ -205,21 +217,22 @@ struct Solver {
                                      active, st);
     }
     T *dv(size_t const *arr, int d) const { return at<T>(arr[d]); }
-    ohm_status smooth_dense(int d, int n, const int *filter, bool all)
+    ohm_status smooth_dense(int d, int n, const int *filter, bool all, int flags = 0)
     {
         return launch_dense_smooth<T>(h, -d, dv(P.d_e, d), dv(P.d_tmp, d), dv(P.d_rhs, d), dv(P.d_eta, d), lam_dt, n,
-                                      all, filter, st);
+                                      all, filter, st, flags);
     }
-    // coarsest grids at depth d (e_d already zero): dense inverse for small
-    // grids, FP-T smoothing sweeps for the others
+    // coarsest grids at depth d, from a zero guess: dense inverse for small
+    // grids, FP-T smoothing sweeps for the others; writes e_d of every problem
+    // that bottoms out at depth d
     ohm_status coarsest(int d)
     {
         void *jobs = at<char>(P.jobs) + coarse_job_bytes() * (size_t)h->nprob * d;
         if (njobs[d] > 0)
             OHM_TRY(launch_coarse_apply<T>(h, d, jobs, njobs[d], h->d_coarse_inv, dv(P.d_rhs, d), dv(P.d_e, d),
                                            active, st));
-        if (has_big[d] && o->coarse_sweeps > 0)
-            OHM_TRY(smooth_dense(d, o->coarse_sweeps, at<int>(P.cmask) + (size_t)h->nprob * d, true));
+        if (has_big[d])
+            OHM_TRY(smooth_dense(d, o->coarse_sweeps, at<int>(P.cmask) + (size_t)h->nprob * d, true, SMOOTH_ZERO));
         return OHM_OK;
     }
     ohm_status zero_level(size_t off, int l)
@@ -230,37 +243,52 @@ struct Solver {
     std::vector<int> has_big;
 
     // V-cycle on the base stack at level lev (0 or dense -d); e at lev holds
-    // the initial guess (the caller zeroes it for a zero guess)
-    ohm_status vcycle_base(int lev)
+    // the initial guess, or zero_guess says it is zero (and e is not read).
+    // An odd post-smoothing count on fused levels prolongs into tmp
+    // (tmp = e + P e_coarse) so that the sweeps end in e without a copy.
+    ohm_status vcycle_base(int lev, bool zero_guess)
     {
         const int nu1 = o->nu_pre, nu2 = o->nu_post;
+        const int zf = zero_guess ? SMOOTH_ZERO : 0;
         if (lev == 0) {
-            OHM_TRY(smooth_blk(0, nu1));
+            OHM_TRY(smooth_blk(0, nu1, zf));
             OHM_TRY(resid_blk(0));
             OHM_TRY(launch_restrict_blk<T>(h, 0, mg(P.res, 0), VN, dv(P.d_rhs, 1), h->dense_cells[1], 3, active, st));
             OHM_TRY(down_dense(1));
-            OHM_TRY(launch_prolong_blk<T>(h, -1, dv(P.d_e, 1), h->dense_cells[1], mg(P.e, 0), VN, 3, 1, active, st));
-            OHM_TRY(smooth_blk(0, nu2));
+            if ((nu2 & 1) && h->amr[0].complete27) {
+                OHM_TRY(launch_prolong_blk<T>(h, -1, dv(P.d_e, 1), h->dense_cells[1], mg(P.tmp, 0), VN, 3, 1, active,
+                                              st, mg(P.e, 0)));
+                OHM_TRY(smooth_blk(0, nu2, SMOOTH_FROM_TMP));
+            } else {
+                OHM_TRY(launch_prolong_blk<T>(h, -1, dv(P.d_e, 1), h->dense_cells[1], mg(P.e, 0), VN, 3, 1, active, st));
+                OHM_TRY(smooth_blk(0, nu2));
+            }
             return OHM_OK;
         }
         const int d = -lev;
         const int nuc1 = o->nu_coarse > 0 ? o->nu_coarse : nu1, nuc2 = o->nu_coarse > 0 ? o->nu_coarse : nu2;
-        OHM_TRY(smooth_dense(d, nuc1, active, false));
+        OHM_TRY(smooth_dense(d, nuc1, active, false, zf));
         OHM_TRY(launch_dense_stencil<T>(h, -d, MODE_RESID, dv(P.d_e, d), dv(P.d_rhs, d), dv(P.d_eta, d), lam_dt,
                                         dv(P.d_res, d), 0, false, active, st));
         OHM_TRY(launch_dense_restrict<T>(h, -d, dv(P.d_res, d), dv(P.d_rhs, d + 1), 3, active, st));
         OHM_TRY(down_dense(d + 1));
-        OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), dv(P.d_e, d + 1), dv(P.d_e, d), 3, 1, active, st));
-        OHM_TRY(smooth_dense(d, nuc2, active, false));
+        if (nuc2 & 1) {
+            OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), dv(P.d_e, d + 1), dv(P.d_tmp, d), 3, 1, active, st,
+                                            (const T *)dv(P.d_e, d)));
+            OHM_TRY(smooth_dense(d, nuc2, active, false, SMOOTH_FROM_TMP));
+        } else {
+            OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), dv(P.d_e, d + 1), dv(P.d_e, d), 3, 1, active, st));
+            OHM_TRY(smooth_dense(d, nuc2, active, false));
+        }
         return OHM_OK;
     }
-    // enter dense depth d with its rhs set: zero guess, coarsest solves for the
-    // problems bottoming out here, a V-cycle for the others
+    // enter dense depth d with its rhs set: coarsest solves for the problems
+    // bottoming out here, a zero-guess V-cycle for the others (between them
+    // every problem present at depth d has e_d written, so no fill is needed)
     ohm_status down_dense(int d)
     {
-        OHM_TRY(vfill<T>(dv(P.d_e, d), 3 * h->dense_cells[d], T(0), st));
         OHM_TRY(coarsest(d));
-        if (h->dense[d].ntile > 0) OHM_TRY(vcycle_base(-d));
+        if (h->dense[d].ntile > 0) OHM_TRY(vcycle_base(-d, true));
         return OHM_OK;
     }
 
@@ -277,10 +305,10 @@ struct Solver {
         for (int d = D - 1; d >= 1; --d) {
             if (h->dense[d].ntile == 0) continue;
             OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), dv(P.d_e, d + 1), dv(P.d_e, d), 3, 0, active, st));
-            for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(-d));
+            for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(-d, false));
         }
         OHM_TRY(launch_prolong_blk<T>(h, -1, dv(P.d_e, 1), h->dense_cells[1], mg(P.e, 0), VN, 3, 0, active, st));
-        for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(0));
+        for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(0, false));
         return OHM_OK;
     }
 
@@ -303,16 +331,14 @@ struct Solver {
         // restrict the level residual under the finer blocks
         if (L > 1 && P.NGt > 0) OHM_TRY(vfill<T>(at<T>(P.mg_g), 3 * P.NGt * NC, T(0), st));
         for (int l = L - 1; l >= 1; --l) {
-            OHM_TRY(zero_level(P.e, l));
-            OHM_TRY(smooth_blk(l, o->nu_pre));
+            OHM_TRY(smooth_blk(l, o->nu_pre, SMOOTH_ZERO));
             OHM_TRY(resid_blk(l));
             OHM_TRY(launch_restrict_blk<T>(h, l, mg(P.res, l), VN, mg(P.rhs, l - 1), VN, 3, active, st));
         }
         if (o->cycle == 1) {
             OHM_TRY(fmg_base());
         } else {
-            OHM_TRY(zero_level(P.e, 0));
-            for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(0));
+            for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(0, v == 0));
         }
         for (int l = 1; l < L; ++l) {
             OHM_TRY(launch_prolong_blk<T>(h, l - 1, mg(P.e, l - 1), VN, mg(P.e, l), VN, 3, 1, active, st));

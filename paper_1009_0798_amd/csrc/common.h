@@ -160,7 +160,8 @@ ohm_status launch_blk_stencil(const ohm_hier *h, int level, int mode, const T *B
                               const double *coef_dev, T *out, int colour, double *partials,
                               const uint8_t *cov_zero, const int *active, hipStream_t s);
 enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_SMOOTH = 2 };
-// one fused red-black sweep B -> out (levels whose blocks have every neighbour)
+// one fused red-black sweep B -> out (levels whose blocks have every neighbour);
+// B == nullptr sweeps a zero input without reading it
 template <typename T>
 ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long cs, const T *S, const T *eta,
                             const double *coef_dev, T *out, const int *active, hipStream_t s);
@@ -198,19 +199,28 @@ template <typename T>
 ohm_status launch_restrict_blk(const ohm_hier *h, int fine_level, const T *fine, long long fcs, T *coarse,
                                long long ccs, int ncomp, const int *active, hipStream_t s);
 template <typename T>
+// coarse_level -1 (first dense level -> level 0) may write base + P(coarse)
+// into fine (base != fine) instead of accumulating in place
 ohm_status launch_prolong_blk(const ohm_hier *h, int coarse_level, const T *coarse, long long ccs, T *fine,
-                              long long fcs, int ncomp, int accumulate, const int *active, hipStream_t s);
+                              long long fcs, int ncomp, int accumulate, const int *active, hipStream_t s,
+                              const T *base = nullptr);
 
 // dense multigrid levels (k_dense.hip)
+// nsweeps fused or two-pass sweeps; the result is always left in B.  flags:
+// SMOOTH_ZERO: the input is zero and is not read; SMOOTH_FROM_TMP: the input
+// is in tmp rather than B.  Sweep parities are arranged so that the fused
+// tiles need no final copy when the count allows it.
+enum { SMOOTH_ZERO = 1, SMOOTH_FROM_TMP = 2 };
 template <typename T>
 ohm_status launch_dense_smooth(const ohm_hier *h, int level, T *B, T *tmp, const T *S, const T *eta,
-                               const double *coef_dev, int nsweeps, bool all, const int *active, hipStream_t s);
+                               const double *coef_dev, int nsweeps, bool all, const int *active, hipStream_t s,
+                               int flags = 0);
 template <typename T>
 ohm_status launch_dense_restrict(const ohm_hier *h, int fine_level, const T *fine, T *coarse, int ncomp,
                                  const int *active, hipStream_t s);
 template <typename T>
 ohm_status launch_dense_prolong(const ohm_hier *h, int coarse_level, const T *coarse, T *fine, int ncomp,
-                                int accumulate, const int *active, hipStream_t s);
+                                int accumulate, const int *active, hipStream_t s, const T *base = nullptr);
 ohm_status coarse_sizes(const ohm_hier *h, size_t *inv_elems, size_t *aug_elems);
 size_t coarse_job_bytes();
 size_t coarse_job_count(const ohm_hier *h, int depth);

@@ -70,8 +70,8 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
     load_tile<T, 3>(sB, B, Bg, cs, gcs, snbr);
     load_tile<T, 1>(sE, eta, etag, 0, 0, snbr);
     __syncthreads();
-    const T ih2 = T(inv_h2_p[pr]);
-    const T coef = T(coef_p[pr]);
+    const T cih2 = T(coef_p[pr]) * T(inv_h2_p[pr]);
+    const T c8 = cih2 * T(0.125), c2 = cih2 * T(0.5);
     const uint8_t cov = cov_zero ? cov_zero[b] : 0;
     double ss[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
 #pragma unroll
@@ -85,8 +85,7 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
         divF_all<T, TW>(sB[0], sB[1], sB[2], sE[0], p, dvs, als);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            T dv = dvs[c] * ih2;
-            T LB = sB[c][p] + coef * dv;
+            const T LB = fma(c8, dvs[c], sB[c][p]);
             if (MODE == MODE_APPLY) {
                 out[c * cs + gi] = zero ? T(0) : LB;
             } else if (MODE == MODE_RESID) {
@@ -97,10 +96,7 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
                 mx[c] = fmax(mx[c], fabs(rd));
             } else {  // smoother half-sweep
                 T v = sB[c][p];
-                if (((x + y + z) & 1) == colour) {
-                    T r = S[c * cs + gi] - LB;
-                    v += r / (T(1) + coef * ih2 * als[c]);
-                }
+                if (((x + y + z) & 1) == colour) v = relax_point(v, S[c * cs + gi], dvs[c], als[c], c8, c2);
                 out[c * cs + gi] = v;
             }
         }
@@ -145,7 +141,7 @@ struct BlockAddr {
     }
 };
 
-template <typename T>
+template <typename T, bool ZERO>
 __global__ void __launch_bounds__(SWEEP_THREADS)
 k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ prob_of,
             const int *__restrict__ active, const double *__restrict__ inv_h2_p, const double *__restrict__ coef_p,
@@ -161,7 +157,7 @@ k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ p
     if (threadIdx.x < 27) snbr[threadIdx.x] = nbr_tab[27 * (long long)b + threadIdx.x];
     __syncthreads();
     const BlockAddr A{snbr, b};
-    fused_sweep_tile<T>(A, B, cs, S, eta, out, T(coef_p[pr]) * T(inv_h2_p[pr]), sB, sE);
+    fused_sweep_tile<T, ZERO>(A, B, cs, S, eta, out, T(coef_p[pr]) * T(inv_h2_p[pr]), sB, sE);
 }
 
 // ---------------------------------------------------------------------------
@@ -262,7 +258,7 @@ k_prolong_blk(int nfine, const int *__restrict__ parent, const int *__restrict__
             T v = T(27) * C[p0] + T(9) * (C[p0 + qx] + C[p0 + qy] + C[p0 + qz]) +
                   T(3) * (C[p0 + qx + qy] + C[p0 + qx + qz] + C[p0 + qy + qz]) + C[p0 + qx + qy + qz];
             v *= T(1.0 / 64.0);
-            long long gi = c * fcs + (long long)b * NC + cell;
+            const long long gi = c * fcs + (long long)b * NC + cell;
             fine[gi] = accumulate ? fine[gi] + v : v;
         }
     }
@@ -272,8 +268,8 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 k_prolong_dense_blk0(int nblk, const int *__restrict__ ijk, const int *__restrict__ prob_of,
                      const DenseProbDev *__restrict__ dp, const int *__restrict__ active,
-                     const T *__restrict__ coarse, long long ccs, T *__restrict__ fine, long long fcs,
-                     int ncomp, int accumulate)
+                     const T *__restrict__ coarse, long long ccs, const T *base, T *fine, long long fcs,
+                     int ncomp)
 {
     const int b = xcd_block(blockIdx.x, nblk);
     const int pr = prob_of[b];
@@ -292,8 +288,8 @@ k_prolong_dense_blk0(int nblk, const int *__restrict__ ijk, const int *__restric
             T v = T(27) * C[at(i, j, k)] + T(9) * (C[at(i1, j, k)] + C[at(i, j1, k)] + C[at(i, j, k1)]) +
                   T(3) * (C[at(i1, j1, k)] + C[at(i1, j, k1)] + C[at(i, j1, k1)]) + C[at(i1, j1, k1)];
             v *= T(1.0 / 64.0);
-            long long gi = c * fcs + (long long)b * NC + cell;
-            fine[gi] = accumulate ? fine[gi] + v : v;
+            const long long gi = c * fcs + (long long)b * NC + cell;
+            fine[gi] = base ? base[gi] + v : v;
         }
     }
 }
@@ -476,7 +472,12 @@ ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long 
     const AmrLevelDev &L = h->amr[level];
     if (L.nb == 0) return OHM_OK;
     if (!L.complete27) return fail(OHM_ERR_ARG, "fused sweep needs every neighbour block of level %d", level);
-    k_blk_sweep<T><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta, out);
+    if (B)
+        k_blk_sweep<T, false><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S,
+                                                             eta, out);
+    else
+        k_blk_sweep<T, true><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S,
+                                                            eta, out);
     return check_launch("fused sweep");
 }
 
@@ -499,9 +500,11 @@ ohm_status launch_restrict_blk(const ohm_hier *h, int fine_level, const T *fine,
 
 template <typename T>
 ohm_status launch_prolong_blk(const ohm_hier *h, int coarse_level, const T *coarse, long long ccs, T *fine,
-                              long long fcs, int ncomp, int accumulate, const int *active, hipStream_t s)
+                              long long fcs, int ncomp, int accumulate, const int *active, hipStream_t s,
+                              const T *base)
 {
     if (coarse_level >= 0) {
+        if (base) return fail(OHM_ERR_ARG, "prolongation between block levels is in place");
         const AmrLevelDev &F = h->amr[coarse_level + 1];
         if (F.nb == 0) return OHM_OK;
         k_prolong_blk<T><<<F.nb, 256, 0, s>>>(F.nb, F.parent, F.octant, F.prob, active, h->amr[coarse_level].nbr,
@@ -509,8 +512,10 @@ ohm_status launch_prolong_blk(const ohm_hier *h, int coarse_level, const T *coar
         return check_launch("prolong");
     }
     const AmrLevelDev &L = h->amr[0];
-    k_prolong_dense_blk0<T><<<L.nb, 256, 0, s>>>(L.nb, L.ijk, L.prob, h->dense[1].probs, active, coarse, ccs, fine,
-                                                 fcs, ncomp, accumulate);
+    if (base && !accumulate) return fail(OHM_ERR_ARG, "prolongation onto a base field must accumulate");
+    if (accumulate && !base) base = fine;
+    k_prolong_dense_blk0<T><<<L.nb, 256, 0, s>>>(L.nb, L.ijk, L.prob, h->dense[1].probs, active, coarse, ccs, base,
+                                                 fine, fcs, ncomp);
     return check_launch("prolong from dense");
 }
 
@@ -562,7 +567,7 @@ ohm_status launch_reduce_problem(int nprob, int nrange, const long long *range_d
     template ohm_status launch_restrict_blk<T>(const ohm_hier *, int, const T *, long long, T *, long long, int, \
                                                const int *, hipStream_t);                                       \
     template ohm_status launch_prolong_blk<T>(const ohm_hier *, int, const T *, long long, T *, long long, int,  \
-                                              int, const int *, hipStream_t);                                   \
+                                              int, const int *, hipStream_t, const T *);                        \
     template ohm_status launch_fill_ghosts<T>(const ohm_hier *, int, const T *, long long, T *, long long, int,  \
                                               const int *, hipStream_t);                                        \
     template ohm_status launch_reflux<T>(const ohm_hier *, int, const T *, long long, const T *, const T *,      \

@@ -50,22 +50,22 @@ k_dense_stencil(const int *__restrict__ tiles, const DenseProbDev *__restrict__ 
     gather<T>(q, i, j, k, b1, [&](long long x) { return B[cs + x]; });
     gather<T>(q, i, j, k, b2, [&](long long x) { return B[2 * cs + x]; });
     gather<T>(q, i, j, k, e, [&](long long x) { return eta[x]; });
-    const T ih2 = T(q.inv_h2), coef = T(coef_p[pr]);
+    const T cih2 = T(coef_p[pr]) * T(q.inv_h2);
+    const T c8 = cih2 * T(0.125), c2 = cih2 * T(0.5);
     const long long gi = q.off + cell;
     const T *bc[3] = {b0, b1, b2};
     T dvs[3], als[3];
     divF_all<T, 3>(b0, b1, b2, e, 13, dvs, als);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        T LB = bc[c][13] + coef * ih2 * dvs[c];
+        const T LB = fma(c8, dvs[c], bc[c][13]);
         if (MODE == MODE_APPLY) {
             out[c * cs + gi] = LB;
         } else if (MODE == MODE_RESID) {
             out[c * cs + gi] = S[c * cs + gi] - LB;
         } else {
             T v = bc[c][13];
-            if (((i + j + k) & 1) == colour)
-                v += (S[c * cs + gi] - LB) / (T(1) + coef * ih2 * als[c]);
+            if (((i + j + k) & 1) == colour) v = relax_point(v, S[c * cs + gi], dvs[c], als[c], c8, c2);
             out[c * cs + gi] = v;
         }
     }
@@ -91,7 +91,7 @@ __device__ __forceinline__ DenseAddr dense_tile(const DenseProbDev &q, int t)
     return DenseAddr{q, 8 * (t % tx), 8 * ((t / tx) % ty), 8 * (t / (tx * ty))};
 }
 
-template <typename T>
+template <typename T, bool ZERO>
 __global__ void __launch_bounds__(SWEEP_THREADS)
 k_dense_sweep(const int *__restrict__ ftiles, const DenseProbDev *__restrict__ dp, const int *__restrict__ active,
               const double *__restrict__ coef_p, const T *__restrict__ B, long long cs, const T *__restrict__ S,
@@ -103,10 +103,10 @@ k_dense_sweep(const int *__restrict__ ftiles, const DenseProbDev *__restrict__ d
     if (active && !active[pr]) return;
     const DenseProbDev q = dp[pr];
     const DenseAddr A = dense_tile(q, t);
-    fused_sweep_tile<T>(A, B, cs, S, eta, out, T(coef_p[pr]) * T(q.inv_h2), sB, sE);
+    fused_sweep_tile<T, ZERO>(A, B, cs, S, eta, out, T(coef_p[pr]) * T(q.inv_h2), sB, sE);
 }
 
-// copy the cells of the listed 8^3 tiles (3 components)
+// copy (src != nullptr) or zero the cells of the listed 8^3 tiles (3 components)
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_dense_tile_copy(const int *__restrict__ ftiles, const DenseProbDev *__restrict__ dp, const int *__restrict__ active,
@@ -117,8 +117,23 @@ k_dense_tile_copy(const int *__restrict__ ftiles, const DenseProbDev *__restrict
     const DenseAddr A = dense_tile(dp[pr], t);
     for (int cell = threadIdx.x; cell < 512; cell += 256) {
         const long long gi = A.at(cell & 7, (cell >> 3) & 7, cell >> 6);
-        for (int c = 0; c < 3; ++c) dst[c * cs + gi] = src[c * cs + gi];
+        for (int c = 0; c < 3; ++c) dst[c * cs + gi] = src ? src[c * cs + gi] : T(0);
     }
+}
+
+// the same over 256-cell runs (prob, first cell) of a problem
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_dense_run_copy(const int *__restrict__ runs, const DenseProbDev *__restrict__ dp, const int *__restrict__ active,
+                 const T *__restrict__ src, T *__restrict__ dst, long long cs)
+{
+    const int pr = runs[2 * blockIdx.x], start = runs[2 * blockIdx.x + 1];
+    if (active && !active[pr]) return;
+    const DenseProbDev q = dp[pr];
+    const int cell = start + threadIdx.x;
+    if (cell >= q.nx * q.ny * q.nz) return;
+    const long long gi = q.off + cell;
+    for (int c = 0; c < 3; ++c) dst[c * cs + gi] = src ? src[c * cs + gi] : T(0);
 }
 
 // dense level -d -> -(d+1): mean of 8 children; one thread per coarse cell
@@ -149,7 +164,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 k_dense_prolong(const int *__restrict__ ftiles, const DenseProbDev *__restrict__ fdp,
                 const DenseProbDev *__restrict__ cdp, const int *__restrict__ active, const T *__restrict__ coarse,
-                long long ccs, T *__restrict__ fine, long long fcs, int ncomp, int accumulate)
+                long long ccs, const T *base, T *fine, long long fcs, int ncomp)
 {
     const int pr = ftiles[2 * blockIdx.x], start = ftiles[2 * blockIdx.x + 1];
     if (active && !active[pr]) return;
@@ -167,7 +182,7 @@ k_dense_prolong(const int *__restrict__ ftiles, const DenseProbDev *__restrict__
               T(3) * (C[at(i1, j1, k)] + C[at(i1, j, k1)] + C[at(i, j1, k1)]) + C[at(i1, j1, k1)];
         v *= T(1.0 / 64.0);
         const long long gi = m * fcs + f.off + cell;
-        fine[gi] = accumulate ? fine[gi] + v : v;
+        fine[gi] = base ? base[gi] + v : v;
     }
 }
 
@@ -205,7 +220,9 @@ k_coarse_assemble(const CoarseJob *__restrict__ jobs, const int *__restrict__ fl
         for (int m = 0; m < 3; ++m)
             gather<double>(J.q, i, j, k, b[m], [&](long long x) { return (m == cj && x == J.q.off + qj) ? 1.0 : 0.0; });
         gather<double>(J.q, i, j, k, e, [&](long long x) { return eta[x]; });
-        double v = b[cr][13] + J.lam_dt * J.q.inv_h2 * divF_cube<double, 3>(b[0], b[1], b[2], e, 13, cr);
+        double dvs[3], als[3];
+        divF_all<double, 3>(b[0], b[1], b[2], e, 13, dvs, als);
+        const double v = fma(J.lam_dt * J.q.inv_h2 * 0.125, dvs[cr], b[cr][13]);
         A[(long long)row * 2 * J.n3 + col] = v;
         A[(long long)row * 2 * J.n3 + J.n3 + col] = (row == col) ? 1.0 : 0.0;
     }
@@ -295,21 +312,37 @@ k_coarse_invert(const CoarseJob *__restrict__ jobs, const int *__restrict__ flag
 }
 
 template <typename T>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 k_coarse_apply(const CoarseJob *__restrict__ jobs, const int *__restrict__ active, const double *__restrict__ inv,
                const T *__restrict__ r, T *__restrict__ e, long long cs)
 {
-    const CoarseJob J = jobs[blockIdx.x];
+    // workgroup (x, job): rows 64 x .. 64 x + 63 of the job's inverse; each of
+    // the 8 wavefronts sums one contiguous slice of the columns, the slices are
+    // then added in a fixed order
+    const CoarseJob J = jobs[blockIdx.y];
     if (active && !active[J.prob]) return;
     const int n = J.n3, cells = n / 3;
-    const double *X = inv + J.inv_off;
-    __shared__ double sr[768];
+    const int row0 = 64 * blockIdx.x;
+    if (row0 >= n) return;
+    __shared__ double sr[COARSE_MAX_DEV];
+    __shared__ double part[8][64];
     for (int t = threadIdx.x; t < n; t += blockDim.x) sr[t] = (double)r[(t / cells) * cs + J.q.off + t % cells];
     __syncthreads();
-    for (int row = threadIdx.x; row < n; row += blockDim.x) {
-        double s = 0.0;
-        for (int c = 0; c < n; ++c) s += X[(long long)c * n + row] * sr[c];
-        e[(row / cells) * cs + J.q.off + row % cells] = (T)s;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int row = row0 + lane;
+    const double *X = inv + J.inv_off;
+    const int per = (n + 7) / 8, c0 = w * per, c1 = min(n, c0 + per);
+    double acc = 0.0;
+    if (row < n) {
+#pragma unroll 8
+        for (int c = c0; c < c1; ++c) acc = fma(X[(long long)c * n + row], sr[c], acc);
+    }
+    part[w][lane] = acc;
+    __syncthreads();
+    if (w == 0 && row < n) {
+        double v = part[0][lane];
+        for (int k = 1; k < 8; ++k) v += part[k][lane];
+        e[(row / cells) * cs + J.q.off + row % cells] = (T)v;
     }
 }
 
@@ -348,31 +381,60 @@ ohm_status launch_dense_stencil(const ohm_hier *h, int level, int mode, const T 
 // are not coarsest at this level.
 template <typename T>
 ohm_status launch_dense_smooth(const ohm_hier *h, int level, T *B, T *tmp, const T *S, const T *eta,
-                               const double *coef_dev, int nsweeps, bool all, const int *active, hipStream_t s)
+                               const double *coef_dev, int nsweeps, bool all, const int *active, hipStream_t s,
+                               int flags)
 {
     const DenseLevelDev &D = h->dense[-level];
     const long long cs = D.ncells;
     const int nft = all ? D.nftile_all : D.nftile, npt = all ? D.nptile_all : D.nptile;
     const int *ft = all ? D.ftiles_all : D.ftiles, *pt = all ? D.ptiles_all : D.ptiles;
+    const bool zero = flags & SMOOTH_ZERO, from_tmp = (flags & SMOOTH_FROM_TMP) && !zero;
     if (nft > 0) {
+        // fused tiles ping-pong between B and tmp; a zero input is not read, so
+        // the first sweep may write either buffer: pick the one that makes the
+        // last sweep land in B
+        T *cur = from_tmp ? tmp : B;
         for (int k = 0; k < nsweeps; ++k) {
-            const T *src = (k & 1) ? tmp : B;
-            T *dst = (k & 1) ? B : tmp;
-            k_dense_sweep<T><<<nft, SWEEP_THREADS, 0, s>>>(ft, D.probs, active, coef_dev, src, cs, S, eta, dst);
+            T *dst;
+            if (k == 0 && zero) {
+                dst = (nsweeps & 1) ? B : tmp;
+                k_dense_sweep<T, true><<<nft, SWEEP_THREADS, 0, s>>>(ft, D.probs, active, coef_dev, nullptr, cs, S, eta,
+                                                                     dst);
+            } else {
+                dst = cur == B ? tmp : B;
+                k_dense_sweep<T, false><<<nft, SWEEP_THREADS, 0, s>>>(ft, D.probs, active, coef_dev, cur, cs, S, eta,
+                                                                      dst);
+            }
             OHM_TRY(check_launch("dense fused sweep"));
+            cur = dst;
         }
-        if (nsweeps & 1) {
-            k_dense_tile_copy<T><<<nft, 256, 0, s>>>(ft, D.probs, active, tmp, B, cs);
+        if (nsweeps == 0 && zero) {
+            k_dense_tile_copy<T><<<nft, 256, 0, s>>>(ft, D.probs, active, nullptr, B, cs);
+            OHM_TRY(check_launch("dense tile zero"));
+        } else if (cur != B) {
+            k_dense_tile_copy<T><<<nft, 256, 0, s>>>(ft, D.probs, active, cur, B, cs);
             OHM_TRY(check_launch("dense tile copy"));
         }
     }
-    if (npt > 0)
+    if (npt > 0) {
+        // two half-sweeps per sweep, each a full out-of-place pass: a sweep
+        // returns to the buffer it started from
+        T *cur = from_tmp ? tmp : B, *oth = from_tmp ? B : tmp;
+        if (zero) {
+            k_dense_run_copy<T><<<npt, 256, 0, s>>>(pt, D.probs, active, nullptr, B, cs);
+            OHM_TRY(check_launch("dense run zero"));
+        }
         for (int k = 0; k < nsweeps; ++k) {
-            k_dense_stencil<T, MODE_SMOOTH><<<npt, 256, 0, s>>>(pt, D.probs, active, coef_dev, B, S, eta, tmp, cs, 0);
+            k_dense_stencil<T, MODE_SMOOTH><<<npt, 256, 0, s>>>(pt, D.probs, active, coef_dev, cur, S, eta, oth, cs, 0);
             OHM_TRY(check_launch("dense half-sweep"));
-            k_dense_stencil<T, MODE_SMOOTH><<<npt, 256, 0, s>>>(pt, D.probs, active, coef_dev, tmp, S, eta, B, cs, 1);
+            k_dense_stencil<T, MODE_SMOOTH><<<npt, 256, 0, s>>>(pt, D.probs, active, coef_dev, oth, S, eta, cur, cs, 1);
             OHM_TRY(check_launch("dense half-sweep"));
         }
+        if (cur != B) {
+            k_dense_run_copy<T><<<npt, 256, 0, s>>>(pt, D.probs, active, cur, B, cs);
+            OHM_TRY(check_launch("dense run copy"));
+        }
+    }
     return OHM_OK;
 }
 
@@ -389,12 +451,14 @@ ohm_status launch_dense_restrict(const ohm_hier *h, int fine_level, const T *fin
 
 template <typename T>
 ohm_status launch_dense_prolong(const ohm_hier *h, int coarse_level, const T *coarse, T *fine, int ncomp,
-                                int accumulate, const int *active, hipStream_t s)
+                                int accumulate, const int *active, hipStream_t s, const T *base)
 {
     const DenseLevelDev &F = h->dense[-coarse_level - 1], &C = h->dense[-coarse_level];
     if (F.ntile == 0) return OHM_OK;
-    k_dense_prolong<T><<<F.ntile, 256, 0, s>>>(F.tiles, F.probs, C.probs, active, coarse, C.ncells, fine, F.ncells,
-                                               ncomp, accumulate);
+    if (base && !accumulate) return fail(OHM_ERR_ARG, "prolongation onto a base field must accumulate");
+    if (accumulate && !base) base = fine;
+    k_dense_prolong<T><<<F.ntile, 256, 0, s>>>(F.tiles, F.probs, C.probs, active, coarse, C.ncells, base, fine,
+                                               F.ncells, ncomp);
     return check_launch("dense prolong");
 }
 
@@ -511,8 +575,8 @@ ohm_status launch_coarse_apply(const ohm_hier *h, int depth, const void *jobs_de
                                const T *r, T *e, const int *active, hipStream_t s)
 {
     if (njobs == 0) return OHM_OK;
-    k_coarse_apply<T><<<njobs, 256, 0, s>>>((const CoarseJob *)jobs_dev, active, inv, r, e,
-                                            h->dense[depth].ncells);
+    k_coarse_apply<T><<<dim3(COARSE_MAX_DEV / 64, njobs), 512, 0, s>>>((const CoarseJob *)jobs_dev, active, inv, r,
+                                                                      e, h->dense[depth].ncells);
     return check_launch("coarse apply");
 }
 
@@ -529,13 +593,13 @@ size_t coarse_job_bytes() { return sizeof(CoarseJob); }
 
 #define INST(T)                                                                                                \
     template ohm_status launch_dense_smooth<T>(const ohm_hier *, int, T *, T *, const T *, const T *,           \
-                                               const double *, int, bool, const int *, hipStream_t);           \
+                                               const double *, int, bool, const int *, hipStream_t, int);      \
     template ohm_status launch_dense_stencil<T>(const ohm_hier *, int, int, const T *, const T *, const T *,   \
                                                 const double *, T *, int, bool, const int *, hipStream_t);     \
     template ohm_status launch_dense_restrict<T>(const ohm_hier *, int, const T *, T *, int, const int *,      \
                                                  hipStream_t);                                                 \
     template ohm_status launch_dense_prolong<T>(const ohm_hier *, int, const T *, T *, int, int, const int *,  \
-                                                hipStream_t);                                                  \
+                                                hipStream_t, const T *);                                       \
     template ohm_status launch_coarse_apply<T>(const ohm_hier *, int, const void *, int, const double *,       \
                                                const T *, T *, const int *, hipStream_t);
 INST(double)

@@ -7,6 +7,9 @@
 // the same arithmetic as two separate half-sweeps.  `Addr::at(x, y, z)` gives
 // the element offset of tile-local cell (x, y, z), -2 <= x, y, z <= 9, inside a
 // component of the field; every such cell must exist (no coarse-fine ghosts).
+// With ZERO the input field is zero and is not read (B may be null): the red
+// update reduces to S / diag and the tile starts from zeros, which gives the
+// same values as a sweep over an explicitly zeroed field.
 #pragma once
 
 #include "stencil.h"
@@ -19,49 +22,71 @@ constexpr int TC2 = TW2 * TW2 * TW2;
 
 __device__ __forceinline__ int tix2(int x, int y, int z) { return (x + 2) + TW2 * ((y + 2) + TW2 * (z + 2)); }
 
-template <typename T, typename Addr>
+template <typename T, bool ZERO, typename Addr>
 __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restrict__ B, long long cs,
                                                  const T *__restrict__ S, const T *__restrict__ eta,
                                                  T *__restrict__ out, const T cih2, T (*sB)[TC2], T *sE)
 {
-    for (int t = threadIdx.x; t < TC2; t += SWEEP_THREADS) {
-        const int x = t % TW2 - 2, y = (t / TW2) % TW2 - 2, z = t / (TW2 * TW2) - 2;
-        const long long gi = A.at(x, y, z);
+    const int u = threadIdx.x;
+    // all global loads of the tile first, then the LDS stores
+    constexpr int ROUNDS = (TC2 + SWEEP_THREADS - 1) / SWEEP_THREADS;
+    T v[ROUNDS][4];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) sB[c][t] = B[c * cs + gi];
-        sE[t] = eta[gi];
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int t = u + SWEEP_THREADS * r;
+        if (t < TC2) {
+            const int x = t % TW2 - 2, y = (t / TW2) % TW2 - 2, z = t / (TW2 * TW2) - 2;
+            const long long gi = A.at(x, y, z);
+            if (!ZERO) {
+                v[r][0] = B[gi];
+                v[r][1] = B[cs + gi];
+                v[r][2] = B[2 * cs + gi];
+            }
+            v[r][3] = eta[gi];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < ROUNDS; ++r) {
+        const int t = u + SWEEP_THREADS * r;
+        if (t < TC2) {
+            sB[0][t] = ZERO ? T(0) : v[r][0];
+            sB[1][t] = ZERO ? T(0) : v[r][1];
+            sB[2][t] = ZERO ? T(0) : v[r][2];
+            sE[t] = v[r][3];
+        }
     }
     __syncthreads();
+    const T c8 = cih2 * T(0.125), c2 = cih2 * T(0.5);
     // red half-sweep: thread u < 256 takes tile cell u of the red colour,
     // 256 <= u < 448 a red first-layer face cell
     T red[3];
     int rp = -1;
-    {
-        const int u = threadIdx.x;
-        if (u < 448) {
-            int x, y, z;
-            if (u < 256) {
-                z = u >> 5;
-                y = (u >> 2) & 7;
-                x = 2 * (u & 3) + ((y + z) & 1);
-            } else {
-                const int v = u - 256, f = v >> 5, w = v & 31;
-                const int d = f >> 1, s = (f & 1) ? 8 : -1;
-                const int bb = w >> 2, a = 2 * (w & 3) + ((s + bb) & 1);
-                if (d == 0) { x = s; y = a; z = bb; }
-                else if (d == 1) { x = a; y = s; z = bb; }
-                else { x = a; y = bb; z = s; }
-            }
-            const int p = tix2(x, y, z);
-            rp = p;
-            const long long gi = A.at(x, y, z);
-            T dv[3], al[3];
-            divF_all<T, TW2>(sB[0], sB[1], sB[2], sE, p, dv, al);
+    if (u < 448) {
+        int x, y, z;
+        if (u < 256) {
+            z = u >> 5;
+            y = (u >> 2) & 7;
+            x = 2 * (u & 3) + ((y + z) & 1);
+        } else {
+            const int w = u - 256, f = w >> 5, k = w & 31;
+            const int d = f >> 1, s = (f & 1) ? 8 : -1;
+            const int bb = k >> 2, a = 2 * (k & 3) + ((s + bb) & 1);
+            if (d == 0) { x = s; y = a; z = bb; }
+            else if (d == 1) { x = a; y = s; z = bb; }
+            else { x = a; y = bb; z = s; }
+        }
+        rp = tix2(x, y, z);
+        const long long gi = A.at(x, y, z);
+        T al[3];
+        if (ZERO) {
+            alpha_all<T, TW2>(sE, rp, al);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const T LB = sB[c][p] + cih2 * dv[c];
-                red[c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * al[c]);
-            }
+            for (int c = 0; c < 3; ++c) red[c] = relax_div(S[c * cs + gi], fma(c2, al[c], T(1)));
+        } else {
+            T dv[3];
+            divF_all<T, TW2>(sB[0], sB[1], sB[2], sE, rp, dv, al);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) red[c] = relax_point(sB[c][rp], S[c * cs + gi], dv[c], al[c], c8, c2);
         }
     }
     __syncthreads();
@@ -71,7 +96,6 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
     __syncthreads();
     // black half-sweep on the tile (threads 0..255)
     {
-        const int u = threadIdx.x;
         T blk[3];
         int p = -1;
         if (u < 256) {
@@ -81,10 +105,7 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
             T dv[3], al[3];
             divF_all<T, TW2>(sB[0], sB[1], sB[2], sE, p, dv, al);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const T LB = sB[c][p] + cih2 * dv[c];
-                blk[c] = sB[c][p] + (S[c * cs + gi] - LB) / (T(1) + cih2 * al[c]);
-            }
+            for (int c = 0; c < 3; ++c) blk[c] = relax_point(sB[c][p], S[c * cs + gi], dv[c], al[c], c8, c2);
         }
         __syncthreads();
         if (p >= 0)
@@ -93,8 +114,7 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
     }
     __syncthreads();
     {
-        const int cell = threadIdx.x;
-        const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
+        const int x = u & 7, y = (u >> 3) & 7, z = u >> 6;
         const int p = tix2(x, y, z);
         const long long gi = A.at(x, y, z);
 #pragma unroll
