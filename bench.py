@@ -50,6 +50,47 @@ def counter_traffic(tag: str):
     return rec["hbm_bytes"] if rec["source_sha256_16"] == sweep_source_hash() else None
 
 
+def record_counters(fetch_dir: str, write_dir: str) -> dict:
+    """Write profiles/roofline_counters.json from the two rocprofv3 --pmc runs
+    of `bench.py --roofline-only` (FETCH_SIZE, then WRITE_SIZE): the 256 MiB
+    device copy calibrates each counter, the sweep dispatches are averaged."""
+    import csv
+    import glob
+    root = os.path.dirname(os.path.abspath(__file__))
+
+    def per_kernel(d, counter):
+        vals = {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(f)):
+                if r["Counter_Name"] == counter:
+                    vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+        return vals
+
+    copy_kib = 256 * 1024
+    out = {"calibration": {"copy_KiB": copy_kib}, "kernels": {}}
+    res = {}
+    for tag, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        vals = per_kernel(d, counter)
+        cal = max(v for k, vs in vals.items() if "copyBuffer" in k for v in vs)
+        out["calibration"][f"{tag}_read_KiB"] = cal
+        out["calibration"][f"{tag}_factor"] = copy_kib / cal
+        res[tag] = (vals, copy_kib / cal)
+    for prec, tname in (("f64", "double"), ("f32", "float")):
+        rec = {"kernel": f"k_blk_sweep<{tname}>", "source_sha256_16": sweep_source_hash()}
+        tot = 0.0
+        for tag in ("fetch", "write"):
+            vals, factor = res[tag]
+            xs = [v for k, vs in vals.items() if f"k_blk_sweep<{tname}" in k for v in vs]
+            rec[f"{tag}_KiB"] = sum(xs) / len(xs)
+            rec["dispatches"] = len(xs)
+            tot += rec[f"{tag}_KiB"] * factor * 1024
+        rec["hbm_bytes"] = tot
+        out["kernels"][prec] = rec
+    with open(os.path.join(root, "profiles", "roofline_counters.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 def _log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -248,17 +289,22 @@ def main():
     ap.add_argument("--streams", type=int, default=2)
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--hbm-gb", type=float, default=64.0)
+    ap.add_argument("--record-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/roofline_counters.json from two rocprofv3 --pmc runs of --roofline-only")
     ap.add_argument("--roofline-only", action="store_true",
                     help="run only a known-size copy and the level-0 smoother launches (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (see the sharding design notes)",
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     import torch
     import ohm_inputs as gen
     import paper_1009_0798_amd as ohm
 
+    if args.record_counters:
+        print(json.dumps(record_counters(*args.record_counters), indent=1))
+        return
     if args.roofline_only:
         roofline_probe(args)
         return
