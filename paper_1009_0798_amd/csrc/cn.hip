@@ -173,6 +173,28 @@ struct Solver {
         return reduce(nq, nq, at<double>(P.dots));
     }
 
+    // y = L x (lam dt) followed by the per-problem dots (xs[q], ys[q]), where
+    // every xs[q] or ys[q] is y itself or another vector.  One level: the dot
+    // partials come out of the operator kernel (same summation order as the
+    // dot kernel); AMR: the refluxed operator first, then the dot kernel.
+    ohm_status apply_dots(size_t xo, size_t yo, const double *const *xs, const double *const *ys, int nq)
+    {
+        if (nlev() == 1) {
+            const double *y = at<double>(yo);
+            StencilDots sd{{nullptr, nullptr}, nq, at<double>(P.part)};
+            for (int q = 0; q < nq; ++q) {
+                const double *other = xs[q] == y ? ys[q] : xs[q];
+                sd.dot_y[q] = other == y ? nullptr : other;
+            }
+            OHM_TRY(launch_blk_stencil<double>(h, 0, MODE_APPLY, vec(xo, 0), at<double>(P.og) + P.LG[0] * NC, VN,
+                                               GN, nullptr, eta64(0), etag64(0), lam_dt, vec(yo, 0), 0, nullptr,
+                                               nullptr, active, st, sd));
+            return reduce(nq, nq, at<double>(P.dots));
+        }
+        OHM_TRY(composite(xo, yo, MODE_APPLY, lam_dt, lam_dt, 0));
+        return dots(xs, ys, nq);
+    }
+
     // ---- multigrid cycle (precision T) ----------------------------------------
     // n sweeps on block level l, result in e.  flags as for dense levels:
     // SMOOTH_ZERO (zero input, not read) or SMOOTH_FROM_TMP (input in tmp)
@@ -252,8 +274,9 @@ struct Solver {
         const int zf = zero_guess ? SMOOTH_ZERO : 0;
         if (lev == 0) {
             OHM_TRY(smooth_blk(0, nu1, zf));
-            OHM_TRY(resid_blk(0));
-            OHM_TRY(launch_restrict_blk<T>(h, 0, mg(P.res, 0), VN, dv(P.d_rhs, 1), h->dense_cells[1], 3, active, st));
+            OHM_TRY(launch_resid_restrict_blk0<T>(h, mg(P.e, 0), at<T>(P.mg_g) + P.LG[0] * NC, VN, GN, mg(P.rhs, 0),
+                                                  etaT(0), etagT(0), lam_dt, dv(P.d_rhs, 1), h->dense_cells[1],
+                                                  active, st));
             OHM_TRY(down_dense(1));
             if ((nu2 & 1) && h->amr[0].complete27) {
                 OHM_TRY(launch_prolong_blk<T>(h, -1, dv(P.d_e, 1), h->dense_cells[1], mg(P.tmp, 0), VN, 3, 1, active,
@@ -487,20 +510,18 @@ struct Solver {
             OHM_TRY(vbicg_p((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.r),
                             at<double>(P.v), at<double>(P.p), st));
             OHM_TRY(precond(P.p, P.ph));
-            OHM_TRY(composite(P.ph, P.v, MODE_APPLY, lam_dt, lam_dt, 0));
             {
                 const double *xs[1] = {at<double>(P.rhat)}, *ys[1] = {at<double>(P.v)};
-                OHM_TRY(dots(xs, ys, 1));
+                OHM_TRY(apply_dots(P.ph, P.v, xs, ys, 1));
                 OHM_TRY(vscal(np, 2, active, at<double>(P.dots), 1, at<double>(P.scal), st));
             }
             OHM_TRY(vbicg_s((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.r),
                             at<double>(P.v), at<double>(P.s), st));
             OHM_TRY(precond(P.s, P.sh));
-            OHM_TRY(composite(P.sh, P.t, MODE_APPLY, lam_dt, lam_dt, 0));
             {
                 const double *xs[2] = {at<double>(P.t), at<double>(P.t)},
                              *ys[2] = {at<double>(P.s), at<double>(P.t)};
-                OHM_TRY(dots(xs, ys, 2));
+                OHM_TRY(apply_dots(P.sh, P.t, xs, ys, 2));
                 OHM_TRY(vscal(np, 3, active, at<double>(P.dots), 2, at<double>(P.scal), st));
             }
             OHM_TRY(vbicg_xr((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.x),

@@ -154,12 +154,30 @@ struct ohm_hier {
 namespace ohm {
 
 // launchers implemented in the kernel translation units ----------------------
+enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_SMOOTH = 2, MODE_RESID_RESTRICT = 3 };
+
+// Optional work fused into the block stencil kernel.  MODE_APPLY with ndot > 0
+// also writes per-block partial dot products of the output with dot_y[q]
+// (nullptr: with the output itself) to dot_part[block][ndot], summed in the
+// same order as the stand-alone dot kernel.
+struct StencilDots {
+    const double *dot_y[2];
+    int ndot;
+    double *dot_part;
+};
+
 template <typename T>
 ohm_status launch_blk_stencil(const ohm_hier *h, int level, int mode, const T *B, const T *Bg,
                               long long cs, long long gcs, const T *S, const T *eta, const T *etag,
                               const double *coef_dev, T *out, int colour, double *partials,
-                              const uint8_t *cov_zero, const int *active, hipStream_t s);
-enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_SMOOTH = 2 };
+                              const uint8_t *cov_zero, const int *active, hipStream_t s,
+                              StencilDots dots = StencilDots{{nullptr, nullptr}, 0, nullptr});
+// level 0 -> first dense level: r = S - L e on the blocks, restricted (mean of
+// the 8 children) straight into coarse; r itself is not stored
+template <typename T>
+ohm_status launch_resid_restrict_blk0(const ohm_hier *h, const T *B, const T *Bg, long long cs, long long gcs,
+                                      const T *S, const T *eta, const T *etag, const double *coef_dev, T *coarse,
+                                      long long ccs, const int *active, hipStream_t s);
 // one fused red-black sweep B -> out (levels whose blocks have every neighbour);
 // B == nullptr sweeps a zero input without reading it
 template <typename T>

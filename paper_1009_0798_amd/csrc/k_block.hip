@@ -56,7 +56,8 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
               const double *__restrict__ inv_h2_p, const double *__restrict__ coef_p,
               const T *__restrict__ B, const T *__restrict__ Bg, long long cs, long long gcs,
               const T *__restrict__ S, const T *__restrict__ eta, const T *__restrict__ etag,
-              T *__restrict__ out, int colour, double *__restrict__ partials)
+              T *__restrict__ out, int colour, double *__restrict__ partials, StencilDots dots,
+              const int *__restrict__ dense_map, const DenseProbDev *__restrict__ dp, long long ccs)
 {
     __shared__ T sB[3][TC];
     __shared__ T sE[1][TC];
@@ -64,7 +65,10 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
     __shared__ double sred[6][4];
     const int b = xcd_block(blockIdx.x, nblk);
     const int pr = prob_of[b];
-    if (active && !active[pr]) return;
+    if (active && !active[pr]) {
+        if (MODE == MODE_APPLY && threadIdx.x < dots.ndot) dots.dot_part[(long long)b * dots.ndot + threadIdx.x] = 0.0;
+        return;
+    }
     if (threadIdx.x < 27) snbr[threadIdx.x] = nbr_tab[27 * (long long)b + threadIdx.x];
     __syncthreads();
     load_tile<T, 3>(sB, B, Bg, cs, gcs, snbr);
@@ -74,6 +78,7 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
     const T c8 = cih2 * T(0.125), c2 = cih2 * T(0.5);
     const uint8_t cov = cov_zero ? cov_zero[b] : 0;
     double ss[3] = {0, 0, 0}, mx[3] = {0, 0, 0};
+    T o[2][3];   // outputs kept for the fused dot products / restriction
 #pragma unroll
     for (int half = 0; half < 2; ++half) {
         const int cell = threadIdx.x + 256 * half;
@@ -87,7 +92,10 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
         for (int c = 0; c < 3; ++c) {
             const T LB = fma(c8, dvs[c], sB[c][p]);
             if (MODE == MODE_APPLY) {
-                out[c * cs + gi] = zero ? T(0) : LB;
+                o[half][c] = zero ? T(0) : LB;
+                out[c * cs + gi] = o[half][c];
+            } else if (MODE == MODE_RESID_RESTRICT) {
+                o[half][c] = zero ? T(0) : S[c * cs + gi] - LB;
             } else if (MODE == MODE_RESID) {
                 T r = zero ? T(0) : S[c * cs + gi] - LB;
                 if (out) out[c * cs + gi] = r;
@@ -98,6 +106,56 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
                 T v = sB[c][p];
                 if (((x + y + z) & 1) == colour) v = relax_point(v, S[c * cs + gi], dvs[c], als[c], c8, c2);
                 out[c * cs + gi] = v;
+            }
+        }
+    }
+    if (MODE == MODE_APPLY && dots.ndot > 0) {
+        // the stand-alone dot kernel's order: thread t sums its elements
+        // (component 0, cells t and t + 256), (component 1, ...), (component 2, ...)
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        for (int q = 0; q < dots.ndot; ++q) {
+            double acc = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    const long long gi = (long long)b * NC + threadIdx.x + 256 * half;
+                    const double y = dots.dot_y[q] ? dots.dot_y[q][c * cs + gi] : (double)o[half][c];
+                    acc += (double)o[half][c] * y;
+                }
+            for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+            if (lane == 0) sred[q][wv] = acc;
+        }
+        __syncthreads();
+        if (threadIdx.x < dots.ndot) {
+            const int q = threadIdx.x;
+            dots.dot_part[(long long)b * dots.ndot + q] = ((sred[q][0] + sred[q][1]) + sred[q][2]) + sred[q][3];
+        }
+    }
+    if (MODE == MODE_RESID_RESTRICT) {
+        // r through LDS (the tile is no longer needed), then the mean of the 8
+        // children of each coarse cell in the order of the restriction kernel
+        __syncthreads();
+#pragma unroll
+        for (int half = 0; half < 2; ++half)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sB[c][threadIdx.x + 256 * half] = o[half][c];
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int t = threadIdx.x;
+            const int i = t & 3, j = (t >> 2) & 3, k = t >> 4;
+            const DenseProbDev q = dp[pr];
+            const long long cidx = dense_map[b] + i + (long long)q.nx * (j + (long long)q.ny * k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                T a = T(0);
+#pragma unroll
+                for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+                    for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+                        for (int dx = 0; dx < 2; ++dx) a += sB[c][(2 * i + dx) + NB * ((2 * j + dy) + NB * (2 * k + dz))];
+                out[c * ccs + cidx] = a * T(0.125);
             }
         }
     }
@@ -444,25 +502,37 @@ template <typename T>
 ohm_status launch_blk_stencil(const ohm_hier *h, int level, int mode, const T *B, const T *Bg, long long cs,
                               long long gcs, const T *S, const T *eta, const T *etag, const double *coef_dev,
                               T *out, int colour, double *partials, const uint8_t *cov_zero, const int *active,
-                              hipStream_t s)
+                              hipStream_t s, StencilDots dots)
 {
     const AmrLevelDev &L = h->amr[level];
     if (L.nb == 0) return OHM_OK;
+    if (dots.ndot < 0 || dots.ndot > 2 || (dots.ndot > 0 && (mode != MODE_APPLY || !dots.dot_part)))
+        return fail(OHM_ERR_ARG, "fused dot products need MODE_APPLY, 1 or 2 products and a partials buffer");
     dim3 grid(L.nb), blk(256);
+#define ARGS L.nb, L.nbr, L.prob, cov_zero, active, L.inv_h2, coef_dev, B, Bg, cs, gcs, S, eta, etag, out, colour, \
+             partials, dots, nullptr, nullptr, 0
     switch (mode) {
-    case MODE_APPLY:
-        k_blk_stencil<T, MODE_APPLY><<<grid, blk, 0, s>>>(L.nb, L.nbr, L.prob, cov_zero, active, L.inv_h2, coef_dev,
-                                                          B, Bg, cs, gcs, S, eta, etag, out, colour, partials);
-        break;
-    case MODE_RESID:
-        k_blk_stencil<T, MODE_RESID><<<grid, blk, 0, s>>>(L.nb, L.nbr, L.prob, cov_zero, active, L.inv_h2, coef_dev,
-                                                          B, Bg, cs, gcs, S, eta, etag, out, colour, partials);
-        break;
-    default:
-        k_blk_stencil<T, MODE_SMOOTH><<<grid, blk, 0, s>>>(L.nb, L.nbr, L.prob, cov_zero, active, L.inv_h2, coef_dev,
-                                                           B, Bg, cs, gcs, S, eta, etag, out, colour, partials);
+    case MODE_APPLY: k_blk_stencil<T, MODE_APPLY><<<grid, blk, 0, s>>>(ARGS); break;
+    case MODE_RESID: k_blk_stencil<T, MODE_RESID><<<grid, blk, 0, s>>>(ARGS); break;
+    case MODE_SMOOTH: k_blk_stencil<T, MODE_SMOOTH><<<grid, blk, 0, s>>>(ARGS); break;
+    default: return fail(OHM_ERR_ARG, "unknown stencil mode %d", mode);
     }
+#undef ARGS
     return check_launch("block stencil");
+}
+
+template <typename T>
+ohm_status launch_resid_restrict_blk0(const ohm_hier *h, const T *B, const T *Bg, long long cs, long long gcs,
+                                      const T *S, const T *eta, const T *etag, const double *coef_dev, T *coarse,
+                                      long long ccs, const int *active, hipStream_t s)
+{
+    const AmrLevelDev &L = h->amr[0];
+    if (L.nb == 0) return OHM_OK;
+    if (h->min_level > -1) return fail(OHM_ERR_ARG, "no dense level below level 0");
+    k_blk_stencil<T, MODE_RESID_RESTRICT><<<L.nb, 256, 0, s>>>(
+        L.nb, L.nbr, L.prob, nullptr, active, L.inv_h2, coef_dev, B, Bg, cs, gcs, S, eta, etag, coarse, 0,
+        nullptr, StencilDots{{nullptr, nullptr}, 0, nullptr}, L.dense_map, h->dense[1].probs, ccs);
+    return check_launch("residual + restriction to dense");
 }
 
 template <typename T>
@@ -563,7 +633,11 @@ ohm_status launch_reduce_problem(int nprob, int nrange, const long long *range_d
                                             const double *, T *, const int *, hipStream_t);                      \
     template ohm_status launch_blk_stencil<T>(const ohm_hier *, int, int, const T *, const T *, long long,      \
                                               long long, const T *, const T *, const T *, const double *, T *,  \
-                                              int, double *, const uint8_t *, const int *, hipStream_t);        \
+                                              int, double *, const uint8_t *, const int *, hipStream_t,         \
+                                              StencilDots);                                                     \
+    template ohm_status launch_resid_restrict_blk0<T>(const ohm_hier *, const T *, const T *, long long,       \
+                                                      long long, const T *, const T *, const T *,             \
+                                                      const double *, T *, long long, const int *, hipStream_t);        \
     template ohm_status launch_restrict_blk<T>(const ohm_hier *, int, const T *, long long, T *, long long, int, \
                                                const int *, hipStream_t);                                       \
     template ohm_status launch_prolong_blk<T>(const ohm_hier *, int, const T *, long long, T *, long long, int,  \
