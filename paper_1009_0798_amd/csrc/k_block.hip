@@ -542,6 +542,9 @@ ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long 
     const AmrLevelDev &L = h->amr[level];
     if (L.nb == 0) return OHM_OK;
     if (!L.complete27) return fail(OHM_ERR_ARG, "fused sweep needs every neighbour block of level %d", level);
+    if ((unsigned long long)L.nb * NC * sizeof(T) > 0xFFFFFFFFull)
+        return fail(OHM_ERR_ARG, "level %d: fused sweep addresses each field array with 32-bit offsets (max 4 GiB)",
+                    level);
     if (B)
         k_blk_sweep<T, false><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S,
                                                              eta, out);

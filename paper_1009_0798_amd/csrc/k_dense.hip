@@ -389,6 +389,8 @@ ohm_status launch_dense_smooth(const ohm_hier *h, int level, T *B, T *tmp, const
     const int nft = all ? D.nftile_all : D.nftile, npt = all ? D.nptile_all : D.nptile;
     const int *ft = all ? D.ftiles_all : D.ftiles, *pt = all ? D.ptiles_all : D.ptiles;
     const bool zero = flags & SMOOTH_ZERO, from_tmp = (flags & SMOOTH_FROM_TMP) && !zero;
+    if (nft > 0 && (unsigned long long)cs * sizeof(T) > 0xFFFFFFFFull)
+        return fail(OHM_ERR_ARG, "dense level %d: fused sweep addresses each field array with 32-bit offsets", level);
     if (nft > 0) {
         // fused tiles ping-pong between B and tmp; a zero input is not read, so
         // the first sweep may write either buffer: pick the one that makes the

@@ -22,37 +22,52 @@ constexpr int TC2 = TW2 * TW2 * TW2;
 
 __device__ __forceinline__ int tix2(int x, int y, int z) { return (x + 2) + TW2 * ((y + 2) + TW2 * (z + 2)); }
 
+// Element at a byte offset from a wavefront-uniform base: the offset stays a
+// 32-bit VGPR and the base an SGPR pair, so the 3 components and eta share one
+// address computation.  The launchers check that every level array fits in
+// 4 GiB.
+template <typename T>
+__device__ __forceinline__ T load_at(const T *base, unsigned off)
+{
+    return *(const T *)((const char *)base + off);
+}
+template <typename T>
+__device__ __forceinline__ void store_at(T *base, unsigned off, T v)
+{
+    *(T *)((char *)base + off) = v;
+}
+
 template <typename T, bool ZERO, typename Addr>
 __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restrict__ B, long long cs,
                                                  const T *__restrict__ S, const T *__restrict__ eta,
                                                  T *__restrict__ out, const T cih2, T (*sB)[TC2], T *sE)
 {
     const int u = threadIdx.x;
-    // all global loads of the tile first, then the LDS stores
-    constexpr int ROUNDS = (TC2 + SWEEP_THREADS - 1) / SWEEP_THREADS;
-    T v[ROUNDS][4];
+    const T *B0 = B, *B1 = ZERO ? B : B + cs, *B2 = ZERO ? B : B + 2 * cs;
+    const T *S0 = S, *S1 = S + cs, *S2 = S + 2 * cs;
+    // tile load: thread u < 432 owns the column (x, y) = u mod 144 of the tile
+    // and four consecutive z; all global loads first, then the LDS stores
+    if (u < 3 * TW2 * TW2) {
+        const int col = u % (TW2 * TW2), zg = u / (TW2 * TW2);
+        const int x = col % TW2 - 2, y = col / TW2 - 2;
+        T v[4][4];
 #pragma unroll
-    for (int r = 0; r < ROUNDS; ++r) {
-        const int t = u + SWEEP_THREADS * r;
-        if (t < TC2) {
-            const int x = t % TW2 - 2, y = (t / TW2) % TW2 - 2, z = t / (TW2 * TW2) - 2;
-            const long long gi = A.at(x, y, z);
+        for (int k = 0; k < 4; ++k) {
+            const unsigned off = (unsigned)A.at(x, y, 4 * zg + k - 2) * (unsigned)sizeof(T);
             if (!ZERO) {
-                v[r][0] = B[gi];
-                v[r][1] = B[cs + gi];
-                v[r][2] = B[2 * cs + gi];
+                v[k][0] = load_at(B0, off);
+                v[k][1] = load_at(B1, off);
+                v[k][2] = load_at(B2, off);
             }
-            v[r][3] = eta[gi];
+            v[k][3] = load_at(eta, off);
         }
-    }
 #pragma unroll
-    for (int r = 0; r < ROUNDS; ++r) {
-        const int t = u + SWEEP_THREADS * r;
-        if (t < TC2) {
-            sB[0][t] = ZERO ? T(0) : v[r][0];
-            sB[1][t] = ZERO ? T(0) : v[r][1];
-            sB[2][t] = ZERO ? T(0) : v[r][2];
-            sE[t] = v[r][3];
+        for (int k = 0; k < 4; ++k) {
+            const int t = col + TW2 * TW2 * (4 * zg + k);
+            sB[0][t] = ZERO ? T(0) : v[k][0];
+            sB[1][t] = ZERO ? T(0) : v[k][1];
+            sB[2][t] = ZERO ? T(0) : v[k][2];
+            sE[t] = v[k][3];
         }
     }
     __syncthreads();
@@ -76,17 +91,18 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
             else { x = a; y = bb; z = s; }
         }
         rp = tix2(x, y, z);
-        const long long gi = A.at(x, y, z);
+        const unsigned off = (unsigned)A.at(x, y, z) * (unsigned)sizeof(T);
+        const T s3[3] = {load_at(S0, off), load_at(S1, off), load_at(S2, off)};
         T al[3];
         if (ZERO) {
             alpha_all<T, TW2>(sE, rp, al);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) red[c] = relax_div(S[c * cs + gi], fma(c2, al[c], T(1)));
+            for (int c = 0; c < 3; ++c) red[c] = relax_div(s3[c], fma(c2, al[c], T(1)));
         } else {
             T dv[3];
             divF_all<T, TW2>(sB[0], sB[1], sB[2], sE, rp, dv, al);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) red[c] = relax_point(sB[c][rp], S[c * cs + gi], dv[c], al[c], c8, c2);
+            for (int c = 0; c < 3; ++c) red[c] = relax_point(sB[c][rp], s3[c], dv[c], al[c], c8, c2);
         }
     }
     __syncthreads();
@@ -101,11 +117,12 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
         if (u < 256) {
             const int z = u >> 5, y = (u >> 2) & 7, x = 2 * (u & 3) + (1 - ((y + z) & 1));
             p = tix2(x, y, z);
-            const long long gi = A.at(x, y, z);
+            const unsigned off = (unsigned)A.at(x, y, z) * (unsigned)sizeof(T);
+            const T s3[3] = {load_at(S0, off), load_at(S1, off), load_at(S2, off)};
             T dv[3], al[3];
             divF_all<T, TW2>(sB[0], sB[1], sB[2], sE, p, dv, al);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) blk[c] = relax_point(sB[c][p], S[c * cs + gi], dv[c], al[c], c8, c2);
+            for (int c = 0; c < 3; ++c) blk[c] = relax_point(sB[c][p], s3[c], dv[c], al[c], c8, c2);
         }
         __syncthreads();
         if (p >= 0)
@@ -116,9 +133,10 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
     {
         const int x = u & 7, y = (u >> 3) & 7, z = u >> 6;
         const int p = tix2(x, y, z);
-        const long long gi = A.at(x, y, z);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) out[c * cs + gi] = sB[c][p];
+        const unsigned off = (unsigned)A.at(x, y, z) * (unsigned)sizeof(T);
+        store_at(out, off, sB[0][p]);
+        store_at(out + cs, off, sB[1][p]);
+        store_at(out + 2 * cs, off, sB[2][p]);
     }
 }
 

@@ -67,6 +67,27 @@ def test_lognormal32_against_oracle(precision, outer, cycle):
     assert np.linalg.norm(R) <= 1.01 * RTOL * np.linalg.norm(S)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_backward_euler_against_oracle(precision):
+    """lambda = 1 (eq. 7): S = b and L = I + dt div F."""
+    announce(f"cn backward euler precision={precision}")
+    n = 32
+    spec = gen.uniform_spec(n)
+    h = spec.dx0
+    eta = gen.lognormal_eta(n, 3.0, seed=23)
+    B = gen.divfree(n, 2.0, seed=24)
+    dt = gen.explicit_dt(h, 1.0, 60.0)
+    st, stats, got = _gpu_step(spec, B, eta, dt, precision=precision, max_iters=400, lam=1.0)
+    ex, _ = mg.cn_step(B, eta, h, dt, lam=1.0, rtol=1e-13)
+    S = ref.source(B, eta, h, dt, 1.0)
+    assert np.array_equal(S, B)
+    print("stats", stats, "rel err vs oracle", np.linalg.norm(got - ex) / np.linalg.norm(ex))
+    assert st == 0 and stats[0]["rel_res"] <= RTOL
+    assert np.linalg.norm(got - ex) <= _bound(np.linalg.norm(S), ex)
+    R = ref.residual(got, S, eta, h, dt)
+    assert np.linalg.norm(R) <= 1.01 * RTOL * np.linalg.norm(S)
+
+
 def test_ragged_box_variable_eta():
     """24 x 16 x 32 box: coarsenings 12x8x16, 6x4x8, 3x2x4 (odd coarsest)."""
     announce("cn ragged box")
