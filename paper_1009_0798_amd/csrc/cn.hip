@@ -198,7 +198,9 @@ struct Solver {
     // ---- multigrid cycle (precision T) ----------------------------------------
     // n sweeps on block level l, result in e.  flags as for dense levels:
     // SMOOTH_ZERO (zero input, not read) or SMOOTH_FROM_TMP (input in tmp)
-    ohm_status smooth_blk(int l, int n, int flags = 0)
+    // coarse (level 0 only): the first sweep reads e + P(coarse), the
+    // prolonged correction from the first dense level, without storing it
+    ohm_status smooth_blk(int l, int n, int flags = 0, const T *coarse = nullptr)
     {
         const bool zero = flags & SMOOTH_ZERO, from_tmp = (flags & SMOOTH_FROM_TMP) && !zero;
         T *e = mg(P.e, l), *tmp = mg(P.tmp, l);
@@ -211,6 +213,10 @@ struct Solver {
                 if (k == 0 && zero) {
                     dst = (n & 1) ? e : tmp;
                     OHM_TRY(launch_blk_sweep<T>(h, l, nullptr, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st));
+                } else if (k == 0 && coarse) {
+                    dst = cur == e ? tmp : e;
+                    OHM_TRY(launch_blk_sweep<T>(h, l, cur, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st, coarse,
+                                                h->dense_cells[1]));
                 } else {
                     dst = cur == e ? tmp : e;
                     OHM_TRY(launch_blk_sweep<T>(h, l, cur, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st));
@@ -278,7 +284,10 @@ struct Solver {
                                                   etaT(0), etagT(0), lam_dt, dv(P.d_rhs, 1), h->dense_cells[1],
                                                   active, st));
             OHM_TRY(down_dense(1));
-            if ((nu2 & 1) && h->amr[0].complete27) {
+            if (h->amr[0].complete27 && nu2 > 0 && !(nu2 & 1)) {
+                // even count: the first sweep adds the correction as it loads
+                OHM_TRY(smooth_blk(0, nu2, 0, dv(P.d_e, 1)));
+            } else if ((nu2 & 1) && h->amr[0].complete27) {
                 OHM_TRY(launch_prolong_blk<T>(h, -1, dv(P.d_e, 1), h->dense_cells[1], mg(P.tmp, 0), VN, 3, 1, active,
                                               st, mg(P.e, 0)));
                 OHM_TRY(smooth_blk(0, nu2, SMOOTH_FROM_TMP));

@@ -179,10 +179,13 @@ ohm_status launch_resid_restrict_blk0(const ohm_hier *h, const T *B, const T *Bg
                                       const T *S, const T *eta, const T *etag, const double *coef_dev, T *coarse,
                                       long long ccs, const int *active, hipStream_t s);
 // one fused red-black sweep B -> out (levels whose blocks have every neighbour);
-// B == nullptr sweeps a zero input without reading it
+// B == nullptr sweeps a zero input without reading it; coarse != nullptr
+// (level 0 only) sweeps B + P(coarse), the trilinear prolongation of the first
+// dense level's field, without storing the corrected input
 template <typename T>
 ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long cs, const T *S, const T *eta,
-                            const double *coef_dev, T *out, const int *active, hipStream_t s);
+                            const double *coef_dev, T *out, const int *active, hipStream_t s,
+                            const T *coarse = nullptr, long long ccs = 0);
 
 template <typename T>
 ohm_status launch_dense_stencil(const ohm_hier *h, int level, int mode, const T *B, const T *S,

@@ -199,15 +199,60 @@ struct BlockAddr {
     }
 };
 
-template <typename T, bool ZERO>
+// Trilinear correction from the first dense level for the tile of a level-0
+// block: the 8^3 coarse cells covering the tile's parents and their
+// neighbours (origin 4 (i, j, k)_block - 2, periodic) are staged in LDS; the
+// weights and the order of the sum are those of k_prolong_dense_blk0.
+template <typename T>
+struct Level0Coarse {
+    static constexpr bool active = true;
+    const T *coarse;
+    long long ccs;
+    DenseProbDev q;
+    int i0, j0, k0;
+    T *sC;      // [3][512] in LDS
+    T r[3];
+    __device__ __forceinline__ void load()
+    {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int t = threadIdx.x + SWEEP_THREADS * k, c = t >> 9, m = t & 511;
+            const int i = (i0 + (m & 7) + q.nx) % q.nx, j = (j0 + ((m >> 3) & 7) + q.ny) % q.ny,
+                      kk = (k0 + (m >> 6) + q.nz) % q.nz;
+            r[k] = coarse[c * ccs + q.off + i + (long long)q.nx * (j + (long long)q.ny * kk)];
+        }
+    }
+    __device__ __forceinline__ void stage()
+    {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sC[threadIdx.x + SWEEP_THREADS * k] = r[k];
+    }
+    __device__ __forceinline__ T add(int x, int y, int z, int c, T base) const
+    {
+        const int i = (x >> 1) + 2, j = (y >> 1) + 2, k = (z >> 1) + 2;
+        const int i1 = i + ((x & 1) ? 1 : -1), j1 = j + ((y & 1) ? 1 : -1), k1 = k + ((z & 1) ? 1 : -1);
+        const T *C = sC + 512 * c;
+        auto at = [](int a, int bb, int cc) { return a + 8 * (bb + 8 * cc); };
+        T v = T(27) * C[at(i, j, k)] + T(9) * (C[at(i1, j, k)] + C[at(i, j1, k)] + C[at(i, j, k1)]) +
+              T(3) * (C[at(i1, j1, k)] + C[at(i1, j, k1)] + C[at(i, j1, k1)]) + C[at(i1, j1, k1)];
+        v *= T(1.0 / 64.0);
+        return base + v;
+    }
+};
+
+// MODE 0: sweep B -> out; 1: zero input (B not read); 2: sweep of B plus the
+// prolonged correction from the first dense level (coarse), B -> out
+template <typename T, int MODE>
 __global__ void __launch_bounds__(SWEEP_THREADS)
 k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ prob_of,
             const int *__restrict__ active, const double *__restrict__ inv_h2_p, const double *__restrict__ coef_p,
             const T *__restrict__ B, long long cs, const T *__restrict__ S, const T *__restrict__ eta,
-            T *__restrict__ out)
+            T *__restrict__ out, const int *__restrict__ ijk, const DenseProbDev *__restrict__ dp,
+            const T *__restrict__ coarse, long long ccs)
 {
     __shared__ T sB[3][TC2];
     __shared__ T sE[TC2];
+    __shared__ T sC[MODE == 2 ? 3 * 512 : 1];
     __shared__ int snbr[27];
     const int b = xcd_block(blockIdx.x, nblk);
     const int pr = prob_of[b];
@@ -215,7 +260,14 @@ k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ p
     if (threadIdx.x < 27) snbr[threadIdx.x] = nbr_tab[27 * (long long)b + threadIdx.x];
     __syncthreads();
     const BlockAddr A{snbr, b};
-    fused_sweep_tile<T, ZERO>(A, B, cs, S, eta, out, T(coef_p[pr]) * T(inv_h2_p[pr]), sB, sE);
+    const T cih2 = T(coef_p[pr]) * T(inv_h2_p[pr]);
+    if (MODE == 2) {
+        Level0Coarse<T> cor{coarse, ccs, dp[pr], 4 * ijk[3 * b] - 2, 4 * ijk[3 * b + 1] - 2, 4 * ijk[3 * b + 2] - 2,
+                            sC, {}};
+        fused_sweep_tile<T, false>(A, B, cs, S, eta, out, cih2, sB, sE, cor);
+    } else {
+        fused_sweep_tile<T, MODE == 1>(A, B, cs, S, eta, out, cih2, sB, sE);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -329,20 +381,29 @@ k_prolong_dense_blk0(int nblk, const int *__restrict__ ijk, const int *__restric
                      const T *__restrict__ coarse, long long ccs, const T *base, T *fine, long long fcs,
                      int ncomp)
 {
+    // the 6^3 coarse cells the block's 8^3 fine cells interpolate from (its
+    // 4^3 parents and one layer around them, periodic) are staged in LDS
+    __shared__ T sc[3][216];
     const int b = xcd_block(blockIdx.x, nblk);
     const int pr = prob_of[b];
     if (active && !active[pr]) return;
     const DenseProbDev q = dp[pr];
     const int bi = ijk[3 * b], bj = ijk[3 * b + 1], bk = ijk[3 * b + 2];
+    const int i0 = 4 * bi - 1, j0 = 4 * bj - 1, k0 = 4 * bk - 1;
+    for (int t = threadIdx.x; t < 216 * ncomp; t += blockDim.x) {
+        const int c = t / 216, r = t % 216;
+        const int i = (i0 + r % 6 + q.nx) % q.nx, j = (j0 + (r / 6) % 6 + q.ny) % q.ny, k = (k0 + r / 36 + q.nz) % q.nz;
+        sc[c][r] = coarse[c * ccs + q.off + i + (long long)q.nx * (j + (long long)q.ny * k)];
+    }
+    __syncthreads();
     for (int cell = threadIdx.x; cell < NC; cell += blockDim.x) {
         const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
-        const int X = NB * bi + x, Y = NB * bj + y, Z = NB * bk + z;
-        const int i = X >> 1, j = Y >> 1, k = Z >> 1;
-        const int si = (X & 1) ? 1 : -1, sj = (Y & 1) ? 1 : -1, sk = (Z & 1) ? 1 : -1;
-        const int i1 = (i + si + q.nx) % q.nx, j1 = (j + sj + q.ny) % q.ny, k1 = (k + sk + q.nz) % q.nz;
-        auto at = [&](int a, int bb, int cc) { return q.off + a + (long long)q.nx * (bb + (long long)q.ny * cc); };
+        // parent (local index 1..4 on each axis) and its neighbour on the child's side
+        const int i = (x >> 1) + 1, j = (y >> 1) + 1, k = (z >> 1) + 1;
+        const int i1 = i + ((x & 1) ? 1 : -1), j1 = j + ((y & 1) ? 1 : -1), k1 = k + ((z & 1) ? 1 : -1);
+        auto at = [](int a, int bb, int cc) { return a + 6 * (bb + 6 * cc); };
         for (int c = 0; c < ncomp; ++c) {
-            const T *C = coarse + c * ccs;
+            const T *C = sc[c];
             T v = T(27) * C[at(i, j, k)] + T(9) * (C[at(i1, j, k)] + C[at(i, j1, k)] + C[at(i, j, k1)]) +
                   T(3) * (C[at(i1, j1, k)] + C[at(i1, j, k1)] + C[at(i, j1, k1)]) + C[at(i1, j1, k1)];
             v *= T(1.0 / 64.0);
@@ -537,7 +598,8 @@ ohm_status launch_resid_restrict_blk0(const ohm_hier *h, const T *B, const T *Bg
 
 template <typename T>
 ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long cs, const T *S, const T *eta,
-                            const double *coef_dev, T *out, const int *active, hipStream_t s)
+                            const double *coef_dev, T *out, const int *active, hipStream_t s, const T *coarse,
+                            long long ccs)
 {
     const AmrLevelDev &L = h->amr[level];
     if (L.nb == 0) return OHM_OK;
@@ -545,12 +607,18 @@ ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long 
     if ((unsigned long long)L.nb * NC * sizeof(T) > 0xFFFFFFFFull)
         return fail(OHM_ERR_ARG, "level %d: fused sweep addresses each field array with 32-bit offsets (max 4 GiB)",
                     level);
-    if (B)
-        k_blk_sweep<T, false><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S,
-                                                             eta, out);
-    else
-        k_blk_sweep<T, true><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S,
-                                                            eta, out);
+    if (coarse) {
+        if (level != 0 || h->min_level > -1 || !B)
+            return fail(OHM_ERR_ARG, "a fused coarse correction needs level 0, a dense level below it and an input");
+        k_blk_sweep<T, 2><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta,
+                                                         out, L.ijk, h->dense[1].probs, coarse, ccs);
+    } else if (B) {
+        k_blk_sweep<T, 0><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta,
+                                                         out, nullptr, nullptr, nullptr, 0);
+    } else {
+        k_blk_sweep<T, 1><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta,
+                                                         out, nullptr, nullptr, nullptr, 0);
+    }
     return check_launch("fused sweep");
 }
 
@@ -586,6 +654,7 @@ ohm_status launch_prolong_blk(const ohm_hier *h, int coarse_level, const T *coar
     }
     const AmrLevelDev &L = h->amr[0];
     if (base && !accumulate) return fail(OHM_ERR_ARG, "prolongation onto a base field must accumulate");
+    if (ncomp < 1 || ncomp > 3) return fail(OHM_ERR_ARG, "prolongation takes 1 to 3 components, got %d", ncomp);
     if (accumulate && !base) base = fine;
     k_prolong_dense_blk0<T><<<L.nb, 256, 0, s>>>(L.nb, L.ijk, L.prob, h->dense[1].probs, active, coarse, ccs, base,
                                                  fine, fcs, ncomp);
@@ -633,7 +702,7 @@ ohm_status launch_reduce_problem(int nprob, int nrange, const long long *range_d
 
 #define INST(T)                                                                                                 \
     template ohm_status launch_blk_sweep<T>(const ohm_hier *, int, const T *, long long, const T *, const T *,   \
-                                            const double *, T *, const int *, hipStream_t);                      \
+                                            const double *, T *, const int *, hipStream_t, const T *, long long);                      \
     template ohm_status launch_blk_stencil<T>(const ohm_hier *, int, int, const T *, const T *, long long,      \
                                               long long, const T *, const T *, const T *, const double *, T *,  \
                                               int, double *, const uint8_t *, const int *, hipStream_t,         \

@@ -9,7 +9,11 @@
 // component of the field; every such cell must exist (no coarse-fine ghosts).
 // With ZERO the input field is zero and is not read (B may be null): the red
 // update reduces to S / diag and the tile starts from zeros, which gives the
-// same values as a sweep over an explicitly zeroed field.
+// same values as a sweep over an explicitly zeroed field.  A `Coarse` object
+// with active = true adds a coarse-grid correction to every tile value as it
+// is loaded (prolongation fused into the first post-smoothing sweep); its
+// load() issues the global reads of whatever it stages, stage() stores them in
+// LDS (a barrier follows) and add(x, y, z, c, v) returns v plus the correction.
 #pragma once
 
 #include "stencil.h"
@@ -21,6 +25,14 @@ constexpr int TW2 = 8 + 4;               // tile edge with a two-cell halo
 constexpr int TC2 = TW2 * TW2 * TW2;
 
 __device__ __forceinline__ int tix2(int x, int y, int z) { return (x + 2) + TW2 * ((y + 2) + TW2 * (z + 2)); }
+
+template <typename T>
+struct NoCoarse {
+    static constexpr bool active = false;
+    __device__ __forceinline__ void load() {}
+    __device__ __forceinline__ void stage() {}
+    __device__ __forceinline__ T add(int, int, int, int, T v) const { return v; }
+};
 
 // Element at a byte offset from a wavefront-uniform base: the offset stays a
 // 32-bit VGPR and the base an SGPR pair, so the 3 components and eta share one
@@ -37,20 +49,24 @@ __device__ __forceinline__ void store_at(T *base, unsigned off, T v)
     *(T *)((char *)base + off) = v;
 }
 
-template <typename T, bool ZERO, typename Addr>
+template <typename T, bool ZERO, typename Addr, typename Coarse = NoCoarse<T>>
 __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restrict__ B, long long cs,
                                                  const T *__restrict__ S, const T *__restrict__ eta,
-                                                 T *__restrict__ out, const T cih2, T (*sB)[TC2], T *sE)
+                                                 T *__restrict__ out, const T cih2, T (*sB)[TC2], T *sE,
+                                                 Coarse cor = Coarse())
 {
     const int u = threadIdx.x;
     const T *B0 = B, *B1 = ZERO ? B : B + cs, *B2 = ZERO ? B : B + 2 * cs;
     const T *S0 = S, *S1 = S + cs, *S2 = S + 2 * cs;
     // tile load: thread u < 432 owns the column (x, y) = u mod 144 of the tile
     // and four consecutive z; all global loads first, then the LDS stores
-    if (u < 3 * TW2 * TW2) {
-        const int col = u % (TW2 * TW2), zg = u / (TW2 * TW2);
-        const int x = col % TW2 - 2, y = col / TW2 - 2;
-        T v[4][4];
+    constexpr int NCOL = TW2 * TW2;
+    const bool loader = u < 3 * NCOL;
+    const int col = u % NCOL, zg = u / NCOL;
+    const int x = col % TW2 - 2, y = col / TW2 - 2;
+    T v[4][4];
+    if (Coarse::active) cor.load();
+    if (loader) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const unsigned off = (unsigned)A.at(x, y, 4 * zg + k - 2) * (unsigned)sizeof(T);
@@ -61,12 +77,18 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
             }
             v[k][3] = load_at(eta, off);
         }
+    }
+    if (Coarse::active) {
+        cor.stage();
+        __syncthreads();
+    }
+    if (loader) {
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
-            const int t = col + TW2 * TW2 * (4 * zg + k);
-            sB[0][t] = ZERO ? T(0) : v[k][0];
-            sB[1][t] = ZERO ? T(0) : v[k][1];
-            sB[2][t] = ZERO ? T(0) : v[k][2];
+            const int z = 4 * zg + k - 2;
+            const int t = col + NCOL * (z + 2);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sB[c][t] = cor.add(x, y, z, c, ZERO ? T(0) : v[k][c]);
             sE[t] = v[k][3];
         }
     }
