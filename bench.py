@@ -19,8 +19,12 @@ import numpy as np
 
 METRIC = "solved cells/s per CN step at rel. residual 1e-10 (FP64 vs mixed); HBM GB/s"
 HBM_PEAK_GBS = 8000.0
-NU = 4          # V(4,4) on the base grid, one sweep on the coarser levels: the schedule
-NU_COARSE = 1   # the autotuner picks for this workload on MI355X
+# Cycle schedules (pre, post sweeps on the base grid; one sweep on the levels
+# below it) picked by the autotuner on MI355X, per precision of the cycle, for
+# the 128^3 log-normal workload, and for the two-level AMR workload
+SCHEDULE = {0: (2, 5), 1: (3, 4)}
+NU_COARSE = 1
+AMR_SCHEDULE = (4, 4)
 
 
 def sweep_source_hash() -> str:
@@ -98,8 +102,8 @@ def _log(msg):
 def run_steps(ohm, H, B0, E, dt, K, precision, ws):
     import torch
     B = [B0.clone()]
-    opts = ohm.default_opts(rtol=1e-10, precision=precision, max_iters=200, nu_pre=NU, nu_post=NU,
-                            nu_coarse=NU_COARSE)
+    opts = ohm.default_opts(rtol=1e-10, precision=precision, max_iters=200, nu_pre=SCHEDULE[precision][0],
+                            nu_post=SCHEDULE[precision][1], nu_coarse=NU_COARSE)
     iters = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -159,7 +163,7 @@ def bench_batched(args):
     dts = [p["dt"] for p in probs]
     cells = sum(p["spec"].cells(0)[0] ** 3 for p in probs)
     best, table = tune.tune(H, [B0], [E], dts, finest_dx=min(p["spec"].dx0 for p in probs), precisions=(1,),
-                            use_cache=False, log=_log)
+                            use_cache=False, log=_log, quick=True)
     ws = ohm.Workspace()
     opts = ohm.default_opts(rtol=1e-10, max_iters=200, **best)
     for _ in range(args.warmup):
@@ -197,8 +201,8 @@ def bench_amr(args):
     out = {}
     for prec in (0, 1):
         ws = ohm.Workspace()
-        opts = ohm.default_opts(rtol=1e-10, max_iters=300, precision=prec, nu_pre=args.nu, nu_post=args.nu,
-                                nu_coarse=NU_COARSE)
+        opts = ohm.default_opts(rtol=1e-10, max_iters=300, precision=prec, nu_pre=args.nu or AMR_SCHEDULE[0],
+                                nu_post=args.nu or AMR_SCHEDULE[1], nu_coarse=NU_COARSE)
         for _ in range(args.warmup):
             ohm.ohm_cn_step(H, [b.clone() for b in B0], E, dt, opts, ws)
         Bs = [[b.clone() for b in B0] for _ in range(args.steps)]
@@ -215,7 +219,7 @@ def bench_amr(args):
             "vs_baseline": None, "dtype": "f64", "data": "synthetic",
             "config": {"workload": "amr2: 64^3 base + level 1 over the central 1/8 and 20% of other base blocks, "
                                    "dense-core eta, dt = 20x explicit on the fine level", "leaf_cells": cells,
-                       "iterations": stats["iters"], "V": args.nu},
+                       "iterations": stats["iters"], "V": [args.nu or AMR_SCHEDULE[0], args.nu or AMR_SCHEDULE[1]]},
             "mixed": {"value": cells / out[1][0], "ms_per_step": out[1][0] * 1e3, "iterations": out[1][1]["iters"]}}
 
 
@@ -281,7 +285,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=64, help="grid edge of the oracle sample (0: skip)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--workload", default="lognormal128", choices=["lognormal128", "batched", "serve", "amr"])
-    ap.add_argument("--nu", type=int, default=4, help="pre/post sweeps of the multigrid cycle")
+    ap.add_argument("--nu", type=int, default=None, help="pre and post sweeps of the AMR workload's cycle")
     ap.add_argument("--nprob", type=int, default=256)
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--pool", type=int, default=8)
@@ -349,7 +353,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"lognormal{n}: {n}^3 periodic, eta log-normal 4 decades, div-free k^-2 B, "
                                f"dt = 100x explicit limit, consecutive CN steps to rel. residual 1e-10",
-                   "cells": cells, "outer": "BiCGStab", "cycle": f"V({NU},{NU}), {NU_COARSE} sweep(s) below the base grid",
+                   "cells": cells, "outer": "BiCGStab",
+                   "cycle": f"V{SCHEDULE[0]} (FP64) / V{SCHEDULE[1]} (mixed), {NU_COARSE} sweep below the base grid",
                    "iterations_per_step": f64["iters"]},
         "roofline": {"kernel": "k_blk_sweep<double> (one fused red-black sweep, level 0)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

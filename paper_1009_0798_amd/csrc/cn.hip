@@ -300,9 +300,8 @@ struct Solver {
         const int d = -lev;
         const int nuc1 = o->nu_coarse > 0 ? o->nu_coarse : nu1, nuc2 = o->nu_coarse > 0 ? o->nu_coarse : nu2;
         OHM_TRY(smooth_dense(d, nuc1, active, false, zf));
-        OHM_TRY(launch_dense_stencil<T>(h, -d, MODE_RESID, dv(P.d_e, d), dv(P.d_rhs, d), dv(P.d_eta, d), lam_dt,
-                                        dv(P.d_res, d), 0, false, active, st));
-        OHM_TRY(launch_dense_restrict<T>(h, -d, dv(P.d_res, d), dv(P.d_rhs, d + 1), 3, active, st));
+        OHM_TRY(launch_dense_resid_restrict<T>(h, -d, dv(P.d_e, d), dv(P.d_rhs, d), dv(P.d_eta, d), lam_dt,
+                                               dv(P.d_res, d), dv(P.d_rhs, d + 1), active, st));
         OHM_TRY(down_dense(d + 1));
         if (nuc2 & 1) {
             OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), dv(P.d_e, d + 1), dv(P.d_tmp, d), 3, 1, active, st,

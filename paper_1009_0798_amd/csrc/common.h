@@ -236,6 +236,11 @@ template <typename T>
 ohm_status launch_dense_smooth(const ohm_hier *h, int level, T *B, T *tmp, const T *S, const T *eta,
                                const double *coef_dev, int nsweeps, bool all, const int *active, hipStream_t s,
                                int flags = 0);
+// dense level -> next coarser: coarse = restriction of S - L B; res is scratch
+// for handles where some continuing problem is not made of 8^3 tiles
+template <typename T>
+ohm_status launch_dense_resid_restrict(const ohm_hier *h, int level, const T *B, const T *S, const T *eta,
+                                       const double *coef_dev, T *res, T *coarse, const int *active, hipStream_t s);
 template <typename T>
 ohm_status launch_dense_restrict(const ohm_hier *h, int fine_level, const T *fine, T *coarse, int ncomp,
                                  const int *active, hipStream_t s);

@@ -136,6 +136,64 @@ k_dense_run_copy(const int *__restrict__ runs, const DenseProbDev *__restrict__ 
     for (int c = 0; c < 3; ++c) dst[c * cs + gi] = src ? src[c * cs + gi] : T(0);
 }
 
+// r = S - L e on one 8^3 tile of a dense level (one-cell periodic halo in
+// LDS) restricted straight to the next coarser level: the same residual and
+// the same 8-child sums as k_dense_stencil<RESID> followed by k_dense_restrict
+template <typename T>
+__global__ void __launch_bounds__(256)
+k_dense_resid_restrict(const int *__restrict__ ftiles, const DenseProbDev *__restrict__ dp,
+                       const DenseProbDev *__restrict__ cdp, const int *__restrict__ active,
+                       const double *__restrict__ coef_p, const T *__restrict__ B, const T *__restrict__ S,
+                       const T *__restrict__ eta, T *__restrict__ coarse, long long cs, long long ccs)
+{
+    constexpr int W = 10;
+    __shared__ T sB[3][W * W * W];
+    __shared__ T sE[W * W * W];
+    const int pr = ftiles[2 * blockIdx.x], tile = ftiles[2 * blockIdx.x + 1];
+    if (active && !active[pr]) return;
+    const DenseProbDev q = dp[pr];
+    const DenseAddr A = dense_tile(q, tile);
+    for (int t = threadIdx.x; t < W * W * W; t += blockDim.x) {
+        const long long gi = A.at(t % W - 1, (t / W) % W - 1, t / (W * W) - 1);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sB[c][t] = B[c * cs + gi];
+        sE[t] = eta[gi];
+    }
+    __syncthreads();
+    const T c8 = T(coef_p[pr]) * T(q.inv_h2) * T(0.125);
+    T r[2][3];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int cell = threadIdx.x + 256 * half;
+        const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
+        const int p = (x + 1) + W * ((y + 1) + W * (z + 1));
+        const long long gi = A.at(x, y, z);
+        T dv[3], al[3];
+        divF_all<T, W>(sB[0], sB[1], sB[2], sE, p, dv, al);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) r[half][c] = S[c * cs + gi] - fma(c8, dv[c], sB[c][p]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int half = 0; half < 2; ++half)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sB[c][threadIdx.x + 256 * half] = r[half][c];
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        const int i = threadIdx.x & 3, j = (threadIdx.x >> 2) & 3, k = threadIdx.x >> 4;
+        const DenseProbDev cq = cdp[pr];
+        const long long ci = cq.off + (A.ox / 2 + i) + (long long)cq.nx * ((A.oy / 2 + j) + (long long)cq.ny * (A.oz / 2 + k));
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            T a = T(0);
+            for (int dz = 0; dz < 2; ++dz)
+                for (int dy = 0; dy < 2; ++dy)
+                    for (int dx = 0; dx < 2; ++dx) a += sB[c][(2 * i + dx) + NB * ((2 * j + dy) + NB * (2 * k + dz))];
+            coarse[c * ccs + ci] = a * T(0.125);
+        }
+    }
+}
+
 // dense level -d -> -(d+1): mean of 8 children; one thread per coarse cell
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -441,6 +499,22 @@ ohm_status launch_dense_smooth(const ohm_hier *h, int level, T *B, T *tmp, const
 }
 
 template <typename T>
+ohm_status launch_dense_resid_restrict(const ohm_hier *h, int level, const T *B, const T *S, const T *eta,
+                                       const double *coef_dev, T *res, T *coarse, const int *active, hipStream_t s)
+{
+    const DenseLevelDev &D = h->dense[-level], &C = h->dense[-level + 1];
+    if (D.ntile == 0) return OHM_OK;
+    if (D.nptile > 0 || D.nftile == 0) {
+        // some continuing problem is not a whole number of 8^3 tiles
+        OHM_TRY(launch_dense_stencil<T>(h, level, MODE_RESID, B, S, eta, coef_dev, res, 0, false, active, s));
+        return launch_dense_restrict<T>(h, level, res, coarse, 3, active, s);
+    }
+    k_dense_resid_restrict<T><<<D.nftile, 256, 0, s>>>(D.ftiles, D.probs, C.probs, active, coef_dev, B, S, eta,
+                                                        coarse, D.ncells, C.ncells);
+    return check_launch("dense residual + restriction");
+}
+
+template <typename T>
 ohm_status launch_dense_restrict(const ohm_hier *h, int fine_level, const T *fine, T *coarse, int ncomp,
                                  const int *active, hipStream_t s)
 {
@@ -600,6 +674,8 @@ size_t coarse_job_bytes() { return sizeof(CoarseJob); }
                                                 const double *, T *, int, bool, const int *, hipStream_t);     \
     template ohm_status launch_dense_restrict<T>(const ohm_hier *, int, const T *, T *, int, const int *,      \
                                                  hipStream_t);                                                 \
+    template ohm_status launch_dense_resid_restrict<T>(const ohm_hier *, int, const T *, const T *, const T *, \
+                                                       const double *, T *, T *, const int *, hipStream_t);    \
     template ohm_status launch_dense_prolong<T>(const ohm_hier *, int, const T *, T *, int, int, const int *,  \
                                                 hipStream_t, const T *);                                       \
     template ohm_status launch_coarse_apply<T>(const ohm_hier *, int, const void *, int, const double *,       \

@@ -20,7 +20,7 @@ from . import Workspace, default_opts, ohm_cn_step
 
 CACHE = os.environ.get("OHM_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "ohm_tune.json"))
 
-SWEEPS = [(1, 1), (2, 2), (3, 3), (4, 4), (5, 5), (6, 6)]
+SWEEPS = [(n1, n2) for n1 in (1, 2, 3, 4) for n2 in (2, 3, 4, 5, 6)]   # (pre, post) on the base grid
 COARSE = [0, 1, 2]          # sweeps on the levels below the base grid (0 = same as the base grid)
 CYCLES = [0, 1]
 OUTERS = [1, 0]
@@ -60,8 +60,6 @@ def candidates(precisions=(0, 1), quick=False):
     cycles = [0] if quick else CYCLES
     outers = [1] if quick else OUTERS
     for (n1, n2), nc, cyc, outer, prec in itertools.product(SWEEPS, COARSE, cycles, outers, precisions):
-        if nc >= n1:
-            continue
         yield dict(nu_pre=n1, nu_post=n2, nu_coarse=nc, cycle=cyc, outer=outer, precision=prec)
 
 
