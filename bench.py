@@ -25,6 +25,7 @@ HBM_PEAK_GBS = 8000.0
 SCHEDULE = {0: (2, 5), 1: (3, 4)}
 NU_COARSE = 1
 AMR_SCHEDULE = (4, 4)
+SERVE_SCHEDULE = (2, 2, 0)   # (pre, post, below the base grid; 0 = as the base grid) for serving
 
 
 def sweep_source_hash() -> str:
@@ -242,15 +243,72 @@ def bench_serve(args):
         s = d["spec"]
         reqs.append(Request(rid=i, arrival=0.0, base_blocks=s.base_blocks, dx0=s.dx0, levels=s.levels, B=d["B"],
                             eta=d["eta"], dt=d["dt"]))
-    srv = Server(hbm_budget=int(args.hbm_gb * (1 << 30)), n_streams=args.streams, max_batch=args.max_batch)
+    sched = dict(zip(("nu_pre", "nu_post", "nu_coarse"), SERVE_SCHEDULE))
+    srv = Server(hbm_budget=int(args.hbm_gb * (1 << 30)), n_streams=args.streams, max_batch=args.max_batch, **sched)
     done = srv.serve(reqs, poisson_arrivals(args.rate, len(reqs), seed=7))
     rep = latency_report(done)
     return {"metric": METRIC, "value": rep["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": len(reqs),
             "warmup": 0, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f32 multigrid + f64 outer", "data": "synthetic",
             "config": {"workload": f"serve: Poisson {args.rate}/s, {len(reqs)} requests of 1-3 level AMR, base "
-                                   "32-192^3", "streams": args.streams, "max_batch": args.max_batch},
+                                   "32-192^3", "streams": args.streams, "max_batch": args.max_batch,
+                       "schedule": sched},
             "latency": rep}
+
+
+def bench_e8(args):
+    """The comparison of section 3.3 at its own size: 64^3 on [-4, 4)^3,
+    eta = exp(-r^2), B_z = exp(-(x^2 + y^2)), to t = 1: the explicit
+    predictor-corrector scheme with dt = 1e-3 (1000 steps) against the implicit
+    scheme with dt = 0.1 (10 steps, lambda = 1/2 and 1), FP64.  Reports the
+    time to solution of each and their differences."""
+    import numpy as np
+    import torch
+    import ohm_inputs as gen
+    import paper_1009_0798_amd as ohm
+    cfg = gen.config_e8(64)
+    spec = cfg["spec"]
+    ijk = spec.levels[0]
+    H = ohm.Hierarchy([(spec.base_blocks, spec.dx0, spec.levels)])
+    B0 = ohm.to_blocks(torch.from_numpy(cfg["B"]), ijk).cuda()
+    E = [ohm.to_blocks(torch.from_numpy(cfg["eta"])[None], ijk).cuda()]
+    nexp = int(round(cfg["t_end"] / cfg["dt_explicit"]))
+    nimp = int(round(cfg["t_end"] / cfg["dt_implicit"]))
+    ws = ohm.Workspace()
+    ohm.ohm_explicit_step(H, [B0.clone()], E, cfg["dt_explicit"], 10, ws)      # warm
+    Bx = B0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ohm.ohm_explicit_step(H, [Bx], E, cfg["dt_explicit"], nexp, ws)
+    torch.cuda.synchronize()
+    t_exp = time.perf_counter() - t0
+    out = {"explicit": {"steps": nexp, "dt": cfg["dt_explicit"], "seconds": t_exp}}
+    for lam in (0.5, 1.0):
+        opts = ohm.default_opts(rtol=1e-10, max_iters=200, lam=lam)
+        ohm.ohm_cn_step(H, [B0.clone()], E, cfg["dt_implicit"], opts, ws)        # warm
+        Bi = B0.clone()
+        its = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(nimp):
+            st, stats = ohm.ohm_cn_step(H, [Bi], E, cfg["dt_implicit"], opts, ws)
+            assert st == 0, st
+            its.append(stats[0]["iters"])
+        torch.cuda.synchronize()
+        t_imp = time.perf_counter() - t0
+        diff = float(torch.linalg.vector_norm(Bi - Bx) / torch.linalg.vector_norm(Bx))
+        out[f"implicit_lambda_{lam}"] = {"steps": nimp, "dt": cfg["dt_implicit"], "seconds": t_imp,
+                                         "iterations": its, "rel_diff_vs_explicit": diff}
+        _log(f"lambda {lam}: {t_imp * 1e3:.1f} ms for {nimp} steps, rel. diff. vs explicit {diff:.2e}")
+    _log(f"explicit: {t_exp * 1e3:.1f} ms for {nexp} steps")
+    cells = spec.cells(0)[0] ** 3
+    return {"metric": METRIC, "value": cells * nimp / out["implicit_lambda_0.5"]["seconds"], "unit": "cells/s",
+            "n_gpus": 1, "steps": nimp, "warmup": 1, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+            "config": {"workload": "e8: section 3.3 comparison, 64^3 on [-4,4)^3, eta = exp(-r^2), "
+                                   "B_z = exp(-(x^2+y^2)), t = 1", "cells": cells},
+            "comparison": out,
+            "speedup_to_solution_vs_explicit": t_exp / out["implicit_lambda_0.5"]["seconds"]}
 
 
 def roofline_probe(args):
@@ -284,7 +342,7 @@ def main():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--cpu-sample", type=int, default=64, help="grid edge of the oracle sample (0: skip)")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--workload", default="lognormal128", choices=["lognormal128", "batched", "serve", "amr"])
+    ap.add_argument("--workload", default="lognormal128", choices=["lognormal128", "batched", "serve", "amr", "e8"])
     ap.add_argument("--nu", type=int, default=None, help="pre and post sweeps of the AMR workload's cycle")
     ap.add_argument("--nprob", type=int, default=256)
     ap.add_argument("--requests", type=int, default=64)
@@ -311,6 +369,9 @@ def main():
         return
     if args.roofline_only:
         roofline_probe(args)
+        return
+    if args.workload == "e8":
+        print(json.dumps(bench_e8(args)), flush=True)
         return
     if args.workload == "batched":
         print(json.dumps(bench_batched(args)), flush=True)

@@ -233,6 +233,25 @@ ohm_status ohm_cn_step(ohm_hier *h, void *const B[], const void *const eta[], co
                        const ohm_cn_opts *opts, void *workspace, size_t ws_bytes,
                        ohm_cn_stats *stats, hipStream_t stream);
 
+/*
+ * Explicit comparison scheme of section 3.3: nsteps steps of size dt[p] of the
+ * predictor-corrector (Heun) update with the same flux divergence as the
+ * implicit operator (eqs. 8-11), on the composite leaf cells of every problem
+ * (coarse-fine faces refluxed as in ohm_cn_step, covered cells set to the mean
+ * of their children after each stage):
+ *   B* = B - dt div F(B),   B <- B - dt/2 (div F(B) + div F(B*)).
+ *   B[l], eta[l] : as for ohm_cn_step (FP64, device)
+ *   dt     : host double[nprob], > 0.  Stability is the caller's: the scheme is
+ *            stable for dt below about h^2 / (6 eta_max) on the finest level.
+ *   workspace : device memory of at least ohm_explicit_workspace_size bytes,
+ *            256-byte aligned (the same layout as the Crank-Nicolson workspace)
+ * Asynchronous except for a final synchronisation of `stream`.  Returns
+ * OHM_ERR_ARG for bad arguments, OHM_ERR_NOMEM for a short workspace.
+ */
+ohm_status ohm_explicit_workspace_size(const ohm_hier *h, size_t *bytes);
+ohm_status ohm_explicit_step(ohm_hier *h, void *const B[], const void *const eta[], const double *dt, int nsteps,
+                             void *workspace, size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -440,3 +440,16 @@ def amr_fields_fourier(spec: HierSpec, seed=5, eta_fn=dense_core_eta, origin=-0.
             ox, oy, oz = 4 * (bi & 1), 4 * (bj & 1), 4 * (bk & 1)
             Bs[l - 1][:, pi_, oz:oz + 4, oy:oy + 4, ox:ox + 4] = Bs[l][:, i].reshape(3, 4, 2, 4, 2, 4, 2).mean(axis=(2, 4, 6))
     return [np.ascontiguousarray(b) for b in Bs], es
+
+
+def config_e8(n=64, L=8.0):
+    """The explicit-comparison test of section 3.3: periodic box [-L/2, L/2)^3
+    resolved by n^3 cells, eta = exp(-r^2), B = (0, 0, exp(-(x^2 + y^2))),
+    run to t = 1 with dt = 1e-3 (explicit) and 1e-1 (implicit)."""
+    h = L / n
+    c = -L / 2 + (np.arange(n) + 0.5) * h
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    eta = np.exp(-(X * X + Y * Y + Z * Z))
+    B = np.zeros((3, n, n, n))
+    B[2] = np.exp(-(X * X + Y * Y))
+    return dict(spec=uniform_spec(n, dx=h), B=B, eta=eta, t_end=1.0, dt_explicit=1e-3, dt_implicit=1e-1)

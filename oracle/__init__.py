@@ -17,9 +17,11 @@ mg       -- the solvers: direct sparse solve, multigrid V-cycle, the paper's
             BiCGStab, one Crank-Nicolson step.
 amr      -- the composite operator on an AMR hierarchy: coarse-fine ghost
             interpolation and refluxing.
+explicit -- the explicit predictor-corrector comparison scheme of section 3.3
+            on one level and on an AMR hierarchy.
 closed   -- closed forms used as pins: the Fourier symbol of the discrete
-            operator, the exact discrete CN amplification per Fourier mode,
-            the continuum decay exp(-eta k^2 t).
+            operator, the exact discrete CN and explicit amplification per
+            Fourier mode, the continuum decay exp(-eta k^2 t).
 
 Parity status: every function is pinned by a test in tests/test_oracle_*.py,
 except the coarse-fine ghost interpolation rule itself (trilinear), which the

@@ -60,3 +60,39 @@ def heat_factor(kx, ky, h, eta0, dt, lam=0.5):
 def continuum_decay(k2, eta0, t):
     """exp(-eta |k|^2 t), the exact continuum decay of a Fourier mode (eq. 25)."""
     return np.exp(-eta0 * k2 * t)
+
+
+def heun_exact(b, eta0, h, dt, nsteps=1):
+    """``nsteps`` steps of the explicit predictor-corrector scheme for constant
+    resistivity, by FFT: each Fourier coefficient is multiplied by
+    E(k) = I - dt M + (dt M)^2 / 2 per step (B* = B - dt M B, then
+    B' = B - dt/2 (M B + M B*))."""
+    _, nz, ny, nx = b.shape
+    kx = 2 * np.pi * np.fft.fftfreq(nx, d=h)
+    ky = 2 * np.pi * np.fft.fftfreq(ny, d=h)
+    kz = 2 * np.pi * np.fft.fftfreq(nz, d=h)
+    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    A = dt * eta0 * symbol(KX, KY, KZ, h)
+    I = np.eye(3)
+    E = I - A + 0.5 * (A @ A)
+    En = np.linalg.matrix_power(E, nsteps)
+    bh = np.fft.fftn(b, axes=(1, 2, 3))
+    bh = np.moveaxis(bh, 0, -1)[..., None]
+    out = (En @ bh)[..., 0]
+    return np.real(np.fft.ifftn(np.moveaxis(out, -1, 0), axes=(1, 2, 3)))
+
+
+def semidiscrete_exact(b, eta0, h, t):
+    """The space-discrete, time-exact solution exp(-t eta M) b for constant
+    resistivity (M is symmetric per wavevector: eigendecomposition)."""
+    _, nz, ny, nx = b.shape
+    kx = 2 * np.pi * np.fft.fftfreq(nx, d=h)
+    ky = 2 * np.pi * np.fft.fftfreq(ny, d=h)
+    kz = 2 * np.pi * np.fft.fftfreq(nz, d=h)
+    KZ, KY, KX = np.meshgrid(kz, ky, kx, indexing="ij")
+    w, V = np.linalg.eigh(eta0 * symbol(KX, KY, KZ, h))
+    G = V @ (np.exp(-t * w)[..., None] * np.swapaxes(V, -1, -2))
+    bh = np.fft.fftn(b, axes=(1, 2, 3))
+    bh = np.moveaxis(bh, 0, -1)[..., None]
+    out = (G @ bh)[..., 0]
+    return np.real(np.fft.ifftn(np.moveaxis(out, -1, 0), axes=(1, 2, 3)))

@@ -191,6 +191,20 @@ def ohm_cn_step(h: Hierarchy, B, eta, dt, opts: CnOpts | None = None, workspace:
     return st, out
 
 
+def ohm_explicit_step(h: Hierarchy, B, eta, dt, nsteps: int, workspace: Workspace | None = None, stream=None):
+    """``nsteps`` explicit predictor-corrector steps of size ``dt`` in place on
+    the per-level FP64 fields ``B`` (the comparison scheme of section 3.3)."""
+    L = lib()
+    nb = ctypes.c_size_t()
+    check(L.ohm_explicit_workspace_size(h.h, ctypes.byref(nb)))
+    ws = workspace if workspace is not None else Workspace()
+    ptr, size = ws.get(nb.value)
+    Bp = (ctypes.c_void_p * len(B))(*[b.data_ptr() for b in B])
+    Ep = (ctypes.c_void_p * len(eta))(*[e.data_ptr() for e in eta])
+    check(L.ohm_explicit_step(h.h, Bp, Ep, _coef(h, dt), int(nsteps), ctypes.c_void_p(ptr), size,
+                              stream_ptr(stream)))
+
+
 def to_blocks(dense, block_ijk):
     """(ncomp, nz, ny, nx) tensor/array -> (ncomp, nb, 8, 8, 8) for the listed blocks."""
     ijk = np.asarray(block_ijk).reshape(-1, 3)

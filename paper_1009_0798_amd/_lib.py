@@ -22,7 +22,8 @@ STATUS_NAMES = {0: "OHM_OK", 1: "OHM_ERR_ARG", 2: "OHM_ERR_LAYOUT", 3: "OHM_ERR_
 
 EXPORTS = ["ohm_hier_create", "ohm_hier_destroy", "ohm_hier_level_info", "ohm_hier_problem_info",
            "ohm_last_error", "ohm_fill_ghosts", "ohm_apply", "ohm_residual", "ohm_smooth", "ohm_restrict",
-           "ohm_prolong", "ohm_reflux", "ohm_cn_default_opts", "ohm_cn_workspace_size", "ohm_cn_step"]
+           "ohm_prolong", "ohm_reflux", "ohm_cn_default_opts", "ohm_cn_workspace_size", "ohm_cn_step",
+           "ohm_explicit_workspace_size", "ohm_explicit_step"]
 
 
 class ProblemDesc(ctypes.Structure):
@@ -82,6 +83,8 @@ def lib() -> ctypes.CDLL:
             "ohm_cn_workspace_size": [P, ctypes.POINTER(CnOpts), ctypes.POINTER(ctypes.c_size_t)],
             "ohm_cn_step": [P, ctypes.POINTER(P), ctypes.POINTER(P), DP, ctypes.POINTER(CnOpts), P,
                             ctypes.c_size_t, ctypes.POINTER(CnStats), P],
+            "ohm_explicit_workspace_size": [P, ctypes.POINTER(ctypes.c_size_t)],
+            "ohm_explicit_step": [P, ctypes.POINTER(P), ctypes.POINTER(P), DP, I32, P, ctypes.c_size_t, P],
         }
         for name, args in sig.items():
             f = getattr(L, name)

@@ -382,7 +382,9 @@ struct Solver {
     }
 
     // ---- setup ----------------------------------------------------------------
-    ohm_status setup(const double *dt)
+    // multigrid = false: only what the explicit scheme needs (tables,
+    // coefficients, coarse-fine ghosts of eta, x = B)
+    ohm_status setup(const double *dt, bool multigrid = true)
     {
         const int np = h->nprob, L = nlev();
         VN = P.NBt * NC;
@@ -427,6 +429,12 @@ struct Solver {
         for (int l = 1; l < L; ++l)
             OHM_TRY(launch_fill_ghosts<double>(h, l, eta64(l - 1), (long long)h->nb_host[l - 1] * NC,
                                                at<double>(P.oeg) + P.LG[l] * NC, 0, 1, nullptr, st));
+        if (!multigrid) {
+            for (int l = 0; l < L; ++l)
+                OHM_TRY(vcopy_level<double, double>((const double *)Buser[l], (long long)h->nb_host[l] * NC,
+                                                    vec(P.x, l), VN, (long long)h->nb_host[l] * NC, 3, st));
+            return OHM_OK;
+        }
         if (P.T32) {
             for (int l = 0; l < L; ++l)
                 OHM_TRY(vconvert<double, T>(eta64(l), at<T>(P.eta_t) + P.LB[l] * NC, (long long)h->nb_host[l] * NC, st));
@@ -601,6 +609,25 @@ struct Solver {
             h->graph_opts = ob;
         }
         OHM_HIP(hipGraphLaunch(h->graph_exec, st));
+        return OHM_OK;
+    }
+
+    // nsteps of the explicit predictor-corrector scheme on x (coefficient
+    // slot neg_lam_dt holds -dt: the caller sets lambda = 1), then copy out
+    ohm_status run_explicit(int nsteps)
+    {
+        const int L = nlev();
+        for (int k = 0; k < nsteps; ++k) {
+            OHM_TRY(composite(P.x, P.p, MODE_APPLY, neg_lam_dt, neg_lam_dt, 0));    // p = x - dt div F(x)
+            OHM_TRY(composite(P.p, P.v, MODE_APPLY, neg_lam_dt, neg_lam_dt, 0));    // v = p - dt div F(p)
+            OHM_TRY(vmean2((int)P.NBt, mlprob, nullptr, VN, at<double>(P.x), at<double>(P.v), st));
+        }
+        for (int l = L - 1; l >= 1; --l)
+            OHM_TRY(launch_restrict_blk<double>(h, l, vec(P.x, l), VN, vec(P.x, l - 1), VN, 3, nullptr, st));
+        for (int l = 0; l < L; ++l)
+            OHM_TRY(vcopy_level<double, double>(vec(P.x, l), VN, (double *)Buser[l], (long long)h->nb_host[l] * NC,
+                                                (long long)h->nb_host[l] * NC, 3, st));
+        OHM_HIP(hipStreamSynchronize(st));
         return OHM_OK;
     }
 
@@ -786,6 +813,45 @@ ohm_status ohm_cn_step(ohm_hier *h, void *const B[], const void *const eta[], co
     S.Euser = eta;
     OHM_TRY(S.setup(dt));
     return S.run(stats);
+}
+
+ohm_status ohm_explicit_workspace_size(const ohm_hier *h, size_t *bytes)
+{
+    if (!h || !bytes) return fail(OHM_ERR_ARG, "NULL argument");
+    ohm_cn_opts o;
+    ohm_cn_default_opts(&o);
+    o.precision = 0;
+    *bytes = make_plan(h, &o).total;
+    return OHM_OK;
+}
+
+ohm_status ohm_explicit_step(ohm_hier *h, void *const B[], const void *const eta[], const double *dt, int nsteps,
+                             void *workspace, size_t ws_bytes, hipStream_t stream)
+{
+    if (!h) return fail(OHM_ERR_ARG, "handle is NULL");
+    if (!B || !eta || !dt) return fail(OHM_ERR_ARG, "NULL argument");
+    if (nsteps < 0) return fail(OHM_ERR_ARG, "nsteps must be >= 0, got %d", nsteps);
+    for (int l = 0; l < h->nlev; ++l)
+        if (!B[l] || !eta[l]) return fail(OHM_ERR_ARG, "B[%d] or eta[%d] is NULL", l, l);
+    ohm_cn_opts o;
+    ohm_cn_default_opts(&o);
+    o.precision = 0;
+    o.lambda = 1.0;    // the coefficient slot -lambda dt is then -dt
+    o.graph = 0;
+    Plan P = make_plan(h, &o);
+    if (!workspace || ws_bytes < P.total)
+        return fail(OHM_ERR_NOMEM, "workspace of %zu bytes is smaller than the %zu needed", ws_bytes, P.total);
+    if (((uintptr_t)workspace & 255) != 0) return fail(OHM_ERR_ARG, "workspace must be 256-byte aligned");
+    Solver<double> S;
+    S.h = h;
+    S.o = &o;
+    S.P = P;
+    S.ws = (char *)workspace;
+    S.st = stream;
+    S.Buser = B;
+    S.Euser = eta;
+    OHM_TRY(S.setup(dt, false));
+    return S.run_explicit(nsteps);
 }
 
 }  // extern "C"

@@ -275,6 +275,8 @@ ohm_status vbicg_s(int nblk, const int *prob_of, const int *active, long long cs
 ohm_status vbicg_xr(int nblk, const int *prob_of, const int *active, long long cs, const double *scal, double *x,
                     const double *ph, const double *sh, const double *sv, const double *t, double *r,
                     const double *rhat, double *part, hipStream_t s);
+ohm_status vmean2(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,
+                  hipStream_t s);
 ohm_status vaxpy1(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,
                   hipStream_t s);
 ohm_status vscal(int nprob, int stage, const int *active, const double *dots, int nq, double *scal, hipStream_t s);

@@ -198,6 +198,19 @@ k_axpy1(int nblk, const int *__restrict__ prob_of, const int *__restrict__ activ
     }
 }
 
+// x = (x + y) / 2 (the corrector of the explicit predictor-corrector step)
+__global__ void __launch_bounds__(256)
+k_mean2(int nblk, const int *__restrict__ prob_of, const int *__restrict__ active, long long cs,
+        double *__restrict__ x, const double *__restrict__ y)
+{
+    const int b = xcd_block2(blockIdx.x, nblk);
+    if (active && !active[prob_of[b]]) return;
+    for (int t = threadIdx.x; t < 3 * NC; t += 256) {
+        const long long gi = (t / NC) * cs + (long long)b * NC + t % NC;
+        x[gi] = 0.5 * (x[gi] + y[gi]);
+    }
+}
+
 // per-problem scalar updates (one thread per problem); `dots` holds the
 // reduced per-problem products of the preceding dot kernel
 __global__ void k_scal(int nprob, int stage, const int *__restrict__ active, const double *__restrict__ dots, int nq,
@@ -296,6 +309,13 @@ ohm_status vbicg_xr(int nblk, const int *prob_of, const int *active, long long c
 {
     k_bicg_xr<<<nblk, 256, 0, s>>>(nblk, prob_of, active, cs, scal, x, ph, sh, sv, t, r, rhat, part);
     return check_launch("bicg xr");
+}
+
+ohm_status vmean2(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,
+                  hipStream_t s)
+{
+    k_mean2<<<nblk, 256, 0, s>>>(nblk, prob_of, active, cs, x, y);
+    return check_launch("mean of two vectors");
 }
 
 ohm_status vaxpy1(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,

@@ -69,13 +69,15 @@ def footprint(req: Request, opts) -> int:
 
 class Server:
     def __init__(self, hbm_budget: int, n_streams: int = 2, max_batch: int = 32, precision: int = 1,
-                 rtol: float = 1e-10):
+                 rtol: float = 1e-10, **schedule):
+        """``schedule``: further ``ohm_cn_opts`` fields (nu_pre, nu_post,
+        nu_coarse, cycle, outer) applied to every batch."""
         import torch
         self.budget = int(hbm_budget)
         self.free = int(hbm_budget)
         self.n_streams = n_streams
         self.max_batch = max_batch
-        self.opts = default_opts(rtol=rtol, precision=precision, max_iters=300)
+        self.opts = default_opts(rtol=rtol, precision=precision, max_iters=300, **schedule)
         self.lock = threading.Condition()
         self.waiting: deque = deque()       # arrived, not admitted
         self.admitted: deque = deque()      # admitted, not started
