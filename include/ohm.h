@@ -101,7 +101,8 @@ ohm_status ohm_hier_level_info(const ohm_hier *h, int32_t level, int64_t *nblock
 /* Per-problem placement at `level`: first cell of the problem inside a field of
  * that level (*cell_offset; -1 if the problem lacks the level) and, for levels
  * < 0, the dense grid size dims[3] (x, y, z).  Also the deepest multigrid level
- * of the problem (*min_level <= 0). */
+ * of the problem (*min_level <= 0).  On levels < 0 every problem starts on a
+ * 64-cell boundary; the cells between problems are unused. */
 ohm_status ohm_hier_problem_info(const ohm_hier *h, int32_t prob, int32_t level,
                                  int64_t *cell_offset, int32_t dims[3], int32_t *min_level);
 
@@ -150,7 +151,10 @@ ohm_status ohm_residual(ohm_hier *h, int32_t level, const void *B, const void *B
  * each a red half-sweep ((i+j+k) even in level-global cell indices) then a
  * black one.  All cells of a colour update together from the state at the
  * start of the half-sweep: B_c += R_c / (1 + alpha_c).  Ghost values are held
- * fixed.  `tmp` is caller scratch of the size of B; B holds the result.
+ * fixed.  `tmp` is caller scratch of the size of B; B holds the result.  On
+ * levels whose blocks all have their 26 neighbours one launch performs a whole
+ * sweep; it needs B and eta aligned to 2 elements (OHM_ERR_ARG otherwise) and
+ * each field array of the level below 4 GiB.
  */
 ohm_status ohm_smooth(ohm_hier *h, int32_t level, void *B, const void *B_ghost, const void *S,
                       const void *eta, const void *eta_ghost, const double *lam_dt,

@@ -189,12 +189,15 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
                 P.nb[l] = 0;
             }
         }
+    // dense levels: each problem's array starts on a 64-cell boundary (the
+    // fused sweeps load aligned pairs), the gaps are never read or written
     for (int dd = 1; dd <= -H->min_level; ++dd) {
         long long c = 0;
         for (auto &P : H->probs) {
             if (-P.min_level >= dd) {
                 P.doff[dd] = c;
                 c += (long long)P.dims[dd][0] * P.dims[dd][1] * P.dims[dd][2];
+                c = (c + 63) & ~63LL;
             } else {
                 P.doff[dd] = -1;
             }

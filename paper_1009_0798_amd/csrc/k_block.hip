@@ -607,6 +607,9 @@ ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long 
     if ((unsigned long long)L.nb * NC * sizeof(T) > 0xFFFFFFFFull)
         return fail(OHM_ERR_ARG, "level %d: fused sweep addresses each field array with 32-bit offsets (max 4 GiB)",
                     level);
+    if (((uintptr_t)B | (uintptr_t)eta | (uintptr_t)(cs * sizeof(T))) % (2 * sizeof(T)) != 0)
+        return fail(OHM_ERR_ARG, "level %d: fused sweep needs B, eta and the component stride %zu-byte aligned", level,
+                    2 * sizeof(T));
     if (coarse) {
         if (level != 0 || h->min_level > -1 || !B)
             return fail(OHM_ERR_ARG, "a fused coarse correction needs level 0, a dense level below it and an input");

@@ -26,6 +26,12 @@ constexpr int TC2 = TW2 * TW2 * TW2;
 
 __device__ __forceinline__ int tix2(int x, int y, int z) { return (x + 2) + TW2 * ((y + 2) + TW2 * (z + 2)); }
 
+// two consecutive elements, loaded and stored as one 2 sizeof(T) access
+template <typename T>
+struct alignas(2 * sizeof(T)) Pair {
+    T a, b;
+};
+
 template <typename T>
 struct NoCoarse {
     static constexpr bool active = false;
@@ -44,6 +50,11 @@ __device__ __forceinline__ T load_at(const T *base, unsigned off)
     return *(const T *)((const char *)base + off);
 }
 template <typename T>
+__device__ __forceinline__ Pair<T> load_pair(const T *base, unsigned off)
+{
+    return *(const Pair<T> *)((const char *)base + off);
+}
+template <typename T>
 __device__ __forceinline__ void store_at(T *base, unsigned off, T v)
 {
     *(T *)((char *)base + off) = v;
@@ -58,24 +69,26 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
     const int u = threadIdx.x;
     const T *B0 = B, *B1 = ZERO ? B : B + cs, *B2 = ZERO ? B : B + 2 * cs;
     const T *S0 = S, *S1 = S + cs, *S2 = S + 2 * cs;
-    // tile load: thread u < 432 owns the column (x, y) = u mod 144 of the tile
-    // and four consecutive z; all global loads first, then the LDS stores
-    constexpr int NCOL = TW2 * TW2;
-    const bool loader = u < 3 * NCOL;
-    const int col = u % NCOL, zg = u / NCOL;
-    const int x = col % TW2 - 2, y = col / TW2 - 2;
-    T v[4][4];
+    // tile load in pairs of x-neighbours (x even, so a pair never straddles a
+    // block or a periodic wrap and is 2 sizeof(T) aligned): thread u < 432
+    // owns pair column (px, y) = u mod 72 and the planes z = 2 (u / 72) - 2
+    // and the next one; all global loads first, then the LDS stores
+    constexpr int NPC = (TW2 / 2) * TW2;     // pair columns per plane
+    const bool loader = u < 6 * NPC;
+    const int pc = u % NPC, zq = u / NPC;
+    const int x = 2 * (pc % (TW2 / 2)) - 2, y = pc / (TW2 / 2) - 2;
+    Pair<T> v[2][4];
     if (Coarse::active) cor.load();
     if (loader) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const unsigned off = (unsigned)A.at(x, y, 4 * zg + k - 2) * (unsigned)sizeof(T);
+        for (int k = 0; k < 2; ++k) {
+            const unsigned off = (unsigned)A.at(x, y, 2 * zq + k - 2) * (unsigned)sizeof(T);
             if (!ZERO) {
-                v[k][0] = load_at(B0, off);
-                v[k][1] = load_at(B1, off);
-                v[k][2] = load_at(B2, off);
+                v[k][0] = load_pair(B0, off);
+                v[k][1] = load_pair(B1, off);
+                v[k][2] = load_pair(B2, off);
             }
-            v[k][3] = load_at(eta, off);
+            v[k][3] = load_pair(eta, off);
         }
     }
     if (Coarse::active) {
@@ -84,12 +97,17 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
     }
     if (loader) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int z = 4 * zg + k - 2;
-            const int t = col + NCOL * (z + 2);
+        for (int k = 0; k < 2; ++k) {
+            const int z = 2 * zq + k - 2;
+            const int t = tix2(x, y, z);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) sB[c][t] = cor.add(x, y, z, c, ZERO ? T(0) : v[k][c]);
-            sE[t] = v[k][3];
+            for (int c = 0; c < 3; ++c) {
+                Pair<T> w;
+                w.a = cor.add(x, y, z, c, ZERO ? T(0) : v[k][c].a);
+                w.b = cor.add(x + 1, y, z, c, ZERO ? T(0) : v[k][c].b);
+                *(Pair<T> *)&sB[c][t] = w;
+            }
+            *(Pair<T> *)&sE[t] = v[k][3];
         }
     }
     __syncthreads();
