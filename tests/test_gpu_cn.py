@@ -67,6 +67,29 @@ def test_lognormal32_against_oracle(precision, outer, cycle):
     assert np.linalg.norm(R) <= 1.01 * RTOL * np.linalg.norm(S)
 
 
+@pytest.mark.parametrize("nu_pre,nu_post,nu_coarse,precision",
+                         [(1, 1, 1, 0), (2, 3, 1, 0), (3, 4, 2, 1), (2, 5, 1, 0), (4, 2, 3, 1), (0, 2, 0, 0)])
+def test_cycle_schedules_against_oracle(nu_pre, nu_post, nu_coarse, precision):
+    """Odd and even pre/post sweep counts take different buffer paths (zero-
+    guess first sweep into either buffer, correction fused into the first
+    post-sweep or prolonged into the scratch buffer, dense levels likewise):
+    every schedule must reach the oracle's answer."""
+    announce(f"cn schedule V({nu_pre},{nu_post}) coarse {nu_coarse} precision {precision}")
+    n = 32
+    spec = gen.uniform_spec(n)
+    h = spec.dx0
+    eta = gen.lognormal_eta(n, 3.0, seed=25)
+    B = gen.divfree(n, 2.0, seed=26)
+    dt = gen.explicit_dt(h, 1.0, 60.0)
+    st, stats, got = _gpu_step(spec, B, eta, dt, precision=precision, max_iters=400, nu_pre=nu_pre,
+                               nu_post=nu_post, nu_coarse=nu_coarse)
+    ex, _ = mg.cn_step(B, eta, h, dt, rtol=1e-13)
+    S = ref.source(B, eta, h, dt)
+    print("stats", stats)
+    assert st == 0 and stats[0]["rel_res"] <= RTOL
+    assert np.linalg.norm(got - ex) <= _bound(np.linalg.norm(S), ex)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_backward_euler_against_oracle(precision):
     """lambda = 1 (eq. 7): S = b and L = I + dt div F."""
