@@ -25,27 +25,50 @@ __device__ __forceinline__ int xcd_block(int w, int n)
 
 __device__ __forceinline__ int side(int c) { return c < 0 ? -1 : (c >= NB ? 1 : 0); }
 
-// Load component arrays of block b plus halo into LDS tile(s).
-template <typename T, int NCOMP>
-__device__ __forceinline__ void load_tile(T (*tile)[TC], const T *f, const T *g, long long cs,
-                                          long long gcs, const int *nbr)
+// B (3 components) and eta of block b plus the one-cell halo into LDS: thread
+// u < 200 owns tile column (x, y) = u mod 100 and five consecutive z, issues
+// all its global loads, then stores them (ghost blocks for negative
+// neighbour entries, zeros for absent corner blocks)
+template <typename T>
+__device__ __forceinline__ void load_tile_b_eta(T (*sB)[TC], T *sE, const T *f, const T *g, long long cs,
+                                                long long gcs, const T *eta, const T *etag, const int *nbr)
 {
-    for (int t = threadIdx.x; t < TC; t += blockDim.x) {
-        int x = t % TW - 1, y = (t / TW) % TW - 1, z = t / (TW * TW) - 1;
-        int sx = side(x), sy = side(y), sz = side(z);
-        int n = nbr[(sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
-        int li = (x - NB * sx) + NB * ((y - NB * sy) + NB * (z - NB * sz));
+    const int u = threadIdx.x;
+    if (u >= 2 * TW * TW) return;
+    const int col = u % (TW * TW), zh = u / (TW * TW);
+    const int x = col % TW - 1, y = col / TW - 1;
+    const int sx = side(x), sy = side(y);
+    const int lxy = (x - NB * sx) + NB * (y - NB * sy);
+    const int sxy = (sx + 1) + 3 * (sy + 1);
+    T v[5][4];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int z = 5 * zh + k - 1, sz = side(z);
+        const int n = nbr[sxy + 9 * (sz + 1)];
+        const int li = lxy + NB * NB * (z - NB * sz);
         if (n >= 0) {
-#pragma unroll
-            for (int c = 0; c < NCOMP; ++c) tile[c][t] = f[c * cs + (long long)n * NC + li];
+            const long long gi = (long long)n * NC + li;
+            v[k][0] = f[gi];
+            v[k][1] = f[cs + gi];
+            v[k][2] = f[2 * cs + gi];
+            v[k][3] = eta[gi];
         } else if (n != NBR_NONE) {
-            int gi = -1 - n;
-#pragma unroll
-            for (int c = 0; c < NCOMP; ++c) tile[c][t] = g[c * gcs + (long long)gi * NC + li];
+            const long long gi = (long long)(-1 - n) * NC + li;
+            v[k][0] = g[gi];
+            v[k][1] = g[gcs + gi];
+            v[k][2] = g[2 * gcs + gi];
+            v[k][3] = etag[gi];
         } else {
-#pragma unroll
-            for (int c = 0; c < NCOMP; ++c) tile[c][t] = T(0);
+            v[k][0] = v[k][1] = v[k][2] = v[k][3] = T(0);
         }
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int t = col + TW * TW * (5 * zh + k);
+        sB[0][t] = v[k][0];
+        sB[1][t] = v[k][1];
+        sB[2][t] = v[k][2];
+        sE[t] = v[k][3];
     }
 }
 
@@ -71,8 +94,7 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
     }
     if (threadIdx.x < 27) snbr[threadIdx.x] = nbr_tab[27 * (long long)b + threadIdx.x];
     __syncthreads();
-    load_tile<T, 3>(sB, B, Bg, cs, gcs, snbr);
-    load_tile<T, 1>(sE, eta, etag, 0, 0, snbr);
+    load_tile_b_eta<T>(sB, sE[0], B, Bg, cs, gcs, eta, etag, snbr);
     __syncthreads();
     const T cih2 = T(coef_p[pr]) * T(inv_h2_p[pr]);
     const T c8 = cih2 * T(0.125), c2 = cih2 * T(0.5);
