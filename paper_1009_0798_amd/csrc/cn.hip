@@ -167,17 +167,25 @@ struct Solver {
         return launch_reduce_problem(h->nprob, nlev(), at<long long>(P.ranges), at<double>(P.part), k, ksum, out, st);
     }
 
-    ohm_status dots(const double *const *x, const double *const *y, int nq)
+    ohm_status dots(const double *const *x, const double *const *y, int nq, int stage = -1)
     {
         OHM_TRY(vdot((int)P.NBt, mlprob, active, VN, x, y, nq, at<double>(P.part), st));
-        return reduce(nq, nq, at<double>(P.dots));
+        return reduce_scal(nq, stage);
+    }
+    // per-problem sums of the nq partials into dots, then BiCGStab scalar
+    // update `stage` (< 0: none), one launch
+    ohm_status reduce_scal(int nq, int stage)
+    {
+        return launch_reduce_scal(h->nprob, nlev(), at<long long>(P.ranges), at<double>(P.part), nq,
+                                  at<double>(P.dots), stage, active, at<double>(P.scal), st);
     }
 
     // y = L x (lam dt) followed by the per-problem dots (xs[q], ys[q]), where
     // every xs[q] or ys[q] is y itself or another vector.  One level: the dot
     // partials come out of the operator kernel (same summation order as the
     // dot kernel); AMR: the refluxed operator first, then the dot kernel.
-    ohm_status apply_dots(size_t xo, size_t yo, const double *const *xs, const double *const *ys, int nq)
+    ohm_status apply_dots(size_t xo, size_t yo, const double *const *xs, const double *const *ys, int nq,
+                          int stage = -1)
     {
         if (nlev() == 1) {
             const double *y = at<double>(yo);
@@ -189,10 +197,10 @@ struct Solver {
             OHM_TRY(launch_blk_stencil<double>(h, 0, MODE_APPLY, vec(xo, 0), at<double>(P.og) + P.LG[0] * NC, VN,
                                                GN, nullptr, eta64(0), etag64(0), lam_dt, vec(yo, 0), 0, nullptr,
                                                nullptr, active, st, sd));
-            return reduce(nq, nq, at<double>(P.dots));
+            return reduce_scal(nq, stage);
         }
         OHM_TRY(composite(xo, yo, MODE_APPLY, lam_dt, lam_dt, 0));
-        return dots(xs, ys, nq);
+        return dots(xs, ys, nq, stage);
     }
 
     // ---- multigrid cycle (precision T) ----------------------------------------
@@ -521,15 +529,14 @@ struct Solver {
     // one BiCGStab iteration (device work only; the host reads the norms)
     ohm_status bicg_iter()
     {
-        const int np = h->nprob;
-            OHM_TRY(vscal(np, 1, active, at<double>(P.dots), 1, at<double>(P.scal), st));
+            // beta and rho were formed by the scalar update that closed the
+            // previous iteration (or the restart)
             OHM_TRY(vbicg_p((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.r),
                             at<double>(P.v), at<double>(P.p), st));
             OHM_TRY(precond(P.p, P.ph));
             {
                 const double *xs[1] = {at<double>(P.rhat)}, *ys[1] = {at<double>(P.v)};
-                OHM_TRY(apply_dots(P.ph, P.v, xs, ys, 1));
-                OHM_TRY(vscal(np, 2, active, at<double>(P.dots), 1, at<double>(P.scal), st));
+                OHM_TRY(apply_dots(P.ph, P.v, xs, ys, 1, 2));
             }
             OHM_TRY(vbicg_s((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.r),
                             at<double>(P.v), at<double>(P.s), st));
@@ -537,14 +544,12 @@ struct Solver {
             {
                 const double *xs[2] = {at<double>(P.t), at<double>(P.t)},
                              *ys[2] = {at<double>(P.s), at<double>(P.t)};
-                OHM_TRY(apply_dots(P.sh, P.t, xs, ys, 2));
-                OHM_TRY(vscal(np, 3, active, at<double>(P.dots), 2, at<double>(P.scal), st));
+                OHM_TRY(apply_dots(P.sh, P.t, xs, ys, 2, 3));
             }
             OHM_TRY(vbicg_xr((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.x),
                              at<double>(P.ph), at<double>(P.sh), at<double>(P.s), at<double>(P.t),
                              at<double>(P.r), at<double>(P.rhat), at<double>(P.part), st));
-            OHM_TRY(reduce(2, 2, at<double>(P.dots)));
-            OHM_TRY(vscal(np, 4, active, at<double>(P.dots), 2, at<double>(P.scal), st));
+            OHM_TRY(reduce_scal(2, 4));
         return OHM_OK;
     }
 
@@ -683,8 +688,7 @@ struct Solver {
                 OHM_TRY(vfill<double>(at<double>(P.v), n, 0.0, st));
                 {
                     const double *xs[1] = {at<double>(P.r)};
-                    OHM_TRY(dots(xs, xs, 1));
-                    OHM_TRY(vscal(np, 0, active, at<double>(P.dots), 1, at<double>(P.scal), st));
+                    OHM_TRY(dots(xs, xs, 1, 0));
                 }
                 std::vector<int> inner(act);
                 while (it_total < maxit) {

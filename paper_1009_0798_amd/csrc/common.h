@@ -275,6 +275,10 @@ ohm_status vbicg_s(int nblk, const int *prob_of, const int *active, long long cs
 ohm_status vbicg_xr(int nblk, const int *prob_of, const int *active, long long cs, const double *scal, double *x,
                     const double *ph, const double *sh, const double *sv, const double *t, double *r,
                     const double *rhat, double *part, hipStream_t s);
+// per-problem sums of k <= 4 block partials into out[p][k], then the BiCGStab
+// scalar update `stage` (< 0: none) for the active problems
+ohm_status launch_reduce_scal(int nprob, int nrange, const long long *range_dev, const double *part, int k,
+                              double *out, int stage, const int *active, double *scal, hipStream_t s);
 ohm_status vmean2(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,
                   hipStream_t s);
 ohm_status vaxpy1(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,

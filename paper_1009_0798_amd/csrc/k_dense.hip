@@ -153,11 +153,26 @@ k_dense_resid_restrict(const int *__restrict__ ftiles, const DenseProbDev *__res
     if (active && !active[pr]) return;
     const DenseProbDev q = dp[pr];
     const DenseAddr A = dense_tile(q, tile);
-    for (int t = threadIdx.x; t < W * W * W; t += blockDim.x) {
-        const long long gi = A.at(t % W - 1, (t / W) % W - 1, t / (W * W) - 1);
+    // thread u < 200 owns tile column (x, y) = u mod 100 and five z: all loads
+    // first, then the LDS stores
+    if (threadIdx.x < 2 * W * W) {
+        const int col = threadIdx.x % (W * W), zh = threadIdx.x / (W * W);
+        const int x = col % W - 1, y = col / W - 1;
+        T v[5][4];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) sB[c][t] = B[c * cs + gi];
-        sE[t] = eta[gi];
+        for (int k = 0; k < 5; ++k) {
+            const long long gi = A.at(x, y, 5 * zh + k - 1);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) v[k][c] = B[c * cs + gi];
+            v[k][3] = eta[gi];
+        }
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+            const int t = col + W * W * (5 * zh + k);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sB[c][t] = v[k][c];
+            sE[t] = v[k][3];
+        }
     }
     __syncthreads();
     const T c8 = T(coef_p[pr]) * T(q.inv_h2) * T(0.125);

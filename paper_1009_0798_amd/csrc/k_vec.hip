@@ -211,16 +211,11 @@ k_mean2(int nblk, const int *__restrict__ prob_of, const int *__restrict__ activ
     }
 }
 
-// per-problem scalar updates (one thread per problem); `dots` holds the
-// reduced per-problem products of the preceding dot kernel
-__global__ void k_scal(int nprob, int stage, const int *__restrict__ active, const double *__restrict__ dots, int nq,
-                       double *__restrict__ scal)
+// BiCGStab scalars of one problem from the reduced products d of the
+// preceding dot kernel.  Stages 0 (restart) and 4 (after the x / r update)
+// also form beta and rho for the next iteration's direction update.
+__device__ __forceinline__ void scal_update(int stage, double *S, const double *d)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nprob) return;
-    if (active && !active[p]) return;
-    double *S = scal + SC_N * p;
-    const double *d = dots + (long long)nq * p;
     switch (stage) {
     case 0:  // restart: rho = alpha = omega = 1, rho_new = (rhat, r) = (r, r)
         S[SC_RHO] = 1.0;
@@ -229,12 +224,6 @@ __global__ void k_scal(int nprob, int stage, const int *__restrict__ active, con
         S[SC_RHONEW] = d[0];
         S[SC_RR] = d[0];
         break;
-    case 1: {  // beta from rho_new; rho <- rho_new
-        const double rn = S[SC_RHONEW];
-        S[SC_BETA] = (rn / S[SC_RHO]) * (S[SC_ALPHA] / S[SC_OMEGA]);
-        S[SC_RHO] = rn;
-        break;
-    }
     case 2:  // alpha = rho / (rhat, v)
         S[SC_ALPHA] = (d[0] != 0.0) ? S[SC_RHO] / d[0] : 0.0;
         break;
@@ -245,6 +234,60 @@ __global__ void k_scal(int nprob, int stage, const int *__restrict__ active, con
         S[SC_RR] = d[0];
         S[SC_RHONEW] = d[1];
         break;
+    }
+    if (stage == 0 || stage == 4) {  // beta from rho_new; rho <- rho_new
+        const double rn = S[SC_RHONEW];
+        S[SC_BETA] = (rn / S[SC_RHO]) * (S[SC_ALPHA] / S[SC_OMEGA]);
+        S[SC_RHO] = rn;
+    }
+}
+
+// per-problem scalar updates (one thread per problem) from reduced products
+__global__ void k_scal(int nprob, int stage, const int *__restrict__ active, const double *__restrict__ dots, int nq,
+                       double *__restrict__ scal)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob) return;
+    if (active && !active[p]) return;
+    scal_update(stage, scal + SC_N * p, dots + (long long)nq * p);
+}
+
+// Per-problem sums of k block partials (part[block][k]) followed by the
+// scalar update of `stage` (stage < 0: sums only).  One workgroup per problem,
+// 256 threads per quantity; every sum is formed exactly as by the block
+// reduction kernel (thread t owns the problem-local indices = t mod 256, wave
+// shuffle, then the 4 wavefronts in order), so results do not depend on the
+// other problems of the handle.
+__global__ void __launch_bounds__(1024)
+k_reduce_scal(int nrange, const long long *__restrict__ range, const double *__restrict__ part, int k,
+              double *__restrict__ out, int stage, const int *__restrict__ active, double *__restrict__ scal)
+{
+    __shared__ double sred[4][4];
+    const int p = blockIdx.x;
+    const int g = threadIdx.x >> 8, tid = threadIdx.x & 255;
+    if (g < k) {
+        double v = 0.0;
+        long long base = 0;
+        for (int r = 0; r < nrange; ++r) {
+            const long long b0 = range[2 * ((long long)p * nrange + r)], b1 = range[2 * ((long long)p * nrange + r) + 1];
+            const long long n = b1 - b0;
+            const long long first = ((tid - base) % 256 + 256) % 256;
+            for (long long i = first; i < n; i += 256) v = v + part[(b0 + i) * k + g];
+            base += n;
+        }
+        for (int o = 32; o > 0; o >>= 1) v = v + __shfl_down(v, o, 64);
+        if ((tid & 63) == 0) sred[g][tid >> 6] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double d[4];
+        for (int q = 0; q < k; ++q) {
+            double t = sred[q][0];
+            for (int w = 1; w < 4; ++w) t = t + sred[q][w];
+            d[q] = t;
+            out[(long long)p * k + q] = t;
+        }
+        if (stage >= 0 && !(active && !active[p])) scal_update(stage, scal + SC_N * p, d);
     }
 }
 
@@ -309,6 +352,14 @@ ohm_status vbicg_xr(int nblk, const int *prob_of, const int *active, long long c
 {
     k_bicg_xr<<<nblk, 256, 0, s>>>(nblk, prob_of, active, cs, scal, x, ph, sh, sv, t, r, rhat, part);
     return check_launch("bicg xr");
+}
+
+ohm_status launch_reduce_scal(int nprob, int nrange, const long long *range_dev, const double *part, int k,
+                              double *out, int stage, const int *active, double *scal, hipStream_t s)
+{
+    if (k < 1 || k > 4) return fail(OHM_ERR_ARG, "reduce + scalars takes 1 to 4 quantities, got %d", k);
+    k_reduce_scal<<<nprob, 256 * k, 0, s>>>(nrange, range_dev, part, k, out, stage, active, scal);
+    return check_launch("reduce + scalars");
 }
 
 ohm_status vmean2(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,
