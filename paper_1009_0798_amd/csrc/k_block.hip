@@ -473,26 +473,29 @@ __device__ T face_flux_h(const T *Bf, const T *Bg, long long cs, long long gcs, 
     return ef * (tr - (F(qd, c) - F(a, c)));
 }
 
+// One workgroup per 64 entries (coarse cells next to covered cells); thread t
+// handles face t mod 6 of entry t / 6 (both tangential components), then the
+// 6 face contributions of each entry are summed in face order.
+constexpr int RF_PER_WG = 64;
+
 template <typename T>
-__global__ void __launch_bounds__(128)
+__global__ void __launch_bounds__(RF_PER_WG * 6)
 k_reflux(int nrf, const int *__restrict__ rf, const int *__restrict__ active, const int *__restrict__ cnbr,
          const int *__restrict__ fnbr, const double *__restrict__ inv_h_c, const double *__restrict__ coef_p,
          const T *__restrict__ Bc, long long ccs, const T *__restrict__ Ec, const T *__restrict__ Bf,
          long long fcs, const T *__restrict__ Bfg, long long fgcs, const T *__restrict__ Ef,
          const T *__restrict__ Efg, T *__restrict__ out)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= nrf) return;
-    const int *ent = rf + RF_INTS * (long long)e;
-    const int pr = ent[15];
-    if (active && !active[pr]) return;
-    const int cb = ent[0], cell = ent[1], mask = ent[2];
-    const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
-    const T ih = T(inv_h_c[pr]);       // coarse 1/h; fine fluxes carry h_f = h/2
-    const T coef = T(coef_p[pr]);
+    __shared__ T sadd[RF_PER_WG][6][3];
+    const int el = threadIdx.x / 6, f = threadIdx.x % 6;
+    const int e = blockIdx.x * RF_PER_WG + el;
     T add[3] = {T(0), T(0), T(0)};
-    for (int f = 0; f < 6; ++f) {
-        if (!((mask >> f) & 1)) continue;
+    const int *ent = rf + RF_INTS * (long long)e;
+    const bool live = e < nrf && !(active && !active[ent[15]]);
+    if (live && ((ent[2] >> f) & 1)) {
+        const int pr = ent[15], cb = ent[0], cell = ent[1];
+        const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
+        const T ih = T(inv_h_c[pr]);       // coarse 1/h; fine fluxes carry h_f = h/2
         const int d = f >> 1;
         const int sg = (f & 1) ? -1 : 1;
         const int fb = ent[3 + f], fbase = ent[9 + f];
@@ -502,7 +505,7 @@ k_reflux(int nrf, const int *__restrict__ rf, const int *__restrict__ active, co
             // coarse flux on the face: after cell p (sg = +1) or after p - e_d
             int qc[3] = {x, y, z};
             if (sg < 0) qc[d] -= 1;
-            T Fc = face_flux_h<T>(Bc, Bc, ccs, ccs, Ec, Ec, cnbr, cb, qc, d, c) * ih;
+            const T Fc = face_flux_h<T>(Bc, Bc, ccs, ccs, Ec, Ec, cnbr, cb, qc, d, c) * ih;
             // the 4 fine faces: the covered-side children start at fbase; the
             // face is after the child (sg < 0) or after the child - e_d (sg > 0)
             T Ff = T(0);
@@ -516,12 +519,29 @@ k_reflux(int nrf, const int *__restrict__ rf, const int *__restrict__ active, co
                     Ff += face_flux_h<T>(Bf, Bfg, fcs, fgcs, Ef, Efg, fnbr, fb, q, d, c);
                 }
             Ff *= T(0.25) * (ih * T(2));
-            add[c] += T(sg) * (Ff - Fc) * ih;
+            add[c] = T(sg) * (Ff - Fc) * ih;
         }
     }
-    const long long gi = (long long)cb * NC + cell;
-    for (int c = 0; c < 3; ++c)
-        if (add[c] != T(0)) out[c * ccs + gi] += coef * add[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) sadd[el][f][c] = add[c];
+    __syncthreads();
+    if (threadIdx.x < RF_PER_WG) {
+        const int e2 = blockIdx.x * RF_PER_WG + threadIdx.x;
+        const int *en = rf + RF_INTS * (long long)e2;
+        if (e2 < nrf && !(active && !active[en[15]])) {
+            const int cb = en[0], cell = en[1];
+            const T coef = T(coef_p[en[15]]);
+            const int mask = en[2];
+            const long long gi = (long long)cb * NC + cell;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                T a = T(0);
+                for (int ff = 0; ff < 6; ++ff)
+                    if ((mask >> ff) & 1) a += sadd[threadIdx.x][ff][c];
+                if (a != T(0)) out[c * ccs + gi] += coef * a;
+            }
+        }
+    }
 }
 
 template <typename T>
@@ -704,8 +724,9 @@ ohm_status launch_reflux(const ohm_hier *h, int level, const T *Bc, long long cc
 {
     const AmrLevelDev &L = h->amr[level];
     if (L.nrf == 0) return OHM_OK;
-    k_reflux<T><<<(L.nrf + 127) / 128, 128, 0, s>>>(L.nrf, L.rf, active, L.nbr, h->amr[level + 1].nbr, L.inv_h,
-                                                     coef_dev, Bc, ccs, etac, Bf, fcs, Bfg, fgcs, etaf, etafg, out);
+    k_reflux<T><<<(L.nrf + RF_PER_WG - 1) / RF_PER_WG, RF_PER_WG * 6, 0, s>>>(
+        L.nrf, L.rf, active, L.nbr, h->amr[level + 1].nbr, L.inv_h, coef_dev, Bc, ccs, etac, Bf, fcs, Bfg, fgcs, etaf,
+        etafg, out);
     return check_launch("reflux");
 }
 
