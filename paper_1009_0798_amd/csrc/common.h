@@ -69,8 +69,13 @@ struct AmrLevelDev {
     // refluxing: coarse cells of this level with faces next to covered cells
     int nrf = 0;
     int *rf = nullptr;         // [nrf][RF_INTS]
+    int *rff = nullptr;        // faces of the entries, entry-major, faces in order: 8 entry + face
+    int *rfs = nullptr;        // [nrf] index of each entry's first face in rff
+    int nrfw = 0;              // workgroups of the refluxing kernel
+    int *rfw = nullptr;        // [nrfw][4]: first entry, entries, first face, faces
 };
-constexpr int RF_INTS = 16;    // block, cell, facemask, 6 x fine block, 6 x fine base cell, pad
+constexpr int RF_INTS = 16;      // block, cell, facemask, 6 x fine block, 6 x fine base cell, problem
+constexpr int RF_WG_FACES = 96;  // faces per refluxing workgroup (10 fluxes each)
 
 // Dense multigrid level (below level 0)
 struct DenseProbDev {

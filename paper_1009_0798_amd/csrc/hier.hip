@@ -376,8 +376,30 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
                 }
             }
         }
-        H->amr[l].nrf = (int)(rf.size() / RF_INTS);
+        const int nrf = (int)(rf.size() / RF_INTS);
+        H->amr[l].nrf = nrf;
         OHM_TRY(upload(&H->amr[l].rf, rf));
+        // face list and workgroup partition: whole entries per workgroup, at
+        // most RF_WG_FACES faces
+        std::vector<int> rff, rfs(nrf), rfw;
+        int w_e0 = 0, w_f0 = 0;
+        for (int e = 0; e <= nrf; ++e) {
+            const int nf = e < nrf ? __builtin_popcount(rf[RF_INTS * e + 2]) : 0;
+            const int cur = (int)rff.size() - w_f0;
+            if (e == nrf || cur + nf > RF_WG_FACES) {
+                if (e > w_e0) rfw.insert(rfw.end(), {w_e0, e - w_e0, w_f0, cur});
+                w_e0 = e;
+                w_f0 = (int)rff.size();
+            }
+            if (e == nrf) break;
+            rfs[e] = (int)rff.size();
+            for (int f = 0; f < 6; ++f)
+                if ((rf[RF_INTS * e + 2] >> f) & 1) rff.push_back(8 * e + f);
+        }
+        H->amr[l].nrfw = (int)(rfw.size() / 4);
+        OHM_TRY(upload(&H->amr[l].rff, rff));
+        OHM_TRY(upload(&H->amr[l].rfs, rfs));
+        OHM_TRY(upload(&H->amr[l].rfw, rfw));
     }
     // ---- dense levels ---------------------------------------------------------
     for (int dd = 1; dd <= -H->min_level; ++dd) {
@@ -458,7 +480,7 @@ static void free_all(ohm_hier *H)
     for (int l = 0; l < OHM_MAX_LEVELS; ++l) {
         AmrLevelDev &L = H->amr[l];
         void *ptrs[] = {L.nbr, L.prob, L.ijk, L.parent, L.octant, L.gparent, L.goctant, L.gprob,
-                        L.cov, L.dense_map, L.rf, L.inv_h2, L.inv_h};
+                        L.cov, L.dense_map, L.rf, L.rff, L.rfs, L.rfw, L.inv_h2, L.inv_h};
         for (void *q : ptrs)
             if (q) (void)hipFree(q);
     }

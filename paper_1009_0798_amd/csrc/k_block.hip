@@ -473,73 +473,97 @@ __device__ T face_flux_h(const T *Bf, const T *Bg, long long cs, long long gcs, 
     return ef * (tr - (F(qd, c) - F(a, c)));
 }
 
-// One workgroup per 64 entries (coarse cells next to covered cells); thread t
-// handles face t mod 6 of entry t / 6 (both tangential components), then the
-// 6 face contributions of each entry are summed in face order.
-constexpr int RF_PER_WG = 64;
-
+// Refluxing.  An entry is a leaf cell of level l with faces next to covered
+// cells; each such face needs, for both tangential components, the coarse
+// flux and the four fine fluxes through it.  A workgroup takes whole entries
+// (at most RF_WG_FACES faces) and gives every one of the ten fluxes of a face
+// its own thread, so each thread's loads are one neighbour lookup deep.  The
+// face corrections and the entry sums are then formed in fixed orders: fine
+// fluxes in child order, faces in face order.
 template <typename T>
-__global__ void __launch_bounds__(RF_PER_WG * 6)
-k_reflux(int nrf, const int *__restrict__ rf, const int *__restrict__ active, const int *__restrict__ cnbr,
+__global__ void __launch_bounds__(RF_WG_FACES * 10)
+k_reflux(const int *__restrict__ rfw, const int *__restrict__ rff, const int *__restrict__ rfs,
+         const int *__restrict__ rf, const int *__restrict__ active, const int *__restrict__ cnbr,
          const int *__restrict__ fnbr, const double *__restrict__ inv_h_c, const double *__restrict__ coef_p,
          const T *__restrict__ Bc, long long ccs, const T *__restrict__ Ec, const T *__restrict__ Bf,
          long long fcs, const T *__restrict__ Bfg, long long fgcs, const T *__restrict__ Ef,
          const T *__restrict__ Efg, T *__restrict__ out)
 {
-    __shared__ T sadd[RF_PER_WG][6][3];
-    const int el = threadIdx.x / 6, f = threadIdx.x % 6;
-    const int e = blockIdx.x * RF_PER_WG + el;
-    T add[3] = {T(0), T(0), T(0)};
-    const int *ent = rf + RF_INTS * (long long)e;
-    const bool live = e < nrf && !(active && !active[ent[15]]);
-    if (live && ((ent[2] >> f) & 1)) {
-        const int pr = ent[15], cb = ent[0], cell = ent[1];
-        const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
-        const T ih = T(inv_h_c[pr]);       // coarse 1/h; fine fluxes carry h_f = h/2
-        const int d = f >> 1;
-        const int sg = (f & 1) ? -1 : 1;
-        const int fb = ent[3 + f], fbase = ent[9 + f];
-        const int fx = fbase & 7, fy = (fbase >> 3) & 7, fz = fbase >> 6;
-        for (int c = 0; c < 3; ++c) {
-            if (c == d) continue;
-            // coarse flux on the face: after cell p (sg = +1) or after p - e_d
-            int qc[3] = {x, y, z};
-            if (sg < 0) qc[d] -= 1;
-            const T Fc = face_flux_h<T>(Bc, Bc, ccs, ccs, Ec, Ec, cnbr, cb, qc, d, c) * ih;
-            // the 4 fine faces: the covered-side children start at fbase; the
-            // face is after the child (sg < 0) or after the child - e_d (sg > 0)
-            T Ff = T(0);
-            const int t1 = (d + 1) % 3, t2 = (d + 2) % 3;
-            for (int a1 = 0; a1 < 2; ++a1)
-                for (int a2 = 0; a2 < 2; ++a2) {
-                    int q[3] = {fx, fy, fz};
-                    q[t1] += a1;
-                    q[t2] += a2;
+    __shared__ T sfl[RF_WG_FACES * 10];
+    __shared__ T sadd[RF_WG_FACES][2];
+    const int e0 = rfw[4 * blockIdx.x], ne = rfw[4 * blockIdx.x + 1], f0 = rfw[4 * blockIdx.x + 2],
+              nf = rfw[4 * blockIdx.x + 3];
+    const int t = threadIdx.x;
+    // one flux: face i, tangential component ci (c = d + 1 + ci mod 3), k = 0
+    // the coarse face, k = 1..4 the fine faces (children a1, a2 = (k-1)/2, (k-1)%2)
+    {
+        const int i = t / 10, ci = (t % 10) / 5, k = t % 5;
+        if (i < nf) {
+            const int it = rff[f0 + i];
+            const int *ent = rf + RF_INTS * (long long)(it >> 3);
+            const int f = it & 7, d = f >> 1, sg = (f & 1) ? -1 : 1;
+            const int c = (d + 1 + ci) % 3;
+            const int pr = ent[15];
+            T v = T(0);
+            if (!(active && !active[pr])) {
+                if (k == 0) {
+                    // coarse face: after cell p (sg = +1) or after p - e_d
+                    const int cell = ent[1];
+                    int q[3] = {cell & 7, (cell >> 3) & 7, cell >> 6};
+                    if (sg < 0) q[d] -= 1;
+                    v = face_flux_h<T>(Bc, Bc, ccs, ccs, Ec, Ec, cnbr, ent[0], q, d, c);
+                } else {
+                    // fine faces: the covered-side children start at the entry's
+                    // fine base cell; the face is after the child (sg < 0) or
+                    // after the child - e_d (sg > 0)
+                    const int fbase = ent[9 + f];
+                    int q[3] = {fbase & 7, (fbase >> 3) & 7, fbase >> 6};
+                    q[(d + 1) % 3] += (k - 1) >> 1;
+                    q[(d + 2) % 3] += (k - 1) & 1;
                     if (sg > 0) q[d] -= 1;
-                    Ff += face_flux_h<T>(Bf, Bfg, fcs, fgcs, Ef, Efg, fnbr, fb, q, d, c);
+                    v = face_flux_h<T>(Bf, Bfg, fcs, fgcs, Ef, Efg, fnbr, ent[3 + f], q, d, c);
                 }
-            Ff *= T(0.25) * (ih * T(2));
-            add[c] = T(sg) * (Ff - Fc) * ih;
+            }
+            sfl[t] = v;
         }
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) sadd[el][f][c] = add[c];
     __syncthreads();
-    if (threadIdx.x < RF_PER_WG) {
-        const int e2 = blockIdx.x * RF_PER_WG + threadIdx.x;
-        const int *en = rf + RF_INTS * (long long)e2;
-        if (e2 < nrf && !(active && !active[en[15]])) {
-            const int cb = en[0], cell = en[1];
-            const T coef = T(coef_p[en[15]]);
+    // face correction per tangential component: sg (<F_fine> - F_coarse) / h
+    if (t < 2 * nf) {
+        const int i = t >> 1, ci = t & 1;
+        const int it = rff[f0 + i];
+        const int sg = (it & 1) ? -1 : 1;
+        const T ih = T(inv_h_c[rf[RF_INTS * (long long)(it >> 3) + 15]]);  // fine fluxes carry h_f = h/2
+        const T *fl = sfl + 10 * i + 5 * ci;
+        const T Fc = fl[0] * ih;
+        T Ff = fl[1];
+        Ff += fl[2];
+        Ff += fl[3];
+        Ff += fl[4];
+        Ff *= T(0.25) * (ih * T(2));
+        sadd[i][ci] = T(sg) * (Ff - Fc) * ih;
+    }
+    __syncthreads();
+    if (t < ne) {
+        const int e = e0 + t;
+        const int *en = rf + RF_INTS * (long long)e;
+        const int pr = en[15];
+        if (!(active && !active[pr])) {
+            const T coef = T(coef_p[pr]);
             const int mask = en[2];
-            const long long gi = (long long)cb * NC + cell;
+            const long long gi = (long long)en[0] * NC + en[1];
+            T a[3] = {T(0), T(0), T(0)};
+            int i = rfs[e] - f0;
+            for (int ff = 0; ff < 6; ++ff)
+                if ((mask >> ff) & 1) {
+                    const int d = ff >> 1;
+                    a[(d + 1) % 3] += sadd[i][0];
+                    a[(d + 2) % 3] += sadd[i][1];
+                    ++i;
+                }
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                T a = T(0);
-                for (int ff = 0; ff < 6; ++ff)
-                    if ((mask >> ff) & 1) a += sadd[threadIdx.x][ff][c];
-                if (a != T(0)) out[c * ccs + gi] += coef * a;
-            }
+            for (int c = 0; c < 3; ++c)
+                if (a[c] != T(0)) out[c * ccs + gi] += coef * a[c];
         }
     }
 }
@@ -724,9 +748,9 @@ ohm_status launch_reflux(const ohm_hier *h, int level, const T *Bc, long long cc
 {
     const AmrLevelDev &L = h->amr[level];
     if (L.nrf == 0) return OHM_OK;
-    k_reflux<T><<<(L.nrf + RF_PER_WG - 1) / RF_PER_WG, RF_PER_WG * 6, 0, s>>>(
-        L.nrf, L.rf, active, L.nbr, h->amr[level + 1].nbr, L.inv_h, coef_dev, Bc, ccs, etac, Bf, fcs, Bfg, fgcs, etaf,
-        etafg, out);
+    k_reflux<T><<<L.nrfw, RF_WG_FACES * 10, 0, s>>>(L.rfw, L.rff, L.rfs, L.rf, active, L.nbr, h->amr[level + 1].nbr,
+                                                   L.inv_h, coef_dev, Bc, ccs, etac, Bf, fcs, Bfg, fgcs, etaf, etafg,
+                                                   out);
     return check_launch("reflux");
 }
 
