@@ -110,7 +110,9 @@ const char *ohm_last_error(void);
 
 /*
  * Coarse-fine ghost fill (AMR levels >= 1).  Every ghost block of `level` --
- * an 8^3 block position next to a level block but not part of the level --
+ * an 8^3 block position next to a level block across a face, an edge or (where
+ * the coarse cells its interpolation needs exist) a corner, but not part of
+ * the level --
  * receives the cell-centred trilinear interpolant (27/9/3/1 over 64) of the
  * level-(level-1) field `coarse`.  The paper leaves its coarse-fine
  * interpolation unstated; this is the library's reading.
@@ -152,9 +154,11 @@ ohm_status ohm_residual(ohm_hier *h, int32_t level, const void *B, const void *B
  * black one.  All cells of a colour update together from the state at the
  * start of the half-sweep: B_c += R_c / (1 + alpha_c).  Ghost values are held
  * fixed.  `tmp` is caller scratch of the size of B; B holds the result.  On
- * levels whose blocks all have their 26 neighbours one launch performs a whole
- * sweep; it needs B and eta aligned to 2 elements (OHM_ERR_ARG otherwise) and
- * each field array of the level below 4 GiB.
+ * levels where each of the 26 neighbour positions of every block is a level
+ * block or a ghost block (all levels, unless some corner ghost would need
+ * coarse cells that do not exist) one launch performs a whole sweep; it needs
+ * B, eta and the ghost arrays aligned to 2 elements (OHM_ERR_ARG otherwise)
+ * and each field or ghost array of the level below 4 GiB.
  */
 ohm_status ohm_smooth(ohm_hier *h, int32_t level, void *B, const void *B_ghost, const void *S,
                       const void *eta, const void *eta_ghost, const double *lam_dt,

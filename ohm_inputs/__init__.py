@@ -267,6 +267,20 @@ def config_amr2(n_base=64, extra_frac=0.2, seed=4):
     return spec
 
 
+def config_corner_gap():
+    """Three levels on a 4^3-block base (32^3 cells on [-1/2, 1/2)^3): level 1
+    is the 3^3 blocks (1..3)^3 without (3, 3, 3), level 2 the single block
+    (4, 4, 4) over level-1 block (2, 2, 2).  Every face and edge neighbour of
+    the level-2 block can be interpolated from level 1; its (+1, +1, +1)
+    corner neighbour cannot (the cells it would need lie in the missing
+    block)."""
+    bb = (4, 4, 4)
+    lev1 = np.array([(i, j, k) for k in range(1, 4) for j in range(1, 4) for i in range(1, 4)
+                     if (i, j, k) != (3, 3, 3)], dtype=np.int32)
+    lev2 = np.array([[4, 4, 4]], dtype=np.int32)
+    return HierSpec(bb, 1.0 / 32, [full_level(bb), morton_order(lev1), lev2])
+
+
 def amr_fields(spec: HierSpec, p=2.0, seed=5, eta_fn=dense_core_eta, origin=-0.5):
     """Sample one smooth div-free field (spectral, defined on the base grid) and
     eta at the cell centres of every level.  Covered coarse B = mean of its 8

@@ -183,17 +183,19 @@ ohm_status ohm_smooth(ohm_hier *h, int32_t level, void *B, const void *B_ghost, 
     double *cd;
     int slot;
     OHM_TRY(coef_slot(h, lam_dt, stream, &cd, &slot));
-    if (level >= 0 && h->amr[level].complete27) {
-        const long long cs = level_cs(h, level);
+    if (level >= 0 && h->amr[level].fused) {
+        const long long cs = level_cs(h, level), gcs = (long long)h->ng_host[level] * NC;
         for (int k = 0; k < nsweeps; ++k) {
             const void *src = (k & 1) ? tmp : B;
             void *dst = (k & 1) ? B : tmp;
             ohm_status st =
                 dtype == OHM_F64
                     ? launch_blk_sweep<double>(h, level, (const double *)src, cs, (const double *)S,
-                                               (const double *)eta, cd, (double *)dst, nullptr, stream)
+                                               (const double *)eta, cd, (double *)dst, nullptr, stream, nullptr, 0,
+                                               (const double *)B_ghost, gcs, (const double *)eta_ghost)
                     : launch_blk_sweep<float>(h, level, (const float *)src, cs, (const float *)S, (const float *)eta,
-                                              cd, (float *)dst, nullptr, stream);
+                                              cd, (float *)dst, nullptr, stream, nullptr, 0, (const float *)B_ghost,
+                                              gcs, (const float *)eta_ghost);
             OHM_TRY(st);
         }
         if (nsweeps & 1) OHM_HIP(hipMemcpyAsync(B, tmp, (size_t)(3 * cs) * (dtype == OHM_F64 ? 8 : 4),

@@ -213,21 +213,24 @@ struct Solver {
         const bool zero = flags & SMOOTH_ZERO, from_tmp = (flags & SMOOTH_FROM_TMP) && !zero;
         T *e = mg(P.e, l), *tmp = mg(P.tmp, l);
         T *cur = from_tmp ? tmp : e;
-        if (h->amr[l].complete27 && n > 0) {
+        const T *gB = at<T>(P.mg_g) + P.LG[l] * NC, *gE = etagT(l);
+        if (h->amr[l].fused && n > 0) {
             // fused sweeps ping-pong e <-> tmp; a zero input is not read, so
             // the first sweep writes whichever buffer makes the last land in e
             for (int k = 0; k < n; ++k) {
                 T *dst;
                 if (k == 0 && zero) {
                     dst = (n & 1) ? e : tmp;
-                    OHM_TRY(launch_blk_sweep<T>(h, l, nullptr, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st));
+                    OHM_TRY(launch_blk_sweep<T>(h, l, nullptr, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st,
+                                                nullptr, 0, nullptr, GN, gE));
                 } else if (k == 0 && coarse) {
                     dst = cur == e ? tmp : e;
                     OHM_TRY(launch_blk_sweep<T>(h, l, cur, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st, coarse,
                                                 h->dense_cells[1]));
                 } else {
                     dst = cur == e ? tmp : e;
-                    OHM_TRY(launch_blk_sweep<T>(h, l, cur, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st));
+                    OHM_TRY(launch_blk_sweep<T>(h, l, cur, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st,
+                                                nullptr, 0, gB, GN, gE));
                 }
                 cur = dst;
             }
@@ -237,7 +240,7 @@ struct Solver {
             T *oth = cur == e ? tmp : e;
             for (int k = 0; k < n; ++k)
                 for (int c = 0; c < 2; ++c)
-                    OHM_TRY(launch_blk_stencil<T>(h, l, MODE_SMOOTH, c == 0 ? cur : oth, at<T>(P.mg_g) + P.LG[l] * NC,
+                    OHM_TRY(launch_blk_stencil<T>(h, l, MODE_SMOOTH, c == 0 ? cur : oth, gB,
                                                   VN, GN, mg(P.rhs, l), etaT(l), etagT(l), lam_dt, c == 0 ? oth : cur,
                                                   c, nullptr, nullptr, active, st));
         }

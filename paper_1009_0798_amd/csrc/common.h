@@ -46,13 +46,15 @@ std::mutex &capture_mutex();
 // device-side tables of one AMR level (all problems of a handle)
 // ---------------------------------------------------------------------------
 // Neighbour entry of a block: >= 0 index of a same-level block; <= -1 means the
-// ghost block -1-entry; NBR_NONE means absent (only allowed for corners).
+// ghost block -1-entry; NBR_NONE means absent (only for corners whose
+// interpolation would need missing coarse cells).
 constexpr int NBR_NONE = -(1 << 30);
 
 struct AmrLevelDev {
     int nb = 0;                // blocks
     int ng = 0;                // coarse-fine ghost blocks
     bool complete27 = false;   // every block has all 26 neighbours as level blocks
+    bool fused = false;        // every neighbour entry is a level or a ghost block
     int *nbr = nullptr;        // [nb][27] neighbour entries, index (dx+1)+3(dy+1)+9(dz+1)
     int *prob = nullptr;       // [nb] problem of each block
     int *ijk = nullptr;        // [nb][3] block coordinates at this level
@@ -183,14 +185,17 @@ template <typename T>
 ohm_status launch_resid_restrict_blk0(const ohm_hier *h, const T *B, const T *Bg, long long cs, long long gcs,
                                       const T *S, const T *eta, const T *etag, const double *coef_dev, T *coarse,
                                       long long ccs, const int *active, hipStream_t s);
-// one fused red-black sweep B -> out (levels whose blocks have every neighbour);
-// B == nullptr sweeps a zero input without reading it; coarse != nullptr
-// (level 0 only) sweeps B + P(coarse), the trilinear prolongation of the first
-// dense level's field, without storing the corrected input
+// one fused red-black sweep B -> out (levels whose every neighbour entry is a
+// level or ghost block; ghost values Bg / etag, held fixed, on levels that
+// have ghosts); B == nullptr sweeps a zero input, with zero ghost values,
+// without reading either; coarse != nullptr (level 0 only) sweeps
+// B + P(coarse), the trilinear prolongation of the first dense level's field,
+// without storing the corrected input
 template <typename T>
 ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long cs, const T *S, const T *eta,
                             const double *coef_dev, T *out, const int *active, hipStream_t s,
-                            const T *coarse = nullptr, long long ccs = 0);
+                            const T *coarse = nullptr, long long ccs = 0, const T *Bg = nullptr, long long gcs = 0,
+                            const T *etag = nullptr);
 
 template <typename T>
 ohm_status launch_dense_stencil(const ohm_hier *h, int level, int mode, const T *B, const T *S,

@@ -219,6 +219,7 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
             if (l >= P.nlevels) continue;
             const LevelMap &M = maps[p][l];
             std::unordered_map<uint64_t, int> ghost_of;
+            int lo3[3], hi3[3];
             for (int b = 0; b < P.nb[l]; ++b) {
                 int gb = (int)P.boff[l] + b;
                 const int *q = &P.blocks[l][3 * b];
@@ -233,7 +234,22 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
                         nbr[27 * (size_t)gb + e] = (int)P.boff[l] + n;
                         continue;
                     }
-                    if ((dx != 0) + (dy != 0) + (dz != 0) == 3) continue;  // corners: unused
+                    if ((dx != 0) + (dy != 0) + (dz != 0) == 3) {
+                        // corners: only the fused two-halo sweep reads them; a
+                        // ghost where the coarse cells its interpolation needs
+                        // exist, else absent (the level then sweeps in halves)
+                        bool ok = l >= 1;
+                        for (int a = 0; a < 3 && ok; ++a) {
+                            const int n = q[a] + (a == 0 ? dx : a == 1 ? dy : dz);
+                            lo3[a] = (int)std::floor((4.0 * n - 1) / 8.0);
+                            hi3[a] = (int)std::floor((4.0 * n + 4) / 8.0);
+                        }
+                        for (int ck = lo3[2]; ok && ck <= hi3[2]; ++ck)
+                        for (int cj = lo3[1]; ok && cj <= hi3[1]; ++cj)
+                        for (int ci = lo3[0]; ok && ci <= hi3[0]; ++ci)
+                            ok = maps[p][l - 1].has(ci, cj, ck);
+                        if (!ok) continue;
+                    }
                     int w[3] = {wrapi(q[0] + dx, M.box[0]), wrapi(q[1] + dy, M.box[1]),
                                 wrapi(q[2] + dz, M.box[2])};
                     uint64_t k = key3(w[0], w[1], w[2]);
@@ -274,6 +290,7 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
         L.ng = ng;
         H->ng_host[l] = ng;
         L.complete27 = std::all_of(nbr.begin(), nbr.end(), [](int v) { return v >= 0; });
+        L.fused = std::all_of(nbr.begin(), nbr.end(), [](int v) { return v != NBR_NONE; });
         std::vector<double> ih2(nprob, 0.0), ih(nprob, 0.0);
         for (int p = 0; p < nprob; ++p)
             if (l < H->probs[p].nlevels) {

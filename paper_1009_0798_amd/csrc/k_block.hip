@@ -211,6 +211,7 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
 // neighbours (the tile body is in sweep.h, shared with the dense levels)
 // ---------------------------------------------------------------------------
 struct BlockAddr {
+    static constexpr bool ghosts = false;
     const int *nbr;   // 27 neighbour entries of the block (LDS)
     int b;
     __device__ __forceinline__ long long at(int x, int y, int z) const
@@ -218,6 +219,30 @@ struct BlockAddr {
         const int sx = side(x), sy = side(y), sz = side(z);
         const int n = nbr[(sx + 1) + 3 * (sy + 1) + 9 * (sz + 1)];
         return (long long)n * NC + (x - NB * sx) + NB * ((y - NB * sy) + NB * (z - NB * sz));
+    }
+};
+
+// Same, on a level whose neighbour entries may name coarse-fine ghost blocks
+// (never absent ones); at() is used for level cells only.
+template <typename T>
+struct GhostBlockAddr {
+    static constexpr bool ghosts = true;
+    const int *nbr;
+    const T *G;       // ghost blocks, component stride gcs
+    long long gcs;
+    const T *EG;      // resistivity of the ghost blocks
+    __device__ __forceinline__ int entry(int x, int y, int z) const
+    {
+        return nbr[(side(x) + 1) + 3 * (side(y) + 1) + 9 * (side(z) + 1)];
+    }
+    __device__ __forceinline__ int local(int x, int y, int z) const
+    {
+        const int sx = side(x), sy = side(y), sz = side(z);
+        return (x - NB * sx) + NB * ((y - NB * sy) + NB * (z - NB * sz));
+    }
+    __device__ __forceinline__ long long at(int x, int y, int z) const
+    {
+        return (long long)entry(x, y, z) * NC + local(x, y, z);
     }
 };
 
@@ -263,14 +288,16 @@ struct Level0Coarse {
 };
 
 // MODE 0: sweep B -> out; 1: zero input (B not read); 2: sweep of B plus the
-// prolonged correction from the first dense level (coarse), B -> out
+// prolonged correction from the first dense level (coarse), B -> out; MODE 3
+// and 4 as 0 and 1 on a level with coarse-fine ghost blocks (Bg, etag)
 template <typename T, int MODE>
 __global__ void __launch_bounds__(SWEEP_THREADS)
 k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ prob_of,
             const int *__restrict__ active, const double *__restrict__ inv_h2_p, const double *__restrict__ coef_p,
             const T *__restrict__ B, long long cs, const T *__restrict__ S, const T *__restrict__ eta,
             T *__restrict__ out, const int *__restrict__ ijk, const DenseProbDev *__restrict__ dp,
-            const T *__restrict__ coarse, long long ccs)
+            const T *__restrict__ coarse, long long ccs, const T *__restrict__ Bg, long long gcs,
+            const T *__restrict__ etag)
 {
     __shared__ T sB[3][TC2];
     __shared__ T sE[TC2];
@@ -281,13 +308,17 @@ k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ p
     if (active && !active[pr]) return;
     if (threadIdx.x < 27) snbr[threadIdx.x] = nbr_tab[27 * (long long)b + threadIdx.x];
     __syncthreads();
-    const BlockAddr A{snbr, b};
     const T cih2 = T(coef_p[pr]) * T(inv_h2_p[pr]);
-    if (MODE == 2) {
+    if constexpr (MODE >= 3) {
+        const GhostBlockAddr<T> A{snbr, Bg, gcs, etag};
+        fused_sweep_tile<T, MODE == 4>(A, B, cs, S, eta, out, cih2, sB, sE);
+    } else if constexpr (MODE == 2) {
+        const BlockAddr A{snbr, b};
         Level0Coarse<T> cor{coarse, ccs, dp[pr], 4 * ijk[3 * b] - 2, 4 * ijk[3 * b + 1] - 2, 4 * ijk[3 * b + 2] - 2,
                             sC, {}};
         fused_sweep_tile<T, false>(A, B, cs, S, eta, out, cih2, sB, sE, cor);
     } else {
+        const BlockAddr A{snbr, b};
         fused_sweep_tile<T, MODE == 1>(A, B, cs, S, eta, out, cih2, sB, sE);
     }
 }
@@ -665,28 +696,46 @@ ohm_status launch_resid_restrict_blk0(const ohm_hier *h, const T *B, const T *Bg
 template <typename T>
 ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long cs, const T *S, const T *eta,
                             const double *coef_dev, T *out, const int *active, hipStream_t s, const T *coarse,
-                            long long ccs)
+                            long long ccs, const T *Bg, long long gcs, const T *etag)
 {
     const AmrLevelDev &L = h->amr[level];
     if (L.nb == 0) return OHM_OK;
-    if (!L.complete27) return fail(OHM_ERR_ARG, "fused sweep needs every neighbour block of level %d", level);
-    if ((unsigned long long)L.nb * NC * sizeof(T) > 0xFFFFFFFFull)
+    if (!L.fused)
+        return fail(OHM_ERR_ARG, "fused sweep needs every neighbour block of level %d as a level or ghost block", level);
+    const bool gh = !L.complete27;
+    if ((unsigned long long)L.nb * NC * sizeof(T) > 0xFFFFFFFFull ||
+        (gh && (unsigned long long)L.ng * NC * sizeof(T) > 0xFFFFFFFFull))
         return fail(OHM_ERR_ARG, "level %d: fused sweep addresses each field array with 32-bit offsets (max 4 GiB)",
                     level);
     if (((uintptr_t)B | (uintptr_t)eta | (uintptr_t)(cs * sizeof(T))) % (2 * sizeof(T)) != 0)
         return fail(OHM_ERR_ARG, "level %d: fused sweep needs B, eta and the component stride %zu-byte aligned", level,
                     2 * sizeof(T));
+    if (gh) {
+        if (coarse) return fail(OHM_ERR_ARG, "a fused coarse correction needs level 0");
+        if ((B && !Bg) || !etag) return fail(OHM_ERR_ARG, "level %d has ghost blocks: B_ghost and eta_ghost needed", level);
+        if (((uintptr_t)Bg | (uintptr_t)etag | (uintptr_t)(gcs * sizeof(T))) % (2 * sizeof(T)) != 0)
+            return fail(OHM_ERR_ARG, "level %d: fused sweep needs the ghost arrays and their stride %zu-byte aligned",
+                        level, 2 * sizeof(T));
+        if (B)
+            k_blk_sweep<T, 3><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S,
+                                                             eta, out, nullptr, nullptr, nullptr, 0, Bg, gcs, etag);
+        else
+            k_blk_sweep<T, 4><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S,
+                                                             eta, out, nullptr, nullptr, nullptr, 0, nullptr, 0, etag);
+        return check_launch("fused sweep with ghosts");
+    }
     if (coarse) {
         if (level != 0 || h->min_level > -1 || !B)
             return fail(OHM_ERR_ARG, "a fused coarse correction needs level 0, a dense level below it and an input");
         k_blk_sweep<T, 2><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta,
-                                                         out, L.ijk, h->dense[1].probs, coarse, ccs);
+                                                         out, L.ijk, h->dense[1].probs, coarse, ccs, nullptr, 0,
+                                                         nullptr);
     } else if (B) {
         k_blk_sweep<T, 0><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta,
-                                                         out, nullptr, nullptr, nullptr, 0);
+                                                         out, nullptr, nullptr, nullptr, 0, nullptr, 0, nullptr);
     } else {
         k_blk_sweep<T, 1><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta,
-                                                         out, nullptr, nullptr, nullptr, 0);
+                                                         out, nullptr, nullptr, nullptr, 0, nullptr, 0, nullptr);
     }
     return check_launch("fused sweep");
 }
@@ -772,7 +821,8 @@ ohm_status launch_reduce_problem(int nprob, int nrange, const long long *range_d
 
 #define INST(T)                                                                                                 \
     template ohm_status launch_blk_sweep<T>(const ohm_hier *, int, const T *, long long, const T *, const T *,   \
-                                            const double *, T *, const int *, hipStream_t, const T *, long long);                      \
+                                            const double *, T *, const int *, hipStream_t, const T *, long long, \
+                                            const T *, long long, const T *);                                   \
     template ohm_status launch_blk_stencil<T>(const ohm_hier *, int, int, const T *, const T *, long long,      \
                                               long long, const T *, const T *, const T *, const double *, T *,  \
                                               int, double *, const uint8_t *, const int *, hipStream_t,         \

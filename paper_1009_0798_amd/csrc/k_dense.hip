@@ -73,6 +73,7 @@ k_dense_stencil(const int *__restrict__ tiles, const DenseProbDev *__restrict__ 
 
 // fused red-black sweep on 8^3 tiles of a dense level (periodic wrap)
 struct DenseAddr {
+    static constexpr bool ghosts = false;
     DenseProbDev q;
     int ox, oy, oz;
     __device__ __forceinline__ long long at(int x, int y, int z) const

@@ -6,10 +6,16 @@
 // black half-sweep on the tile then reads those updated red values.  This is
 // the same arithmetic as two separate half-sweeps.  `Addr::at(x, y, z)` gives
 // the element offset of tile-local cell (x, y, z), -2 <= x, y, z <= 9, inside a
-// component of the field; every such cell must exist (no coarse-fine ghosts).
-// With ZERO the input field is zero and is not read (B may be null): the red
-// update reduces to S / diag and the tile starts from zeros, which gives the
-// same values as a sweep over an explicitly zeroed field.  A `Coarse` object
+// component of the field.  Without `Addr::ghosts` every such cell is a level
+// cell; with it, `Addr::entry(x, y, z)` is the neighbour entry of the cell's
+// block (a level block, or ghost block -1-entry of the ghost arrays A.G, A.EG
+// with component stride A.gcs), tile values of ghost blocks are loaded from
+// those arrays, and first-layer red cells of ghost blocks keep their values
+// (ghost values are fixed during smoothing).
+// With ZERO the input field is zero and is not read (B may be null; so must
+// be the ghost values): the red update reduces to S / diag and the tile starts
+// from zeros, which gives the same values as a sweep over an explicitly zeroed
+// field.  A `Coarse` object
 // with active = true adds a coarse-grid correction to every tile value as it
 // is loaded (prolongation fused into the first post-smoothing sweep); its
 // load() issues the global reads of whatever it stages, stage() stores them in
@@ -82,13 +88,27 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
     if (loader) {
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
-            const unsigned off = (unsigned)A.at(x, y, 2 * zq + k - 2) * (unsigned)sizeof(T);
-            if (!ZERO) {
-                v[k][0] = load_pair(B0, off);
-                v[k][1] = load_pair(B1, off);
-                v[k][2] = load_pair(B2, off);
+            const int z = 2 * zq + k - 2;
+            if constexpr (Addr::ghosts) {
+                const int n = A.entry(x, y, z);
+                const bool g = n < 0;
+                const unsigned off = ((unsigned)(g ? -1 - n : n) * (unsigned)NC + (unsigned)A.local(x, y, z)) *
+                                     (unsigned)sizeof(T);
+                if (!ZERO) {
+                    v[k][0] = load_pair(g ? A.G : B0, off);
+                    v[k][1] = load_pair(g ? A.G + A.gcs : B1, off);
+                    v[k][2] = load_pair(g ? A.G + 2 * A.gcs : B2, off);
+                }
+                v[k][3] = load_pair(g ? A.EG : eta, off);
+            } else {
+                const unsigned off = (unsigned)A.at(x, y, z) * (unsigned)sizeof(T);
+                if (!ZERO) {
+                    v[k][0] = load_pair(B0, off);
+                    v[k][1] = load_pair(B1, off);
+                    v[k][2] = load_pair(B2, off);
+                }
+                v[k][3] = load_pair(eta, off);
             }
-            v[k][3] = load_pair(eta, off);
         }
     }
     if (Coarse::active) {
@@ -130,19 +150,23 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
             else if (d == 1) { x = a; y = s; z = bb; }
             else { x = a; y = bb; z = s; }
         }
-        rp = tix2(x, y, z);
-        const unsigned off = (unsigned)A.at(x, y, z) * (unsigned)sizeof(T);
-        const T s3[3] = {load_at(S0, off), load_at(S1, off), load_at(S2, off)};
-        T al[3];
-        if (ZERO) {
-            alpha_all<T, TW2>(sE, rp, al);
+        bool upd = true;
+        if constexpr (Addr::ghosts) upd = u < 256 || A.entry(x, y, z) >= 0;
+        if (upd) {
+            rp = tix2(x, y, z);
+            const unsigned off = (unsigned)A.at(x, y, z) * (unsigned)sizeof(T);
+            const T s3[3] = {load_at(S0, off), load_at(S1, off), load_at(S2, off)};
+            T al[3];
+            if (ZERO) {
+                alpha_all<T, TW2>(sE, rp, al);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) red[c] = relax_div(s3[c], fma(c2, al[c], T(1)));
-        } else {
-            T dv[3];
-            divF_all<T, TW2>(sB[0], sB[1], sB[2], sE, rp, dv, al);
+                for (int c = 0; c < 3; ++c) red[c] = relax_div(s3[c], fma(c2, al[c], T(1)));
+            } else {
+                T dv[3];
+                divF_all<T, TW2>(sB[0], sB[1], sB[2], sE, rp, dv, al);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) red[c] = relax_point(sB[c][rp], s3[c], dv[c], al[c], c8, c2);
+                for (int c = 0; c < 3; ++c) red[c] = relax_point(sB[c][rp], s3[c], dv[c], al[c], c8, c2);
+            }
         }
     }
     __syncthreads();

@@ -154,6 +154,34 @@ def test_amr_two_levels_against_oracle():
     assert np.linalg.norm(diff) <= 1.5 * RTOL * nS + 1e-12 * np.linalg.norm(exv)
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_amr_three_levels_corner_gap_against_oracle(precision):
+    """Three levels whose finest level lacks one corner ghost: level 1 smooths
+    with one launch per sweep (ghosts on every side), level 2 with half-sweeps."""
+    announce(f"cn amr 3 levels corner gap precision={precision}")
+    spec = gen.config_corner_gap()
+    C = amr.Composite(spec)
+    Bb, eb = gen.amr_fields(spec, p=2.0, seed=7)
+    L = spec.nlevels
+    Bs = C.average_down([C.to_dense(l, Bb[l]) for l in range(L)])
+    es = [C.to_dense(l, eb[l]) for l in range(L)]
+    dt = 20.0 * spec.dx(L - 1) ** 2 / (6 * 10.0)
+    import paper_1009_0798_amd as ohm
+    H = hier(spec)
+    Bt = [cuda(dense_to_blocks(Bs[l], spec.levels[l])) for l in range(L)]
+    Et = [cuda(dense_to_blocks(es[l], spec.levels[l])[None]) for l in range(L)]
+    st, stats = ohm.ohm_cn_step(H, Bt, Et, dt, ohm.default_opts(rtol=RTOL, max_iters=300, precision=precision))
+    print(stats)
+    assert st == 0 and stats[0]["rel_res"] <= RTOL
+    ex, _ = C.cn_step(Bs, es, dt, rtol=1e-13)
+    nS = np.linalg.norm(C.pack(C.source(Bs, es, dt)))
+    got = [blocks_to_dense(host(Bt[l]), spec.levels[l], spec.cells(l)) for l in range(L)]
+    diff = np.concatenate([(got[l] - ex[l])[:, C.leaf[l]].ravel() for l in range(L)])
+    exv = C.pack(ex)
+    print("rel err", np.linalg.norm(diff) / np.linalg.norm(exv))
+    assert np.linalg.norm(diff) <= 1.5 * RTOL * nS + 1e-12 * np.linalg.norm(exv)
+
+
 def test_batched_equals_alone():
     """Three problems of different sizes in one handle give the same answer as
     each solved alone (per-problem reductions in a fixed order)."""

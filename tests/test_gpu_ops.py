@@ -148,6 +148,47 @@ def _amr_fields(spec, seed):
     return Bs, es
 
 
+@pytest.mark.parametrize("nsweeps", [1, 2])
+def test_smoother_with_ghosts(nsweeps):
+    """Smoothing on AMR levels with ghost blocks held fixed.  Level 1 of this
+    hierarchy has ghosts on faces, edges and corners (one launch per sweep);
+    level 2 lacks one corner ghost (two half-sweep launches per sweep)."""
+    import torch
+    import paper_1009_0798_amd as ohm
+    announce(f"smoother with ghosts nsweeps={nsweeps}")
+    spec = gen.config_corner_gap()
+    C = amr.Composite(spec)
+    Bs, es = _amr_fields(spec, 12)
+    Bs = C.average_down(Bs)
+    H = hier(spec)
+    Bt = [cuda(dense_to_blocks(Bs[l], spec.levels[l])) for l in range(3)]
+    Et = [cuda(dense_to_blocks(es[l], spec.levels[l])[None]) for l in range(3)]
+    Bfull = C.fill_ghosts(Bs)
+    efull = C.fill_ghosts(es)
+    coef = 0.7 * spec.dx(2) ** 2
+    for l in (1, 2):
+        g = H.ghost(l, 3)
+        ohm.ohm_fill_ghosts(H, l, Bt[l - 1], g)
+        ge = H.ghost(l, 1)
+        ohm.ohm_fill_ghosts(H, l, Et[l - 1], ge)
+        h = spec.dx(l)
+        S = np.random.default_rng(20 + l).standard_normal(Bs[l].shape)
+        St = cuda(dense_to_blocks(S, spec.levels[l]))
+        Bsm = Bt[l].clone()
+        ohm.ohm_smooth(H, l, Bsm, St, Et[l], coef, nsweeps, torch.empty_like(Bsm), B_ghost=g, eta_ghost=ge)
+        got = blocks_to_dense(host(Bsm), spec.levels[l], spec.cells(l))
+        m = C.mask[l]
+        x = Bfull[l].copy()
+        ghost_vals = x.copy()
+        for _ in range(nsweeps):
+            for colour in (0, 1):
+                x = ref.rb_halfsweep(x, S, efull[l], h, coef, colour)
+                x = np.where(m[None], x, ghost_vals)
+        scale = _scale(Bfull[l][:, m], efull[l], coef, h)
+        err = float(np.abs(got[:, m] - x[:, m]).max())
+        assert err <= 5e-13 * scale, (l, err, scale)
+
+
 @pytest.mark.parametrize("three", [False, True])
 def test_amr_ghosts_apply_reflux_transfers(three):
     """Level applies with coarse-fine ghosts, refluxed composite apply on the
