@@ -430,6 +430,7 @@ struct Solver {
                                st));
         std::vector<int> ones(np, 1);
         OHM_HIP(hipMemcpyAsync(at<int>(P.active), ones.data(), sizeof(int) * np, hipMemcpyHostToDevice, st));
+        act_dev = ones;
         mlprob = at<int>(P.mlprob);
         active_mut = at<int>(P.active);
         active = active_mut;
@@ -496,18 +497,8 @@ struct Solver {
         return OHM_OK;
     }
 
-    // |S|^2 per problem and the current residual norms
-    std::vector<double> Snorm2, rr;
-
-    ohm_status read_rr(std::vector<double> &out)
-    {
-        out.resize(h->nprob);
-        std::vector<double> d((size_t)h->nprob * 8);
-        OHM_HIP(hipMemcpyAsync(d.data(), at<double>(P.dots), sizeof(double) * 8 * h->nprob, hipMemcpyDeviceToHost, st));
-        OHM_HIP(hipStreamSynchronize(st));
-        for (int p = 0; p < h->nprob; ++p) out[p] = d[p];
-        return OHM_OK;
-    }
+    // |S|^2 per problem
+    std::vector<double> Snorm2;
 
     // true residual r = S - L x, returns per-problem |r|^2 (in dots[p*1])
     ohm_status true_residual(std::vector<double> &r2)
@@ -523,9 +514,13 @@ struct Solver {
         return OHM_OK;
     }
 
+    // device flags as last uploaded (setup uploads all ones)
+    std::vector<int> act_dev;
     ohm_status set_active(const std::vector<int> &a)
     {
+        if (a == act_dev) return OHM_OK;
         OHM_HIP(hipMemcpyAsync(active_mut, a.data(), sizeof(int) * a.size(), hipMemcpyHostToDevice, st));
+        act_dev = a;
         return OHM_OK;
     }
 
@@ -643,17 +638,25 @@ struct Solver {
     {
         const int np = h->nprob;
         std::vector<int> iters(np, 0), mgapps(np, 0), act(np, 1);
-        // |S|^2
+        // |S|^2 and the residual of the initial guess, read back together
+        std::vector<double> r2(np);
+        Snorm2.assign(np, 0.0);
         {
-            const double *xs[1] = {at<double>(P.S)};
-            OHM_TRY(dots(xs, xs, 1));
-            std::vector<double> d(np);
-            OHM_HIP(hipMemcpyAsync(d.data(), at<double>(P.dots), sizeof(double) * np, hipMemcpyDeviceToHost, st));
+            OHM_TRY(composite(P.x, P.r, MODE_RESID, lam_dt, neg_lam_dt, P.S));
+            const double *xs[2] = {at<double>(P.S), at<double>(P.r)};
+            OHM_TRY(dots(xs, xs, 2));
+            std::vector<double> d((size_t)np * 2);
+            OHM_HIP(hipMemcpyAsync(d.data(), at<double>(P.dots), sizeof(double) * d.size(), hipMemcpyDeviceToHost, st));
             OHM_HIP(hipStreamSynchronize(st));
-            Snorm2 = d;
+            for (int p = 0; p < np; ++p) {
+                Snorm2[p] = d[2 * p];
+                r2[p] = d[2 * p + 1];
+            }
         }
-        std::vector<double> r2;
-        OHM_TRY(true_residual(r2));
+        // |r|^2 of each problem's latest true residual.  A problem stops being
+        // updated only right after a true residual that included it, so at the
+        // end r holds every problem's residual at its final B.
+        std::vector<double> rfin = r2;
         auto converged = [&](int p, double v) {
             return !(v > o->rtol * o->rtol * std::max(Snorm2[p], 1e-300));
         };
@@ -674,6 +677,7 @@ struct Solver {
                     if (act[p]) {
                         ++iters[p];
                         ++mgapps[p];
+                        rfin[p] = r2[p];
                         if (!std::isfinite(r2[p])) return fail(OHM_ERR_NONFINITE, "problem %d: non-finite residual", p);
                         if (converged(p, r2[p])) act[p] = 0;
                     }
@@ -719,19 +723,27 @@ struct Solver {
                 OHM_TRY(set_active(act));
                 OHM_TRY(true_residual(r2));
                 for (int p = 0; p < np; ++p)
-                    if (act[p] && converged(p, r2[p])) act[p] = 0;
+                    if (act[p]) {
+                        rfin[p] = r2[p];
+                        if (converged(p, r2[p])) act[p] = 0;
+                    }
                 OHM_TRY(set_active(act));
             }
         }
-        // final state: true residual of every problem, average-down, copy out
-        std::vector<int> all(np, 1);
-        OHM_TRY(set_active(all));
-        OHM_TRY(true_residual(r2));
-        OHM_TRY(vnorms((int)P.NBt, mlprob, active, VN, at<double>(P.r), at<double>(P.part), st));
+        // final state: norms of the true residuals, average-down, copy out,
+        // one synchronisation
+        OHM_TRY(vnorms((int)P.NBt, mlprob, nullptr, VN, at<double>(P.r), at<double>(P.part), st));
         OHM_TRY(reduce(6, 3, at<double>(P.dots)));
         std::vector<double> nrm((size_t)np * 6);
         OHM_HIP(hipMemcpyAsync(nrm.data(), at<double>(P.dots), sizeof(double) * 6 * np, hipMemcpyDeviceToHost, st));
+        const int L = nlev();
+        for (int l = L - 1; l >= 1; --l)
+            OHM_TRY(launch_restrict_blk<double>(h, l, vec(P.x, l), VN, vec(P.x, l - 1), VN, 3, nullptr, st));
+        for (int l = 0; l < L; ++l)
+            OHM_TRY(vcopy_level<double, double>(vec(P.x, l), VN, (double *)Buser[l], (long long)h->nb_host[l] * NC,
+                                                (long long)h->nb_host[l] * NC, 3, st));
         OHM_HIP(hipStreamSynchronize(st));
+        r2 = rfin;
         for (int p = 0; p < np; ++p) {
             const double rel = std::sqrt(r2[p] / std::max(Snorm2[p], 1e-300));
             if (stats) {
@@ -745,13 +757,6 @@ struct Solver {
                 result = fail(OHM_ERR_NOCONV, "problem %d: relative residual %.3e after %d iterations", p, rel,
                               iters[p]);
         }
-        const int L = nlev();
-        for (int l = L - 1; l >= 1; --l)
-            OHM_TRY(launch_restrict_blk<double>(h, l, vec(P.x, l), VN, vec(P.x, l - 1), VN, 3, nullptr, st));
-        for (int l = 0; l < L; ++l)
-            OHM_TRY(vcopy_level<double, double>(vec(P.x, l), VN, (double *)Buser[l], (long long)h->nb_host[l] * NC,
-                                                (long long)h->nb_host[l] * NC, 3, st));
-        OHM_HIP(hipStreamSynchronize(st));
         return result;
     }
 };
