@@ -34,6 +34,39 @@ def _setup_uniform(bb=(3, 2, 4), seed=0):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_apply_keeps_two_coordinate_fields(dtype):
+    """B = (0, 0, B_z(x, y)) with eta(x, y): every z-plane of the result is the
+    same, bit for bit (so d/dz of it is exactly zero), and the x and y
+    components vanish to rounding.  They are not exact zeros: the kernel forms
+    the +face and -face terms of a component in one expression, which the
+    compiler contracts into a fused multiply-add, so the two equal products are
+    rounded differently."""
+    import torch
+    import paper_1009_0798_amd as ohm
+    announce(f"two-coordinate field apply {dtype}")
+    bb = (3, 2, 4)
+    spec = gen.HierSpec(bb, 0.05, [gen.full_level(bb)])
+    nx, ny, nz = spec.cells(0)
+    rng = np.random.default_rng(17)
+    B = np.zeros((3, nz, ny, nx))
+    B[2] = rng.standard_normal((1, ny, nx))
+    eta = np.broadcast_to(np.exp(rng.uniform(-1, 1, (1, ny, nx))), (nz, ny, nx))
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    ijk = spec.levels[0]
+    H = hier(spec)
+    Bt, Et = cuda(dense_to_blocks(B, ijk), tdt), cuda(dense_to_blocks(np.ascontiguousarray(eta), ijk)[None], tdt)
+    out = torch.empty_like(Bt)
+    coef = 0.37 * spec.dx0 ** 2
+    ohm.ohm_apply(H, 0, Bt, Et, coef, out)
+    got = blocks_to_dense(host(out), ijk, spec.cells(0))
+    scale = _scale(B, eta, coef, spec.dx0)
+    eps = 4 * float(torch.finfo(tdt).eps)
+    assert all(np.array_equal(got[:, k], got[:, 0]) for k in range(nz))
+    assert np.abs(got[:2]).max() <= eps * scale
+    assert np.abs(got[2]).max() > 0.1 * np.abs(B[2]).max()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
 def test_uniform_apply_residual_smooth(dtype):
     import torch
     announce(f"uniform apply/residual/smooth {dtype}")
