@@ -370,12 +370,17 @@ struct Solver {
             OHM_TRY(vconvert<double, T>(at<double>(ro), at<T>(P.rhs), n, st));
         }
         // AMR levels, finest first: smooth with zero coarse-fine ghosts,
-        // restrict the level residual under the finer blocks
+        // restrict the level residual under the finer blocks, and take the
+        // refluxed fluxes of the level's correction out of the residual of the
+        // coarser leaf cells next to it (the coarser correction is still zero
+        // there): the coarser level then solves the composite residual
         if (L > 1 && P.NGt > 0) OHM_TRY(vfill<T>(at<T>(P.mg_g), 3 * P.NGt * NC, T(0), st));
         for (int l = L - 1; l >= 1; --l) {
             OHM_TRY(smooth_blk(l, o->nu_pre, SMOOTH_ZERO));
             OHM_TRY(resid_blk(l));
             OHM_TRY(launch_restrict_blk<T>(h, l, mg(P.res, l), VN, mg(P.rhs, l - 1), VN, 3, active, st));
+            OHM_TRY(launch_reflux<T>(h, l - 1, nullptr, VN, etaT(l - 1), mg(P.e, l), VN, at<T>(P.mg_g) + P.LG[l] * NC,
+                                     GN, etaT(l), etagT(l), neg_lam_dt, mg(P.rhs, l - 1), active, st));
         }
         if (o->cycle == 1) {
             OHM_TRY(fmg_base());

@@ -212,6 +212,8 @@ ohm_status launch_prolong(const ohm_hier *h, int coarse_level, const T *coarse, 
 template <typename T>
 ohm_status launch_fill_ghosts(const ohm_hier *h, int level, const T *coarse, long long ccs,
                               T *ghost, long long gcs, int ncomp, const int *active, hipStream_t s);
+// out += coef (F_fine mean - F_coarse) (+-1/h) on faces between leaf cells of
+// `level` and covered cells; Bc == nullptr takes the coarse field as zero
 template <typename T>
 ohm_status launch_reflux(const ohm_hier *h, int level, const T *Bc, long long ccs, const T *etac,
                          const T *Bf, long long fcs, const T *Bfg, long long fgcs, const T *etaf,

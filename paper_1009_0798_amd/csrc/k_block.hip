@@ -538,11 +538,12 @@ k_reflux(const int *__restrict__ rfw, const int *__restrict__ rff, const int *__
             T v = T(0);
             if (!(active && !active[pr])) {
                 if (k == 0) {
-                    // coarse face: after cell p (sg = +1) or after p - e_d
+                    // coarse face: after cell p (sg = +1) or after p - e_d; a
+                    // null coarse field stands for zero
                     const int cell = ent[1];
                     int q[3] = {cell & 7, (cell >> 3) & 7, cell >> 6};
                     if (sg < 0) q[d] -= 1;
-                    v = face_flux_h<T>(Bc, Bc, ccs, ccs, Ec, Ec, cnbr, ent[0], q, d, c);
+                    if (Bc) v = face_flux_h<T>(Bc, Bc, ccs, ccs, Ec, Ec, cnbr, ent[0], q, d, c);
                 } else {
                     // fine faces: the covered-side children start at the entry's
                     // fine base cell; the face is after the child (sg < 0) or
