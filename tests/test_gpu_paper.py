@@ -134,3 +134,61 @@ def test_iteration_contraction_refined():
     print("max|R| per iteration", r)
     assert r[1] <= 0.1 * r[0] and r[2] <= 0.1 * r[1]
     assert r[2] <= 1e-3
+
+
+def _gauss_spec():
+    """Section 3.2: [-16, 16)^3, base 32^3 (h = 1), level 1 (h = 1/2) over
+    |x|, |y| < 8 and level 2 (h = 1/4) over |x|, |y| < 4, all z."""
+    lev0 = gen.full_level((4, 4, 4))
+    l1 = np.array([(i, j, k) for k in range(8) for j in range(2, 6) for i in range(2, 6)], dtype=np.int32)
+    l2 = np.array([(i, j, k) for k in range(16) for j in range(6, 10) for i in range(6, 10)], dtype=np.int32)
+    return gen.HierSpec((4, 4, 4), 1.0, [lev0, gen.morton_order(l1), gen.morton_order(l2)])
+
+
+def _gauss(spec, t, t0=1.0):
+    """B_z = exp(-(x^2 + y^2) / (4 eta (t + t0))) / (4 pi eta (t + t0)), eta = 1."""
+    Bs, es = [], []
+    for l in range(spec.nlevels):
+        nx, ny, nz = spec.cells(l)
+        h = spec.dx(l)
+        y, x = np.meshgrid(-16 + (np.arange(ny) + .5) * h, -16 + (np.arange(nx) + .5) * h, indexing="ij")
+        B = np.zeros((3, nz, ny, nx))
+        B[2] = (np.exp(-(x * x + y * y) / (4 * (t + t0))) / (4 * np.pi * (t + t0)))[None]
+        Bs.append(B)
+        es.append(np.ones((nz, ny, nx)))
+    return Bs, es
+
+
+@pytest.mark.parametrize("lam,lo,hi", [(0.5, 1.5, 3.2), (1.0, 0.5, 1.2)])
+def test_gaussian_per_level_error_slopes(lam, lo, hi):
+    """Figs. 8-9: L1 error of every level against the analytic Gaussian at
+    t = 4 for dt = 4, 2, 1, 1/2.  Levels 1 and 2 fall with the order of the
+    scheme (two for lambda = 1/2, one for lambda = 1; least-squares slopes);
+    level 0, far from the Gaussian and touched by its periodic images, falls
+    more slowly than level 2 for lambda = 1/2."""
+    import paper_1009_0798_amd as ohm
+    announce(f"paper E6/E7 Gaussian lambda={lam}")
+    spec = _gauss_spec()
+    C = amr.Composite(spec)
+    B0, es = _gauss(spec, 0.0)
+    B0 = C.average_down(B0)
+    Bex, _ = _gauss(spec, 4.0)
+    H = hier(spec)
+    dts = (4.0, 2.0, 1.0, 0.5)
+    errs = []
+    for dt in dts:
+        Bt = [cuda(dense_to_blocks(B0[l], spec.levels[l])) for l in range(3)]
+        Et = [cuda(dense_to_blocks(es[l], spec.levels[l])[None]) for l in range(3)]
+        o = ohm.default_opts(lam=lam)
+        ws = ohm.Workspace()
+        for _ in range(int(round(4.0 / dt))):
+            st, stats = ohm.ohm_cn_step(H, Bt, Et, dt, o, ws)
+            assert st == 0
+        B = [blocks_to_dense(host(Bt[l]), spec.levels[l], spec.cells(l)) for l in range(3)]
+        errs.append([np.abs(B[l][2][C.leaf[l]] - Bex[l][2][C.leaf[l]]).mean() for l in range(3)])
+    errs = np.log2(np.array(errs))
+    slopes = [np.polyfit(np.log2(dts), errs[:, l], 1)[0] for l in range(3)]
+    print("L1 per level per dt (log2)", errs.round(2).tolist(), "slopes", slopes)
+    assert lo <= slopes[1] <= hi and lo <= slopes[2] <= hi, slopes
+    if lam == 0.5:
+        assert slopes[0] < slopes[2], slopes
