@@ -256,16 +256,25 @@ struct Solver {
                                      active, st);
     }
     T *dv(size_t const *arr, int d) const { return at<T>(arr[d]); }
-    ohm_status smooth_dense(int d, int n, const int *filter, bool all, int flags = 0)
+    ohm_status smooth_dense(int d, int n, const int *filter, bool all, int flags = 0, const T *coarse = nullptr,
+                            T **last = nullptr)
     {
         return launch_dense_smooth<T>(h, -d, dv(P.d_e, d), dv(P.d_tmp, d), dv(P.d_rhs, d), dv(P.d_eta, d), lam_dt, n,
-                                      all, filter, st, flags);
+                                      all, filter, st, flags, coarse, last);
     }
+    // where each dense level's current correction is: its e buffer, or its
+    // tmp buffer when the post-smoothing sweeps ended there (no copy back)
+    T *ecur[17] = {};
+    T *ecur_of(int d) const { return ecur[d] ? ecur[d] : dv(P.d_e, d); }
+    // post-smoothing of dense level d may leave its result in tmp only when no
+    // problem takes its coarsest solve there (that solve writes e)
+    bool may_end_in_tmp(int d) const { return njobs[d] == 0 && !has_big[d]; }
     // coarsest grids at depth d, from a zero guess: dense inverse for small
     // grids, FP-T smoothing sweeps for the others; writes e_d of every problem
     // that bottoms out at depth d
     ohm_status coarsest(int d)
     {
+        ecur[d] = dv(P.d_e, d);
         void *jobs = at<char>(P.jobs) + coarse_job_bytes() * (size_t)h->nprob * d;
         if (njobs[d] > 0)
             OHM_TRY(launch_coarse_apply<T>(h, d, jobs, njobs[d], h->d_coarse_inv, dv(P.d_rhs, d), dv(P.d_e, d),
@@ -295,31 +304,41 @@ struct Solver {
                                                   etaT(0), etagT(0), lam_dt, dv(P.d_rhs, 1), h->dense_cells[1],
                                                   active, st));
             OHM_TRY(down_dense(1));
+            const T *e1 = ecur_of(1);
             if (h->amr[0].complete27 && nu2 > 0 && !(nu2 & 1)) {
                 // even count: the first sweep adds the correction as it loads
-                OHM_TRY(smooth_blk(0, nu2, 0, dv(P.d_e, 1)));
+                OHM_TRY(smooth_blk(0, nu2, 0, e1));
             } else if ((nu2 & 1) && h->amr[0].complete27) {
-                OHM_TRY(launch_prolong_blk<T>(h, -1, dv(P.d_e, 1), h->dense_cells[1], mg(P.tmp, 0), VN, 3, 1, active,
-                                              st, mg(P.e, 0)));
+                OHM_TRY(launch_prolong_blk<T>(h, -1, e1, h->dense_cells[1], mg(P.tmp, 0), VN, 3, 1, active, st,
+                                              mg(P.e, 0)));
                 OHM_TRY(smooth_blk(0, nu2, SMOOTH_FROM_TMP));
             } else {
-                OHM_TRY(launch_prolong_blk<T>(h, -1, dv(P.d_e, 1), h->dense_cells[1], mg(P.e, 0), VN, 3, 1, active, st));
+                OHM_TRY(launch_prolong_blk<T>(h, -1, e1, h->dense_cells[1], mg(P.e, 0), VN, 3, 1, active, st));
                 OHM_TRY(smooth_blk(0, nu2));
             }
             return OHM_OK;
         }
         const int d = -lev;
         const int nuc1 = o->nu_coarse > 0 ? o->nu_coarse : nu1, nuc2 = o->nu_coarse > 0 ? o->nu_coarse : nu2;
-        OHM_TRY(smooth_dense(d, nuc1, active, false, zf));
+        const int f1 = zero_guess ? SMOOTH_ZERO : (ecur_of(d) == dv(P.d_tmp, d) ? SMOOTH_FROM_TMP : 0);
+        OHM_TRY(smooth_dense(d, nuc1, active, false, f1));
+        ecur[d] = dv(P.d_e, d);
         OHM_TRY(launch_dense_resid_restrict<T>(h, -d, dv(P.d_e, d), dv(P.d_rhs, d), dv(P.d_eta, d), lam_dt,
                                                dv(P.d_res, d), dv(P.d_rhs, d + 1), active, st));
         OHM_TRY(down_dense(d + 1));
-        if (nuc2 & 1) {
-            OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), dv(P.d_e, d + 1), dv(P.d_tmp, d), 3, 1, active, st,
+        const T *ec = ecur_of(d + 1);
+        if (nuc2 > 0 && h->dense[d].nptile == 0 && (!(nuc2 & 1) || may_end_in_tmp(d))) {
+            // the first sweep adds the prolonged coarser correction as it
+            // loads; the result stays where the last sweep put it
+            T *last = nullptr;
+            OHM_TRY(smooth_dense(d, nuc2, active, false, 0, ec, &last));
+            ecur[d] = last;
+        } else if (nuc2 & 1) {
+            OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), ec, dv(P.d_tmp, d), 3, 1, active, st,
                                             (const T *)dv(P.d_e, d)));
             OHM_TRY(smooth_dense(d, nuc2, active, false, SMOOTH_FROM_TMP));
         } else {
-            OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), dv(P.d_e, d + 1), dv(P.d_e, d), 3, 1, active, st));
+            OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), ec, dv(P.d_e, d), 3, 1, active, st));
             OHM_TRY(smooth_dense(d, nuc2, active, false));
         }
         return OHM_OK;
@@ -346,10 +365,11 @@ struct Solver {
         for (int d = 1; d <= D; ++d) OHM_TRY(coarsest(d));
         for (int d = D - 1; d >= 1; --d) {
             if (h->dense[d].ntile == 0) continue;
-            OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), dv(P.d_e, d + 1), dv(P.d_e, d), 3, 0, active, st));
+            OHM_TRY(launch_dense_prolong<T>(h, -(d + 1), ecur_of(d + 1), dv(P.d_e, d), 3, 0, active, st));
+            ecur[d] = dv(P.d_e, d);
             for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(-d, false));
         }
-        OHM_TRY(launch_prolong_blk<T>(h, -1, dv(P.d_e, 1), h->dense_cells[1], mg(P.e, 0), VN, 3, 0, active, st));
+        OHM_TRY(launch_prolong_blk<T>(h, -1, ecur_of(1), h->dense_cells[1], mg(P.e, 0), VN, 3, 0, active, st));
         for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(0, false));
         return OHM_OK;
     }

@@ -239,15 +239,18 @@ ohm_status launch_prolong_blk(const ohm_hier *h, int coarse_level, const T *coar
                               const T *base = nullptr);
 
 // dense multigrid levels (k_dense.hip)
-// nsweeps fused or two-pass sweeps; the result is always left in B.  flags:
-// SMOOTH_ZERO: the input is zero and is not read; SMOOTH_FROM_TMP: the input
-// is in tmp rather than B.  Sweep parities are arranged so that the fused
-// tiles need no final copy when the count allows it.
+// nsweeps fused or two-pass sweeps; the result is left in B, or, when `last`
+// is given, wherever the fused sweeps end (B or tmp, returned in *last).
+// flags: SMOOTH_ZERO: the input is zero and is not read; SMOOTH_FROM_TMP: the
+// input is in tmp rather than B.  Sweep parities are arranged so that the
+// fused tiles need no final copy when the count allows it.  coarse: the first
+// sweep adds the trilinear prolongation of the next coarser level's field as
+// it loads (coarse and last need a level of whole tiles, an input and a sweep).
 enum { SMOOTH_ZERO = 1, SMOOTH_FROM_TMP = 2 };
 template <typename T>
 ohm_status launch_dense_smooth(const ohm_hier *h, int level, T *B, T *tmp, const T *S, const T *eta,
                                const double *coef_dev, int nsweeps, bool all, const int *active, hipStream_t s,
-                               int flags = 0);
+                               int flags = 0, const T *coarse = nullptr, T **last = nullptr);
 // dense level -> next coarser: coarse = restriction of S - L B; res is scratch
 // for handles where some continuing problem is not made of 8^3 tiles
 template <typename T>

@@ -246,47 +246,6 @@ struct GhostBlockAddr {
     }
 };
 
-// Trilinear correction from the first dense level for the tile of a level-0
-// block: the 8^3 coarse cells covering the tile's parents and their
-// neighbours (origin 4 (i, j, k)_block - 2, periodic) are staged in LDS; the
-// weights and the order of the sum are those of k_prolong_dense_blk0.
-template <typename T>
-struct Level0Coarse {
-    static constexpr bool active = true;
-    const T *coarse;
-    long long ccs;
-    DenseProbDev q;
-    int i0, j0, k0;
-    T *sC;      // [3][512] in LDS
-    T r[3];
-    __device__ __forceinline__ void load()
-    {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int t = threadIdx.x + SWEEP_THREADS * k, c = t >> 9, m = t & 511;
-            const int i = (i0 + (m & 7) + q.nx) % q.nx, j = (j0 + ((m >> 3) & 7) + q.ny) % q.ny,
-                      kk = (k0 + (m >> 6) + q.nz) % q.nz;
-            r[k] = coarse[c * ccs + q.off + i + (long long)q.nx * (j + (long long)q.ny * kk)];
-        }
-    }
-    __device__ __forceinline__ void stage()
-    {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) sC[threadIdx.x + SWEEP_THREADS * k] = r[k];
-    }
-    __device__ __forceinline__ T add(int x, int y, int z, int c, T base) const
-    {
-        const int i = (x >> 1) + 2, j = (y >> 1) + 2, k = (z >> 1) + 2;
-        const int i1 = i + ((x & 1) ? 1 : -1), j1 = j + ((y & 1) ? 1 : -1), k1 = k + ((z & 1) ? 1 : -1);
-        const T *C = sC + 512 * c;
-        auto at = [](int a, int bb, int cc) { return a + 8 * (bb + 8 * cc); };
-        T v = T(27) * C[at(i, j, k)] + T(9) * (C[at(i1, j, k)] + C[at(i, j1, k)] + C[at(i, j, k1)]) +
-              T(3) * (C[at(i1, j1, k)] + C[at(i1, j, k1)] + C[at(i, j1, k1)]) + C[at(i1, j1, k1)];
-        v *= T(1.0 / 64.0);
-        return base + v;
-    }
-};
-
 // MODE 0: sweep B -> out; 1: zero input (B not read); 2: sweep of B plus the
 // prolonged correction from the first dense level (coarse), B -> out; MODE 3
 // and 4 as 0 and 1 on a level with coarse-fine ghost blocks (Bg, etag)
@@ -314,8 +273,8 @@ k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ p
         fused_sweep_tile<T, MODE == 4>(A, B, cs, S, eta, out, cih2, sB, sE);
     } else if constexpr (MODE == 2) {
         const BlockAddr A{snbr, b};
-        Level0Coarse<T> cor{coarse, ccs, dp[pr], 4 * ijk[3 * b] - 2, 4 * ijk[3 * b + 1] - 2, 4 * ijk[3 * b + 2] - 2,
-                            sC, {}};
+        TileCoarse<T> cor{coarse, ccs, dp[pr], 4 * ijk[3 * b] - 2, 4 * ijk[3 * b + 1] - 2, 4 * ijk[3 * b + 2] - 2,
+                          sC, {}};
         fused_sweep_tile<T, false>(A, B, cs, S, eta, out, cih2, sB, sE, cor);
     } else {
         const BlockAddr A{snbr, b};

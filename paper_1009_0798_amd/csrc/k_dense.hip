@@ -92,11 +92,15 @@ __device__ __forceinline__ DenseAddr dense_tile(const DenseProbDev &q, int t)
     return DenseAddr{q, 8 * (t % tx), 8 * ((t / tx) % ty), 8 * (t / (tx * ty))};
 }
 
-template <typename T, bool ZERO>
+// MODE 0: sweep B -> out; 1: zero input (B not read); 2: sweep of B plus the
+// trilinear prolongation of the next coarser grid's field (coarse, problems
+// cdp), B -> out, without storing the corrected input
+template <typename T, int MODE>
 __global__ void __launch_bounds__(SWEEP_THREADS)
 k_dense_sweep(const int *__restrict__ ftiles, const DenseProbDev *__restrict__ dp, const int *__restrict__ active,
               const double *__restrict__ coef_p, const T *__restrict__ B, long long cs, const T *__restrict__ S,
-              const T *__restrict__ eta, T *__restrict__ out)
+              const T *__restrict__ eta, T *__restrict__ out, const T *__restrict__ coarse, long long ccs,
+              const DenseProbDev *__restrict__ cdp)
 {
     __shared__ T sB[3][TC2];
     __shared__ T sE[TC2];
@@ -104,7 +108,14 @@ k_dense_sweep(const int *__restrict__ ftiles, const DenseProbDev *__restrict__ d
     if (active && !active[pr]) return;
     const DenseProbDev q = dp[pr];
     const DenseAddr A = dense_tile(q, t);
-    fused_sweep_tile<T, ZERO>(A, B, cs, S, eta, out, T(coef_p[pr]) * T(q.inv_h2), sB, sE);
+    const T cih2 = T(coef_p[pr]) * T(q.inv_h2);
+    if constexpr (MODE == 2) {
+        __shared__ T sC[3 * 512];
+        TileCoarse<T> cor{coarse, ccs, cdp[pr], A.ox / 2 - 2, A.oy / 2 - 2, A.oz / 2 - 2, sC, {}};
+        fused_sweep_tile<T, false>(A, B, cs, S, eta, out, cih2, sB, sE, cor);
+    } else {
+        fused_sweep_tile<T, MODE == 1>(A, B, cs, S, eta, out, cih2, sB, sE);
+    }
 }
 
 // copy (src != nullptr) or zero the cells of the listed 8^3 tiles (3 components)
@@ -456,7 +467,7 @@ ohm_status launch_dense_stencil(const ohm_hier *h, int level, int mode, const T 
 template <typename T>
 ohm_status launch_dense_smooth(const ohm_hier *h, int level, T *B, T *tmp, const T *S, const T *eta,
                                const double *coef_dev, int nsweeps, bool all, const int *active, hipStream_t s,
-                               int flags)
+                               int flags, const T *coarse, T **last)
 {
     const DenseLevelDev &D = h->dense[-level];
     const long long cs = D.ncells;
@@ -465,6 +476,10 @@ ohm_status launch_dense_smooth(const ohm_hier *h, int level, T *B, T *tmp, const
     const bool zero = flags & SMOOTH_ZERO, from_tmp = (flags & SMOOTH_FROM_TMP) && !zero;
     if (nft > 0 && (unsigned long long)cs * sizeof(T) > 0xFFFFFFFFull)
         return fail(OHM_ERR_ARG, "dense level %d: fused sweep addresses each field array with 32-bit offsets", level);
+    if ((coarse || last) && (npt > 0 || zero || nsweeps < 1 || -level >= -h->min_level))
+        return fail(OHM_ERR_ARG, "dense level %d: a fused coarse correction or a result left in place needs whole "
+                                 "tiles, an input, a sweep and a coarser level", level);
+    const DenseLevelDev *Dc = coarse ? &h->dense[-level + 1] : nullptr;
     if (nft > 0) {
         // fused tiles ping-pong between B and tmp; a zero input is not read, so
         // the first sweep may write either buffer: pick the one that makes the
@@ -474,17 +489,23 @@ ohm_status launch_dense_smooth(const ohm_hier *h, int level, T *B, T *tmp, const
             T *dst;
             if (k == 0 && zero) {
                 dst = (nsweeps & 1) ? B : tmp;
-                k_dense_sweep<T, true><<<nft, SWEEP_THREADS, 0, s>>>(ft, D.probs, active, coef_dev, nullptr, cs, S, eta,
-                                                                     dst);
+                k_dense_sweep<T, 1><<<nft, SWEEP_THREADS, 0, s>>>(ft, D.probs, active, coef_dev, nullptr, cs, S, eta,
+                                                                  dst, nullptr, 0, nullptr);
+            } else if (k == 0 && coarse) {
+                dst = cur == B ? tmp : B;
+                k_dense_sweep<T, 2><<<nft, SWEEP_THREADS, 0, s>>>(ft, D.probs, active, coef_dev, cur, cs, S, eta,
+                                                                  dst, coarse, Dc->ncells, Dc->probs);
             } else {
                 dst = cur == B ? tmp : B;
-                k_dense_sweep<T, false><<<nft, SWEEP_THREADS, 0, s>>>(ft, D.probs, active, coef_dev, cur, cs, S, eta,
-                                                                      dst);
+                k_dense_sweep<T, 0><<<nft, SWEEP_THREADS, 0, s>>>(ft, D.probs, active, coef_dev, cur, cs, S, eta,
+                                                                  dst, nullptr, 0, nullptr);
             }
             OHM_TRY(check_launch("dense fused sweep"));
             cur = dst;
         }
-        if (nsweeps == 0 && zero) {
+        if (last) {
+            *last = cur;   // the caller takes the result where the sweeps left it
+        } else if (nsweeps == 0 && zero) {
             k_dense_tile_copy<T><<<nft, 256, 0, s>>>(ft, D.probs, active, nullptr, B, cs);
             OHM_TRY(check_launch("dense tile zero"));
         } else if (cur != B) {
@@ -685,7 +706,8 @@ size_t coarse_job_bytes() { return sizeof(CoarseJob); }
 
 #define INST(T)                                                                                                \
     template ohm_status launch_dense_smooth<T>(const ohm_hier *, int, T *, T *, const T *, const T *,           \
-                                               const double *, int, bool, const int *, hipStream_t, int);      \
+                                               const double *, int, bool, const int *, hipStream_t, int,       \
+                                               const T *, T **);                                               \
     template ohm_status launch_dense_stencil<T>(const ohm_hier *, int, int, const T *, const T *, const T *,   \
                                                 const double *, T *, int, bool, const int *, hipStream_t);     \
     template ohm_status launch_dense_restrict<T>(const ohm_hier *, int, const T *, T *, int, const int *,      \

@@ -22,6 +22,7 @@
 // LDS (a barrier follows) and add(x, y, z, c, v) returns v plus the correction.
 #pragma once
 
+#include "common.h"
 #include "stencil.h"
 
 namespace ohm {
@@ -65,6 +66,48 @@ __device__ __forceinline__ void store_at(T *base, unsigned off, T v)
 {
     *(T *)((char *)base + off) = v;
 }
+
+// Trilinear correction (27/9/3/1 over 64) from the next coarser grid, a dense
+// grid q, for the tile of fine origin 8 (i, j, k): the 8^3 coarse cells that
+// hold the parents of the tile's cells and their neighbours (origin
+// 4 (i, j, k) - 2, periodic) are staged in LDS; the weights and the order of
+// the sum are those of the stand-alone prolongation kernels.
+template <typename T>
+struct TileCoarse {
+    static constexpr bool active = true;
+    const T *coarse;
+    long long ccs;
+    DenseProbDev q;
+    int i0, j0, k0;
+    T *sC;      // [3][512] in LDS
+    T r[3];
+    __device__ __forceinline__ void load()
+    {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int t = threadIdx.x + SWEEP_THREADS * k, c = t >> 9, m = t & 511;
+            const int i = (i0 + (m & 7) + q.nx) % q.nx, j = (j0 + ((m >> 3) & 7) + q.ny) % q.ny,
+                      kk = (k0 + (m >> 6) + q.nz) % q.nz;
+            r[k] = coarse[c * ccs + q.off + i + (long long)q.nx * (j + (long long)q.ny * kk)];
+        }
+    }
+    __device__ __forceinline__ void stage()
+    {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) sC[threadIdx.x + SWEEP_THREADS * k] = r[k];
+    }
+    __device__ __forceinline__ T add(int x, int y, int z, int c, T base) const
+    {
+        const int i = (x >> 1) + 2, j = (y >> 1) + 2, k = (z >> 1) + 2;
+        const int i1 = i + ((x & 1) ? 1 : -1), j1 = j + ((y & 1) ? 1 : -1), k1 = k + ((z & 1) ? 1 : -1);
+        const T *C = sC + 512 * c;
+        auto at = [](int a, int bb, int cc) { return a + 8 * (bb + 8 * cc); };
+        T v = T(27) * C[at(i, j, k)] + T(9) * (C[at(i1, j, k)] + C[at(i, j1, k)] + C[at(i, j, k1)]) +
+              T(3) * (C[at(i1, j1, k)] + C[at(i1, j, k1)] + C[at(i, j1, k1)]) + C[at(i1, j1, k1)];
+        v *= T(1.0 / 64.0);
+        return base + v;
+    }
+};
 
 template <typename T, bool ZERO, typename Addr, typename Coarse = NoCoarse<T>>
 __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restrict__ B, long long cs,
