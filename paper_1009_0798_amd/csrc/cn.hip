@@ -573,6 +573,15 @@ struct Solver {
                              at<double>(P.ph), at<double>(P.sh), at<double>(P.s), at<double>(P.t),
                              at<double>(P.r), at<double>(P.rhat), at<double>(P.part), st));
             OHM_TRY(reduce_scal(2, 4));
+            return copy_dots(2);
+    }
+    // the first nq * nprob norms to the handle's pinned host buffer (part of a
+    // captured iteration: one node, no separate copy command); read after a
+    // synchronisation of the stream
+    ohm_status copy_dots(int nq)
+    {
+        OHM_HIP(hipMemcpyAsync(h->h_dots, at<double>(P.dots), sizeof(double) * nq * h->nprob, hipMemcpyDeviceToHost,
+                               st));
         return OHM_OK;
     }
 
@@ -583,16 +592,16 @@ struct Solver {
         OHM_TRY(vaxpy1((int)P.NBt, mlprob, active, VN, at<double>(P.x), at<double>(P.ph), st));
         OHM_TRY(composite(P.x, P.r, MODE_RESID, lam_dt, neg_lam_dt, P.S));
         const double *xs[1] = {at<double>(P.r)};
-        return dots(xs, xs, 1);
+        OHM_TRY(dots(xs, xs, 1));
+        return copy_dots(1);
     }
 
+    // the norms an iteration copied to the pinned buffer (stride nq)
     ohm_status read_dots(int nq, std::vector<double> &out)
     {
-        std::vector<double> d((size_t)h->nprob * nq);
-        OHM_HIP(hipMemcpyAsync(d.data(), at<double>(P.dots), sizeof(double) * d.size(), hipMemcpyDeviceToHost, st));
         OHM_HIP(hipStreamSynchronize(st));
         out.assign(h->nprob, 0.0);
-        for (int p = 0; p < h->nprob; ++p) out[p] = d[(size_t)p * nq];
+        for (int p = 0; p < h->nprob; ++p) out[p] = h->h_dots[(size_t)p * nq];
         return OHM_OK;
     }
 
@@ -726,10 +735,8 @@ struct Solver {
                 while (it_total < maxit) {
                     OHM_TRY(replay(1, [&]() { return bicg_iter(); }));
                     ++it_total;
-                    std::vector<double> d((size_t)np * 2);
-                    OHM_HIP(hipMemcpyAsync(d.data(), at<double>(P.dots), sizeof(double) * 2 * np, hipMemcpyDeviceToHost,
-                                           st));
                     OHM_HIP(hipStreamSynchronize(st));
+                    const double *d = h->h_dots;
                     bool any_inner = false;
                     for (int p = 0; p < np; ++p)
                         if (inner[p]) {

@@ -136,6 +136,7 @@ struct ohm_hier {
     double *d_part = nullptr;        // reduction partials
     size_t part_cap = 0;
     double *d_norms = nullptr;       // [nprob * 6]
+    double *h_dots = nullptr;        // pinned host copy of an iteration's norms [8 * nprob]
     // ring of device slots for per-problem coefficients passed by the host to
     // the primitive calls (slot reuse waits on the event of its last use)
     double *d_ring = nullptr;        // [RING][nprob]

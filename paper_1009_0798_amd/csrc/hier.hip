@@ -481,6 +481,7 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
     // ---- scratch ---------------------------------------------------------------
     OHM_HIP(hipMalloc((void **)&H->d_scal, sizeof(double) * 4 * nprob));
     OHM_HIP(hipMalloc((void **)&H->d_norms, sizeof(double) * 8 * nprob));
+    OHM_HIP(hipHostMalloc((void **)&H->h_dots, sizeof(double) * 8 * nprob, hipHostMallocDefault));
     size_t maxnb = 1;
     for (int l = 0; l < H->nlev; ++l) maxnb = std::max(maxnb, (size_t)H->nb_host[l]);
     H->part_cap = maxnb * 8 + 2 * (size_t)nprob * OHM_MAX_LEVELS + 64;
@@ -510,6 +511,7 @@ static void free_all(ohm_hier *H)
     void *ptrs[] = {H->d_scal, H->d_part, H->d_norms, H->d_coarse_inv, H->d_ring, H->d_coarse_eta, H->d_coarse_flags};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    if (H->h_dots) (void)hipHostFree(H->h_dots);
     for (int i = 0; i < 64; ++i)
         if (H->ring_ev[i]) (void)hipEventDestroy(H->ring_ev[i]);
     if (H->graph_exec) (void)hipGraphExecDestroy(H->graph_exec);
