@@ -167,9 +167,9 @@ struct Solver {
         return launch_reduce_problem(h->nprob, nlev(), at<long long>(P.ranges), at<double>(P.part), k, ksum, out, st);
     }
 
-    ohm_status dots(const double *const *x, const double *const *y, int nq, int stage = -1)
+    ohm_status dots(const double *const *x, const double *const *y, int nq, int stage = -1, double *copy = nullptr)
     {
-        OHM_TRY(vdot((int)P.NBt, mlprob, active, VN, x, y, nq, at<double>(P.part), st));
+        OHM_TRY(vdot((int)P.NBt, mlprob, active, VN, x, y, nq, at<double>(P.part), st, copy));
         return reduce_scal(nq, stage);
     }
     // per-problem sums of the nq partials into dots, then BiCGStab scalar
@@ -722,14 +722,13 @@ struct Solver {
             // residual has converged but the true one has not
             int it_total = 0;
             while (any() && it_total < maxit) {
-                // restart: rhat = r, p = v = 0, rho = alpha = omega = 1
-                const long long n = 3 * P.NBt * NC;
-                OHM_TRY(vconvert<double, double>(at<double>(P.r), at<double>(P.rhat), n, st));
-                OHM_TRY(vfill<double>(at<double>(P.p), n, 0.0, st));
-                OHM_TRY(vfill<double>(at<double>(P.v), n, 0.0, st));
+                // restart: rhat = r (copied by the dot kernel that forms
+                // (r, r)), rho = alpha = omega = 1, and a first direction p = r
+                // (the scalar stage sets beta = 0, which the direction update
+                // reads as p = v = 0, so neither is filled)
                 {
                     const double *xs[1] = {at<double>(P.r)};
-                    OHM_TRY(dots(xs, xs, 1, 0));
+                    OHM_TRY(dots(xs, xs, 1, 0, at<double>(P.rhat)));
                 }
                 std::vector<int> inner(act);
                 while (it_total < maxit) {

@@ -281,7 +281,7 @@ ohm_status vconvert(const S *a, D *b, long long n, hipStream_t s);
 template <typename S, typename D>
 ohm_status vcopy_level(const S *a, long long acs, D *b, long long bcs, long long n, int ncomp, hipStream_t s);
 ohm_status vdot(int nblk, const int *prob_of, const int *active, long long cs, const double *const *x,
-                const double *const *y, int nq, double *part, hipStream_t s);
+                const double *const *y, int nq, double *part, hipStream_t s, double *copy = nullptr);
 ohm_status vnorms(int nblk, const int *prob_of, const int *active, long long cs, const double *x, double *part,
                   hipStream_t s);
 ohm_status vbicg_p(int nblk, const int *prob_of, const int *active, long long cs, const double *scal,

@@ -43,6 +43,7 @@ __global__ void k_copy_level(const S *__restrict__ a, long long acs, D *__restri
 struct DotArgs {
     const double *x[3];
     const double *y[3];
+    double *copy;   // when set, also receives x[0] (the products' operand, unchanged)
 };
 
 __global__ void __launch_bounds__(256)
@@ -60,6 +61,7 @@ k_dot(int nblk, const int *__restrict__ prob_of, const int *__restrict__ active,
         const int c = t / NC, cell = t % NC;
         const long long gi = c * cs + (long long)b * NC + cell;
         for (int q = 0; q < nq; ++q) acc[q] += a.x[q][gi] * a.y[q][gi];
+        if (a.copy) a.copy[gi] = a.x[0][gi];
     }
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int q = 0; q < nq; ++q) {
@@ -124,6 +126,13 @@ k_bicg_p(int nblk, const int *__restrict__ prob_of, const int *__restrict__ acti
     const int pr = prob_of[b];
     if (active && !active[pr]) return;
     const double beta = scal[SC_N * pr + SC_BETA], omega = scal[SC_N * pr + SC_OMEGA];
+    if (beta == 0.0) {   // restart: p = r; p and v are not read (they hold no state yet)
+        for (int t = threadIdx.x; t < 3 * NC; t += 256) {
+            const long long gi = (t / NC) * cs + (long long)b * NC + t % NC;
+            p[gi] = r[gi];
+        }
+        return;
+    }
     for (int t = threadIdx.x; t < 3 * NC; t += 256) {
         const long long gi = (t / NC) * cs + (long long)b * NC + t % NC;
         p[gi] = r[gi] + beta * (p[gi] - omega * v[gi]);
@@ -240,6 +249,9 @@ __device__ __forceinline__ void scal_update(int stage, double *S, const double *
         S[SC_BETA] = (rn / S[SC_RHO]) * (S[SC_ALPHA] / S[SC_OMEGA]);
         S[SC_RHO] = rn;
     }
+    // a restart starts the direction from p = v = 0, so its first p is r: the
+    // direction update takes beta = 0 as "p = r" and reads neither p nor v
+    if (stage == 0) S[SC_BETA] = 0.0;
 }
 
 // per-problem scalar updates (one thread per problem) from reduced products
@@ -321,9 +333,10 @@ ohm_status vcopy_level(const S *a, long long acs, D *b, long long bcs, long long
 }
 
 ohm_status vdot(int nblk, const int *prob_of, const int *active, long long cs, const double *const *x,
-                const double *const *y, int nq, double *part, hipStream_t s)
+                const double *const *y, int nq, double *part, hipStream_t s, double *copy)
 {
     DotArgs a;
+    a.copy = copy;
     for (int q = 0; q < 3; ++q) {
         a.x[q] = q < nq ? x[q] : nullptr;
         a.y[q] = q < nq ? y[q] : nullptr;
