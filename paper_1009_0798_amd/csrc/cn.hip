@@ -29,7 +29,7 @@ struct Plan {
     size_t x, r, rhat, p, v, s, t, ph, sh, S, og, oeg;
     size_t rhs, e, tmp, res, mg_g, eta_t, eta_tg;
     size_t d_rhs[16], d_e[16], d_tmp[16], d_res[16], d_eta[16], d_eta64[16];
-    size_t inv, aug, jobs, part, dots, scal, ranges, mlprob, active, cmask, coefs;
+    size_t inv, aug, jobs, force, part, dots, scal, ranges, mlprob, active, cmask, coefs;
     size_t inv_elems = 0, aug_elems = 0;
 };
 
@@ -82,10 +82,15 @@ Plan make_plan(const ohm_hier *h, const ohm_cn_opts *o)
     coarse_sizes(h, &P.inv_elems, &P.aug_elems);
     P.inv = take(8 * P.inv_elems + 8);
     P.aug = take(8 * P.aug_elems + 8);
-    P.jobs = take(coarse_job_bytes() * (size_t)h->nprob * 17 + 8);
     P.part = take(8 * (size_t)P.NBt * 8);
     P.dots = take(8 * (size_t)h->nprob * 8);
     P.scal = take(8 * (size_t)h->nprob * scal_stride());
+    // tables the host builds each step, contiguous from jobs to coefs (one
+    // staged upload): coarse jobs and force flags per depth, block ranges
+    // per problem and level, block -> problem, active flags, coarse masks,
+    // coefficients
+    P.jobs = take(coarse_job_bytes() * (size_t)h->nprob * 17 + 8);
+    P.force = take(4 * (size_t)h->nprob * 17);
     P.ranges = take(8 * (size_t)h->nprob * OHM_MAX_LEVELS * 2);
     P.mlprob = take(4 * (size_t)P.NBt);
     P.active = take(4 * (size_t)h->nprob);
@@ -425,10 +430,26 @@ struct Solver {
         const int np = h->nprob, L = nlev();
         VN = P.NBt * NC;
         GN = P.NGt * NC;
-        // tables: multi-level block -> problem, per-problem block ranges
-        std::vector<int> mp;
-        mp.reserve(P.NBt);
-        for (int l = 0; l < L; ++l) mp.insert(mp.end(), h->blk_prob_host[l].begin(), h->blk_prob_host[l].end());
+        // the step's tables, built on the host in pinned staging memory laid
+        // out like the workspace region from jobs to coefs, then one upload
+        const size_t tab0 = P.jobs, tab_bytes = P.coefs + 8 * (size_t)np * 4 - P.jobs;
+        if (h->stage_live) OHM_HIP(hipEventSynchronize(h->stage_ev));   // the previous upload is done
+        h->stage_live = false;
+        if (h->stage_bytes < tab_bytes) {
+            if (h->h_stage) OHM_HIP(hipHostFree(h->h_stage));
+            h->h_stage = nullptr;
+            h->stage_bytes = 0;
+            OHM_HIP(hipHostMalloc((void **)&h->h_stage, tab_bytes, hipHostMallocDefault));
+            h->stage_bytes = tab_bytes;
+        }
+        if (!h->stage_ev) OHM_HIP(hipEventCreateWithFlags(&h->stage_ev, hipEventDisableTiming));
+        char *stg = h->h_stage;
+        auto host = [&](size_t off) { return stg + (off - tab0); };
+        // multi-level block -> problem, per-problem block ranges
+        {
+            int *mp = (int *)host(P.mlprob);
+            for (int l = 0; l < L; ++l) mp = std::copy(h->blk_prob_host[l].begin(), h->blk_prob_host[l].end(), mp);
+        }
         ranges_host.assign((size_t)np * L * 2, 0);
         for (int p = 0; p < np; ++p)
             for (int l = 0; l < L; ++l) {
@@ -441,6 +462,7 @@ struct Solver {
                 ranges_host[2 * ((size_t)p * L + l)] = b0;
                 ranges_host[2 * ((size_t)p * L + l) + 1] = b1;
             }
+        std::copy(ranges_host.begin(), ranges_host.end(), (long long *)host(P.ranges));
         std::vector<double> coefs(4 * (size_t)np);
         for (int p = 0; p < np; ++p) {
             if (!(dt[p] > 0.0) || !std::isfinite(dt[p])) return fail(OHM_ERR_ARG, "dt[%d] must be positive", p);
@@ -448,13 +470,30 @@ struct Solver {
             coefs[np + p] = -(1.0 - o->lambda) * dt[p];
             coefs[2 * np + p] = -o->lambda * dt[p];
         }
-        OHM_HIP(hipMemcpyAsync(at<int>(P.mlprob), mp.data(), sizeof(int) * mp.size(), hipMemcpyHostToDevice, st));
-        OHM_HIP(hipMemcpyAsync(at<long long>(P.ranges), ranges_host.data(), sizeof(long long) * ranges_host.size(),
-                               hipMemcpyHostToDevice, st));
-        OHM_HIP(hipMemcpyAsync(at<double>(P.coefs), coefs.data(), sizeof(double) * coefs.size(), hipMemcpyHostToDevice,
-                               st));
+        std::copy(coefs.begin(), coefs.end(), (double *)host(P.coefs));
         std::vector<int> ones(np, 1);
-        OHM_HIP(hipMemcpyAsync(at<int>(P.active), ones.data(), sizeof(int) * np, hipMemcpyHostToDevice, st));
+        std::copy(ones.begin(), ones.end(), (int *)host(P.active));
+        // coarsest grids: a dense inverse (job tables, force flags) or, for
+        // grids above 768 unknowns, smoothing sweeps (mask per depth)
+        njobs.assign(17, 0);
+        has_big.assign(17, 0);
+        {
+            int *cm = (int *)host(P.cmask);
+            std::fill(cm, cm + (size_t)np * 17, 0);
+            for (int p = 0; p < np; ++p) {
+                const ohm_prob_host &Q = h->probs[p];
+                const int dd = -Q.min_level;
+                const int *dm = Q.dims[dd];
+                if (3LL * dm[0] * dm[1] * dm[2] > 768) {
+                    has_big[dd] = 1;
+                    cm[(size_t)np * dd + p] = 1;
+                }
+            }
+        }
+        if (multigrid) coarse_plan(h, coefs.data(), host(P.jobs), (int *)host(P.force), njobs.data());
+        OHM_HIP(hipMemcpyAsync(at<char>(tab0), stg, tab_bytes, hipMemcpyHostToDevice, st));
+        OHM_HIP(hipEventRecord(h->stage_ev, st));
+        h->stage_live = true;
         act_dev = ones;
         mlprob = at<int>(P.mlprob);
         active_mut = at<int>(P.active);
@@ -489,30 +528,11 @@ struct Solver {
         }
         // coarsest grids: dense inverses (kept in the handle, rebuilt when
         // lam_dt or the coarsest resistivity changes)
-        njobs.assign(17, 0);
-        has_big.assign(17, 0);
-        std::vector<int> cmask((size_t)np * 17, 0);
-        for (int p = 0; p < np; ++p) {
-            const ohm_prob_host &Q = h->probs[p];
-            const int dd = -Q.min_level;
-            const int *dm = Q.dims[dd];
-            if (3LL * dm[0] * dm[1] * dm[2] > 768) {
-                has_big[dd] = 1;
-                cmask[(size_t)np * dd + p] = 1;
-            }
-        }
-        OHM_HIP(hipMemcpyAsync(at<int>(P.cmask), cmask.data(), sizeof(int) * cmask.size(), hipMemcpyHostToDevice, st));
-        for (int d = 1; d <= D; ++d) {
-            void *jobs = at<char>(P.jobs) + coarse_job_bytes() * (size_t)np * d;
-            int nj = 0;
-            OHM_TRY(upload_coarse_jobs(h, d, jobs, &nj, st));
-            njobs[d] = nj;
-        }
         if (P.inv_elems > 0) {
             std::vector<const double *> ed(17, nullptr);
             for (int d = 1; d <= D; ++d) ed[d] = at<double>(P.d_eta64[d]);
-            void *jobs_tmp = at<char>(P.jobs);   // depth-0 slot is free for the build
-            OHM_TRY(build_coarse_inverses(h, ed.data(), coefs.data(), nullptr, at<double>(P.aug), jobs_tmp, st));
+            OHM_TRY(launch_coarse_build(h, ed.data(), at<char>(P.jobs), at<int>(P.force), njobs.data(),
+                                        at<double>(P.aug), st));
         }
         // x = b (user B), S = b - (1 - lambda) dt div F(b) on leaf cells
         for (int l = 0; l < L; ++l)

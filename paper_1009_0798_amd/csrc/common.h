@@ -137,6 +137,10 @@ struct ohm_hier {
     size_t part_cap = 0;
     double *d_norms = nullptr;       // [nprob * 6]
     double *h_dots = nullptr;        // pinned host copy of an iteration's norms [8 * nprob]
+    char *h_stage = nullptr;         // pinned staging of a step's host-built tables
+    size_t stage_bytes = 0;
+    hipEvent_t stage_ev = nullptr;   // recorded after the staged upload
+    bool stage_live = false;
     // ring of device slots for per-problem coefficients passed by the host to
     // the primitive calls (slot reuse waits on the event of its last use)
     double *d_ring = nullptr;        // [RING][nprob]
@@ -265,10 +269,16 @@ ohm_status launch_dense_prolong(const ohm_hier *h, int coarse_level, const T *co
                                 int accumulate, const int *active, hipStream_t s, const T *base = nullptr);
 ohm_status coarse_sizes(const ohm_hier *h, size_t *inv_elems, size_t *aug_elems);
 size_t coarse_job_bytes();
-size_t coarse_job_count(const ohm_hier *h, int depth);
-ohm_status build_coarse_inverses(ohm_hier *h, const double *const *eta_dense, const double *lam_dt_host,
-                                 double *inv, double *aug, void *jobs_dev, hipStream_t s);
-ohm_status upload_coarse_jobs(const ohm_hier *h, int depth, void *jobs_dev, int *njobs, hipStream_t s);
+// Coarsest grids with at most 768 unknowns take a dense inverse kept in the
+// handle.  coarse_plan fills, on the host, the job table of a step (per depth
+// d, the jobs at slots d * nprob ...) and a force flag per job (lam_dt differs
+// from the one the inverse was built for), and records the new lam_dt;
+// launch_coarse_build then rebuilds, from the uploaded tables, every inverse
+// that is forced or whose coarsest resistivity (eta_dense[d], FP64) changed.
+// Scratch `aug` holds sum 2 n3^2 doubles.
+void coarse_plan(ohm_hier *h, const double *lam_dt_host, void *jobs_host, int *force_host, int *njobs);
+ohm_status launch_coarse_build(ohm_hier *h, const double *const *eta_dense, const void *jobs_dev,
+                               const int *force_dev, const int *njobs, double *aug, hipStream_t s);
 template <typename T>
 ohm_status launch_coarse_apply(const ohm_hier *h, int depth, const void *jobs_dev, int njobs, const double *inv,
                                const T *r, T *e, const int *active, hipStream_t s);

@@ -512,6 +512,9 @@ static void free_all(ohm_hier *H)
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     if (H->h_dots) (void)hipHostFree(H->h_dots);
+    if (H->stage_ev) (void)hipEventSynchronize(H->stage_ev);
+    if (H->h_stage) (void)hipHostFree(H->h_stage);
+    if (H->stage_ev) (void)hipEventDestroy(H->stage_ev);
     for (int i = 0; i < 64; ++i)
         if (H->ring_ev[i]) (void)hipEventDestroy(H->ring_ev[i]);
     if (H->graph_exec) (void)hipGraphExecDestroy(H->graph_exec);

@@ -575,12 +575,6 @@ ohm_status launch_dense_prolong(const ohm_hier *h, int coarse_level, const T *co
     return check_launch("dense prolong");
 }
 
-// Coarsest-grid inverses for every problem whose coarsest grid has at most
-// OHM_COARSE_MAX unknowns.  eta_dense[d] points at FP64 resistivity of dense
-// level -d.  Scratch `aug` must hold sum 2 n3^2 doubles.
-ohm_status build_coarse_inverses(ohm_hier *h, const double *const *eta_dense, const double *lam_dt_host,
-                                 double *inv, double *aug, void *jobs_dev, hipStream_t s);
-ohm_status coarse_sizes(const ohm_hier *h, size_t *inv_elems, size_t *aug_elems);
 
 constexpr int COARSE_MAX = 768;
 
@@ -633,56 +627,57 @@ static std::vector<CoarseJob> coarse_jobs(const ohm_hier *h, const double *lam_d
     return jobs;
 }
 
-size_t coarse_job_count(const ohm_hier *h, int depth)
+void coarse_plan(ohm_hier *h, const double *lam_dt_host, void *jobs_host, int *force_host, int *njobs)
 {
-    return coarse_jobs(h, nullptr, depth).size();
+    for (int d = 0; d < 17; ++d) njobs[d] = 0;
+    if (h->cinv_lamdt.size() != (size_t)h->nprob) h->cinv_lamdt.assign(h->nprob, -1.0);
+    CoarseJob *J = (CoarseJob *)jobs_host;
+    for (int d = 1; d <= -h->min_level; ++d) {
+        const std::vector<CoarseJob> jobs = coarse_jobs(h, lam_dt_host, d);
+        for (size_t j = 0; j < jobs.size(); ++j) {
+            const int p = jobs[j].prob;
+            J[(size_t)d * h->nprob + j] = jobs[j];
+            force_host[(size_t)d * h->nprob + j] = (h->cinv_lamdt[p] != lam_dt_host[p]) ? 1 : 0;
+            h->cinv_lamdt[p] = lam_dt_host[p];
+        }
+        njobs[d] = (int)jobs.size();
+    }
 }
 
-ohm_status build_coarse_inverses(ohm_hier *h, const double *const *eta_dense, const double *lam_dt_host,
-                                 double *inv, double *aug, void *jobs_dev, hipStream_t s)
+ohm_status launch_coarse_build(ohm_hier *h, const double *const *eta_dense, const void *jobs_dev,
+                               const int *force_dev, const int *njobs, double *aug, hipStream_t s)
 {
-    // inverses live in the handle and are rebuilt only for problems whose
-    // lam_dt or coarsest resistivity changed since the last build
+    // inverses live in the handle; each job is rebuilt only when forced (new
+    // lam_dt) or when its coarsest resistivity differs from the saved copy
     size_t inv_elems = 0, aug_elems = 0;
     coarse_sizes(h, &inv_elems, &aug_elems);
-    (void)inv;
     if (inv_elems == 0) return OHM_OK;
     if (!h->d_coarse_inv) {
         OHM_HIP(hipMalloc((void **)&h->d_coarse_inv, sizeof(double) * inv_elems));
         // saved resistivity: one cells-sized slot at inv_off / n3 per job
         OHM_HIP(hipMalloc((void **)&h->d_coarse_eta, sizeof(double) * inv_elems));
-        OHM_HIP(hipMalloc((void **)&h->d_coarse_flags, sizeof(int) * 2 * (size_t)h->nprob));
-        h->cinv_lamdt.assign(h->nprob, -1.0);
+        OHM_HIP(hipMalloc((void **)&h->d_coarse_flags, sizeof(int) * (size_t)h->nprob));
     }
-    for (int dd = 1; dd <= -h->min_level; ++dd) {
-        std::vector<CoarseJob> jobs = coarse_jobs(h, lam_dt_host, dd);
-        if (jobs.empty()) continue;
-        std::vector<int> force(jobs.size());
-        for (size_t j = 0; j < jobs.size(); ++j) {
-            const int p = jobs[j].prob;
-            force[j] = (h->cinv_lamdt[p] != lam_dt_host[p]) ? 1 : 0;
-            h->cinv_lamdt[p] = lam_dt_host[p];
-        }
-        CoarseJob *jd = (CoarseJob *)jobs_dev;
-        int *fl = h->d_coarse_flags, *fo = h->d_coarse_flags + h->nprob;
-        OHM_HIP(hipMemcpyAsync(jd, jobs.data(), sizeof(CoarseJob) * jobs.size(), hipMemcpyHostToDevice, s));
-        OHM_HIP(hipMemcpyAsync(fo, force.data(), sizeof(int) * force.size(), hipMemcpyHostToDevice, s));
-        k_coarse_check<<<(unsigned)jobs.size(), 256, 0, s>>>(jd, fo, eta_dense[dd], h->d_coarse_eta, fl);
-        OHM_TRY(check_launch("coarse check"));
+    for (int d = 1; d <= -h->min_level; ++d) {
+        if (njobs[d] == 0) continue;
+        const CoarseJob *jd = (const CoarseJob *)jobs_dev + (size_t)d * h->nprob;
+        const int *fo = force_dev + (size_t)d * h->nprob;
+        int *fl = h->d_coarse_flags;   // reused per depth: the launches are stream-ordered
         int maxn = 0;
-        for (auto &J : jobs) maxn = std::max(maxn, J.n3);
-        dim3 g(maxn, (unsigned)jobs.size());
-        k_coarse_assemble<<<g, 256, 0, s>>>(jd, fl, eta_dense[dd], aug);
+        for (const CoarseJob &J : coarse_jobs(h, nullptr, d)) maxn = std::max(maxn, J.n3);
+        k_coarse_check<<<(unsigned)njobs[d], 256, 0, s>>>(jd, fo, eta_dense[d], h->d_coarse_eta, fl);
+        OHM_TRY(check_launch("coarse check"));
+        dim3 g(maxn, (unsigned)njobs[d]);
+        k_coarse_assemble<<<g, 256, 0, s>>>(jd, fl, eta_dense[d], aug);
         OHM_TRY(check_launch("coarse assemble"));
-        k_coarse_invert<<<(unsigned)jobs.size(), dim3(32, 32), 0, s>>>(jd, fl, aug, h->d_coarse_inv);
+        k_coarse_invert<<<(unsigned)njobs[d], dim3(32, 32), 0, s>>>(jd, fl, aug, h->d_coarse_inv);
         OHM_TRY(check_launch("coarse invert"));
-        OHM_HIP(hipStreamSynchronize(s));   // the job table is reused per depth
     }
     return OHM_OK;
 }
 
 // x = inverse * r on the coarsest grid of every problem whose coarsest level is
-// -depth (jobs_dev filled by upload_coarse_jobs for that depth)
+// -depth (jobs_dev: that depth's slots of the step's job table)
 template <typename T>
 ohm_status launch_coarse_apply(const ohm_hier *h, int depth, const void *jobs_dev, int njobs, const double *inv,
                                const T *r, T *e, const int *active, hipStream_t s)
@@ -693,14 +688,6 @@ ohm_status launch_coarse_apply(const ohm_hier *h, int depth, const void *jobs_de
     return check_launch("coarse apply");
 }
 
-ohm_status upload_coarse_jobs(const ohm_hier *h, int depth, void *jobs_dev, int *njobs, hipStream_t s)
-{
-    std::vector<CoarseJob> jobs = coarse_jobs(h, nullptr, depth);
-    *njobs = (int)jobs.size();
-    if (!jobs.empty())
-        OHM_HIP(hipMemcpyAsync(jobs_dev, jobs.data(), sizeof(CoarseJob) * jobs.size(), hipMemcpyHostToDevice, s));
-    return OHM_OK;
-}
 
 size_t coarse_job_bytes() { return sizeof(CoarseJob); }
 
