@@ -423,9 +423,12 @@ struct Solver {
     }
 
     // ---- setup ----------------------------------------------------------------
-    // multigrid = false: only what the explicit scheme needs (tables,
-    // coefficients, coarse-fine ghosts of eta, x = B)
-    ohm_status setup(const double *dt, bool multigrid = true)
+    // A step starts with setup_host (tables staged in pinned memory, host
+    // state), copy_in (x = B) and start_device (everything on the device up to
+    // the norms of the initial residual; one captured graph when graphs are
+    // on).  multigrid = false: only what the explicit scheme needs (tables,
+    // coefficients, coarse-fine ghosts of eta).
+    ohm_status setup_host(const double *dt, bool multigrid = true)
     {
         const int np = h->nprob, L = nlev();
         VN = P.NBt * NC;
@@ -490,10 +493,10 @@ struct Solver {
                 }
             }
         }
-        if (multigrid) coarse_plan(h, coefs.data(), host(P.jobs), (int *)host(P.force), njobs.data());
-        OHM_HIP(hipMemcpyAsync(at<char>(tab0), stg, tab_bytes, hipMemcpyHostToDevice, st));
-        OHM_HIP(hipEventRecord(h->stage_ev, st));
-        h->stage_live = true;
+        if (multigrid) {
+            coarse_plan(h, coefs.data(), host(P.jobs), (int *)host(P.force), njobs.data());
+            OHM_TRY(ensure_coarse_storage(h));
+        }
         act_dev = ones;
         mlprob = at<int>(P.mlprob);
         active_mut = at<int>(P.active);
@@ -501,16 +504,39 @@ struct Solver {
         lam_dt = at<double>(P.coefs);
         src_coef = lam_dt + np;
         neg_lam_dt = lam_dt + 2 * np;
-        // coarse-fine ghosts of eta (FP64), FP32 copies
+        return OHM_OK;
+    }
+
+    // x = B (user fields), outside any captured graph (B may change per call)
+    ohm_status copy_in()
+    {
+        for (int l = 0; l < nlev(); ++l)
+            OHM_TRY(vcopy_level<double, double>((const double *)Buser[l], (long long)h->nb_host[l] * NC, vec(P.x, l),
+                                                VN, (long long)h->nb_host[l] * NC, 3, st));
+        return OHM_OK;
+    }
+
+    // the staged upload becomes safe to overwrite once the stream passes here
+    ohm_status staged_done()
+    {
+        OHM_HIP(hipEventRecord(h->stage_ev, st));
+        h->stage_live = true;
+        return OHM_OK;
+    }
+
+    // device part of the start of a step: the staged tables, coarse-fine
+    // ghosts of eta (FP64) and FP32 copies, dense-level resistivity, coarsest
+    // inverses, S = b - (1 - lambda) dt div F(b), and (multigrid) the initial
+    // residual with |S|^2 and |r|^2 copied to the pinned buffer
+    ohm_status start_device(bool multigrid)
+    {
+        const int L = nlev();
+        const size_t tab_bytes = P.coefs + 8 * (size_t)h->nprob * 4 - P.jobs;
+        OHM_HIP(hipMemcpyAsync(at<char>(P.jobs), h->h_stage, tab_bytes, hipMemcpyHostToDevice, st));
         for (int l = 1; l < L; ++l)
             OHM_TRY(launch_fill_ghosts<double>(h, l, eta64(l - 1), (long long)h->nb_host[l - 1] * NC,
                                                at<double>(P.oeg) + P.LG[l] * NC, 0, 1, nullptr, st));
-        if (!multigrid) {
-            for (int l = 0; l < L; ++l)
-                OHM_TRY(vcopy_level<double, double>((const double *)Buser[l], (long long)h->nb_host[l] * NC,
-                                                    vec(P.x, l), VN, (long long)h->nb_host[l] * NC, 3, st));
-            return OHM_OK;
-        }
+        if (!multigrid) return OHM_OK;
         if (P.T32) {
             for (int l = 0; l < L; ++l)
                 OHM_TRY(vconvert<double, T>(eta64(l), at<T>(P.eta_t) + P.LB[l] * NC, (long long)h->nb_host[l] * NC, st));
@@ -534,12 +560,13 @@ struct Solver {
             OHM_TRY(launch_coarse_build(h, ed.data(), at<char>(P.jobs), at<int>(P.force), njobs.data(),
                                         at<double>(P.aug), st));
         }
-        // x = b (user B), S = b - (1 - lambda) dt div F(b) on leaf cells
-        for (int l = 0; l < L; ++l)
-            OHM_TRY(vcopy_level<double, double>((const double *)Buser[l], (long long)h->nb_host[l] * NC, vec(P.x, l),
-                                                VN, (long long)h->nb_host[l] * NC, 3, st));
+        // S = b - (1 - lambda) dt div F(b) on leaf cells (x holds b)
         OHM_TRY(composite(P.x, P.S, MODE_APPLY, src_coef, src_coef, 0));
-        return OHM_OK;
+        // the initial residual and its norms
+        OHM_TRY(composite(P.x, P.r, MODE_RESID, lam_dt, neg_lam_dt, P.S));
+        const double *xs[2] = {at<double>(P.S), at<double>(P.r)};
+        OHM_TRY(dots(xs, xs, 2));
+        return copy_dots(2);
     }
 
     // |S|^2 per problem
@@ -634,10 +661,11 @@ struct Solver {
         std::vector<const void *> key = {ws};
         for (int l = 0; l < nlev(); ++l) key.push_back(Euser[l]);
         std::vector<char> ob((const char *)o, (const char *)o + sizeof(*o));
-        if (!h->graph_exec || h->graph_kind != kind || h->graph_key != key || h->graph_opts != ob) {
-            if (h->graph_exec) {
-                OHM_HIP(hipGraphExecDestroy(h->graph_exec));
-                h->graph_exec = nullptr;
+        ohm_hier::GraphSlot &G = h->graphs[kind];
+        if (!G.exec || G.key != key || G.opts != ob) {
+            if (G.exec) {
+                OHM_HIP(hipGraphExecDestroy(G.exec));
+                G.exec = nullptr;
             }
             // record on the handle's own stream (the caller's may be the null
             // stream, which cannot be captured); replay on the caller's stream
@@ -655,17 +683,16 @@ struct Solver {
                 return s;
             }
             if (e != hipSuccess) return fail(OHM_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
-            e = hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0);
+            e = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) {
-                h->graph_exec = nullptr;
+                G.exec = nullptr;
                 return fail(OHM_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
             }
-            h->graph_kind = kind;
-            h->graph_key = key;
-            h->graph_opts = ob;
+            G.key = key;
+            G.opts = ob;
         }
-        OHM_HIP(hipGraphLaunch(h->graph_exec, st));
+        OHM_HIP(hipGraphLaunch(G.exec, st));
         return OHM_OK;
     }
 
@@ -688,24 +715,37 @@ struct Solver {
         return OHM_OK;
     }
 
+    // one CN step: the start (captured once per workspace, resistivity and
+    // options when graphs are on), then the outer iteration
+    ohm_status step(const double *dt, ohm_cn_stats *stats)
+    {
+        OHM_TRY(setup_host(dt));
+        OHM_TRY(copy_in());
+        OHM_TRY(replay(2, [&]() { return start_device(true); }));
+        OHM_TRY(staged_done());
+        return run(stats);
+    }
+
+    ohm_status explicit_steps(const double *dt, int nsteps)
+    {
+        OHM_TRY(setup_host(dt, false));
+        OHM_TRY(copy_in());
+        OHM_TRY(start_device(false));
+        OHM_TRY(staged_done());
+        return run_explicit(nsteps);
+    }
+
     ohm_status run(ohm_cn_stats *stats)
     {
         const int np = h->nprob;
         std::vector<int> iters(np, 0), mgapps(np, 0), act(np, 1);
-        // |S|^2 and the residual of the initial guess, read back together
+        // |S|^2 and the residual of the initial guess (start_device copied them)
         std::vector<double> r2(np);
         Snorm2.assign(np, 0.0);
-        {
-            OHM_TRY(composite(P.x, P.r, MODE_RESID, lam_dt, neg_lam_dt, P.S));
-            const double *xs[2] = {at<double>(P.S), at<double>(P.r)};
-            OHM_TRY(dots(xs, xs, 2));
-            std::vector<double> d((size_t)np * 2);
-            OHM_HIP(hipMemcpyAsync(d.data(), at<double>(P.dots), sizeof(double) * d.size(), hipMemcpyDeviceToHost, st));
-            OHM_HIP(hipStreamSynchronize(st));
-            for (int p = 0; p < np; ++p) {
-                Snorm2[p] = d[2 * p];
-                r2[p] = d[2 * p + 1];
-            }
+        OHM_HIP(hipStreamSynchronize(st));
+        for (int p = 0; p < np; ++p) {
+            Snorm2[p] = h->h_dots[2 * p];
+            r2[p] = h->h_dots[2 * p + 1];
         }
         // |r|^2 of each problem's latest true residual.  A problem stops being
         // updated only right after a true residual that included it, so at the
@@ -863,8 +903,7 @@ ohm_status ohm_cn_step(ohm_hier *h, void *const B[], const void *const eta[], co
         S.st = stream;
         S.Buser = B;
         S.Euser = eta;
-        OHM_TRY(S.setup(dt));
-        return S.run(stats);
+        return S.step(dt, stats);
     }
     Solver<double> S;
     S.h = h;
@@ -874,8 +913,7 @@ ohm_status ohm_cn_step(ohm_hier *h, void *const B[], const void *const eta[], co
     S.st = stream;
     S.Buser = B;
     S.Euser = eta;
-    OHM_TRY(S.setup(dt));
-    return S.run(stats);
+    return S.step(dt, stats);
 }
 
 ohm_status ohm_explicit_workspace_size(const ohm_hier *h, size_t *bytes)
@@ -913,8 +951,7 @@ ohm_status ohm_explicit_step(ohm_hier *h, void *const B[], const void *const eta
     S.st = stream;
     S.Buser = B;
     S.Euser = eta;
-    OHM_TRY(S.setup(dt, false));
-    return S.run_explicit(nsteps);
+    return S.explicit_steps(dt, nsteps);
 }
 
 }  // extern "C"

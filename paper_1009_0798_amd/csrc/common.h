@@ -148,11 +148,15 @@ struct ohm_hier {
     bool ring_live[64] = {};
     int ring_pos = 0;
     // captured outer iteration of ohm_cn_step, reused while its key matches
-    hipGraphExec_t graph_exec = nullptr;
+    // replayed graphs, one per kind (0: iteration of eqs. 16-18, 1: BiCGStab
+    // iteration, 2: start of a step), each valid for its workspace, resistivity
+    // pointers and options
+    struct GraphSlot {
+        hipGraphExec_t exec = nullptr;
+        std::vector<const void *> key;
+        std::vector<char> opts;
+    } graphs[3];
     hipStream_t cap_stream = nullptr;    // capture stream (the null stream cannot be captured)
-    std::vector<const void *> graph_key;
-    std::vector<char> graph_opts;
-    int graph_kind = -1;
     // solver state cache
     double *d_coarse_inv = nullptr;  // per-problem dense inverse of the coarsest grid
     double *d_coarse_eta = nullptr;  // coarsest resistivity each inverse was built from
@@ -277,6 +281,7 @@ size_t coarse_job_bytes();
 // that is forced or whose coarsest resistivity (eta_dense[d], FP64) changed.
 // Scratch `aug` holds sum 2 n3^2 doubles.
 void coarse_plan(ohm_hier *h, const double *lam_dt_host, void *jobs_host, int *force_host, int *njobs);
+ohm_status ensure_coarse_storage(ohm_hier *h);   // the handle's inverse storage (before any capture)
 ohm_status launch_coarse_build(ohm_hier *h, const double *const *eta_dense, const void *jobs_dev,
                                const int *force_dev, const int *njobs, double *aug, hipStream_t s);
 template <typename T>

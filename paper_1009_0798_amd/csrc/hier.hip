@@ -517,7 +517,8 @@ static void free_all(ohm_hier *H)
     if (H->stage_ev) (void)hipEventDestroy(H->stage_ev);
     for (int i = 0; i < 64; ++i)
         if (H->ring_ev[i]) (void)hipEventDestroy(H->ring_ev[i]);
-    if (H->graph_exec) (void)hipGraphExecDestroy(H->graph_exec);
+    for (auto &g : H->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (H->cap_stream) (void)hipStreamDestroy(H->cap_stream);
 }
 

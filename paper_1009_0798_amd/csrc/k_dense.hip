@@ -644,6 +644,18 @@ void coarse_plan(ohm_hier *h, const double *lam_dt_host, void *jobs_host, int *f
     }
 }
 
+ohm_status ensure_coarse_storage(ohm_hier *h)
+{
+    size_t inv_elems = 0, aug_elems = 0;
+    coarse_sizes(h, &inv_elems, &aug_elems);
+    if (inv_elems == 0 || h->d_coarse_inv) return OHM_OK;
+    OHM_HIP(hipMalloc((void **)&h->d_coarse_inv, sizeof(double) * inv_elems));
+    // saved resistivity: one cells-sized slot at inv_off / n3 per job
+    OHM_HIP(hipMalloc((void **)&h->d_coarse_eta, sizeof(double) * inv_elems));
+    OHM_HIP(hipMalloc((void **)&h->d_coarse_flags, sizeof(int) * (size_t)h->nprob));
+    return OHM_OK;
+}
+
 ohm_status launch_coarse_build(ohm_hier *h, const double *const *eta_dense, const void *jobs_dev,
                                const int *force_dev, const int *njobs, double *aug, hipStream_t s)
 {
@@ -652,12 +664,7 @@ ohm_status launch_coarse_build(ohm_hier *h, const double *const *eta_dense, cons
     size_t inv_elems = 0, aug_elems = 0;
     coarse_sizes(h, &inv_elems, &aug_elems);
     if (inv_elems == 0) return OHM_OK;
-    if (!h->d_coarse_inv) {
-        OHM_HIP(hipMalloc((void **)&h->d_coarse_inv, sizeof(double) * inv_elems));
-        // saved resistivity: one cells-sized slot at inv_off / n3 per job
-        OHM_HIP(hipMalloc((void **)&h->d_coarse_eta, sizeof(double) * inv_elems));
-        OHM_HIP(hipMalloc((void **)&h->d_coarse_flags, sizeof(int) * (size_t)h->nprob));
-    }
+    if (!h->d_coarse_inv) return fail(OHM_ERR_ARG, "internal: coarse inverse storage not allocated");
     for (int d = 1; d <= -h->min_level; ++d) {
         if (njobs[d] == 0) continue;
         const CoarseJob *jd = (const CoarseJob *)jobs_dev + (size_t)d * h->nprob;
