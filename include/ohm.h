@@ -209,9 +209,10 @@ typedef struct {
     int32_t coarse_sweeps;/* sweeps on a coarsest grid too large for a dense solve  */
     int32_t nu_coarse;    /* sweeps before and after on the levels below the base grid
                              (0 = nu_pre / nu_post)                                  */
-    int32_t graph;        /* 1 = replay each outer iteration as a captured HIP graph
-                             (kept in the handle while workspace, eta pointers and
-                             options stay the same)                                 */
+    int32_t graph;        /* 1 = replay the device work of a step's start and of
+                             each outer iteration as captured HIP graphs (kept in
+                             the handle while workspace, eta pointers and options
+                             stay the same)                                         */
 } ohm_cn_opts;
 
 typedef struct {
@@ -233,7 +234,9 @@ ohm_status ohm_cn_workspace_size(const ohm_hier *h, const ohm_cn_opts *opts, siz
  *   dt     : host double[nprob]
  *   workspace : device memory of at least ohm_cn_workspace_size bytes, 256-byte aligned
  *   stats  : host ohm_cn_stats[nprob] (may be NULL)
- * Synchronises `stream` once per outer iteration to test convergence.
+ * Synchronises `stream` once after the initial residual and once per outer
+ * iteration to test convergence (the norms reach the host through a pinned
+ * buffer of the handle), and once at the end.
  * Returns OHM_ERR_NOCONV if a problem reached max_iters (B then holds the last
  * iterate and stats are filled) and OHM_ERR_NONFINITE on a non-finite norm.
  */
