@@ -182,6 +182,54 @@ def test_amr_three_levels_corner_gap_against_oracle(precision):
     assert np.linalg.norm(diff) <= 1.5 * RTOL * nS + 1e-12 * np.linalg.norm(exv)
 
 
+def test_nonfinite_input_is_reported():
+    """A NaN in B reaches the initial residual: the step stops with
+    OHM_ERR_NONFINITE before any iteration."""
+    import paper_1009_0798_amd as ohm
+    from paper_1009_0798_amd import _lib
+    announce("cn non-finite input")
+    n = 16
+    spec = gen.uniform_spec(n)
+    B = gen.divfree(n, 2.0, seed=3)
+    eta = gen.lognormal_eta(n, 1.0, seed=4)
+    B[1, 3, 4, 5] = np.nan
+    H = hier(spec)
+    Bt = [cuda(dense_to_blocks(B, spec.levels[0]))]
+    Et = [cuda(dense_to_blocks(eta, spec.levels[0])[None])]
+    with pytest.raises(_lib.OhmError) as err:
+        ohm.ohm_cn_step(H, Bt, Et, gen.explicit_dt(spec.dx0, 1.0, 50.0), ohm.default_opts())
+    assert err.value.status == _lib.OHM_ERR_NONFINITE
+
+
+@pytest.mark.parametrize("lam", [0.5, 1.0])
+def test_large_step_undulation_and_monotone_decay(lam):
+    """Section 3.2's remark on large steps: for a high-frequency B_z(x, y)
+    mode with eta dt mu = 20 one CN step multiplies it by (1 - 10)/(1 + 10) < 0
+    (the mode flips sign), one backward-Euler step by 1/21 > 0 (monotone
+    decay); both as the closed-form factor, to the solve tolerance."""
+    import paper_1009_0798_amd as ohm
+    announce(f"cn large-step mode factor lambda={lam}")
+    n, h = 32, 1.0 / 32
+    spec = gen.uniform_spec(n)
+    z, y, x = np.meshgrid((np.arange(n) + 0.5) * h, (np.arange(n) + 0.5) * h, (np.arange(n) + 0.5) * h,
+                          indexing="ij")
+    kx, ky = 2 * np.pi * 12, 2 * np.pi * 10
+    B = np.zeros((3, n, n, n))
+    B[2] = np.sin(kx * x + ky * y)
+    mu = (2 / h * np.sin(kx * h / 2)) ** 2 + (2 / h * np.sin(ky * h / 2)) ** 2
+    dt = 20.0 / mu
+    g = closed.heat_factor(kx, ky, h, 1.0, dt, lam)
+    assert (g < -0.8) if lam == 0.5 else (0 < g < 0.05)
+    H = hier(spec)
+    Bt = [cuda(dense_to_blocks(B, spec.levels[0]))]
+    Et = [cuda(dense_to_blocks(np.ones((n, n, n)), spec.levels[0])[None])]
+    st, stats = ohm.ohm_cn_step(H, Bt, Et, dt, ohm.default_opts(lam=lam, rtol=1e-12, max_iters=300))
+    assert st == 0
+    got = blocks_to_dense(host(Bt[0]), spec.levels[0], spec.cells(0))
+    assert np.abs(got[:2]).max() <= 1e-12
+    assert np.abs(got[2] - g * B[2]).max() <= 1e-9
+
+
 def test_batched_equals_alone():
     """Three problems of different sizes in one handle give the same answer as
     each solved alone (per-problem reductions in a fixed order)."""

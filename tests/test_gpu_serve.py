@@ -78,3 +78,24 @@ def test_admission_by_footprint():
     tiny = Server(hbm_budget=min(fps) - 1, n_streams=1)
     done = tiny.serve(reqs[:1], [0.0])
     assert done[0].status != 0
+
+
+def test_cancel_releases_budget():
+    """Cancelling an admitted request frees its footprint and admits the next
+    waiting one; cancelling a waiting request removes it; both are reported
+    with a non-zero status and nothing is solved for them."""
+    from paper_1009_0798_amd.serve import Server, footprint
+    announce("serve: cancel")
+    reqs = _requests(3, seed=73)
+    probe = Server(hbm_budget=1, n_streams=1)
+    fps = [footprint(r, probe.opts) for r in reqs]
+    srv = Server(hbm_budget=max(fps), n_streams=1)
+    for r in reqs:
+        srv.submit(r)
+    assert [r.rid for r in srv.admitted] == [0] and [r.rid for r in srv.waiting] == [1, 2]
+    assert srv.free == max(fps) - fps[0]
+    assert srv.cancel(0)
+    assert [r.rid for r in srv.admitted] == [1] and srv.free == max(fps) - fps[1]
+    assert srv.cancel(2) and not srv.waiting
+    assert not srv.cancel(2)
+    assert sorted(r.rid for r in srv.finished) == [0, 2] and all(r.status != 0 for r in srv.finished)
