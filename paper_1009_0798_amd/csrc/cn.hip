@@ -213,7 +213,12 @@ struct Solver {
     // SMOOTH_ZERO (zero input, not read) or SMOOTH_FROM_TMP (input in tmp)
     // coarse (level 0 only): the first sweep reads e + P(coarse), the
     // prolonged correction from the first dense level, without storing it
-    ohm_status smooth_blk(int l, int n, int flags = 0, const T *coarse = nullptr)
+    // out64_: when set, the level-0 post-smoothing of the coming V-cycle writes
+    // its last sweep as FP64 there (the preconditioned vector) and sets wrote64_
+    double *out64_ = nullptr;
+    bool wrote64_ = false;
+
+    ohm_status smooth_blk(int l, int n, int flags = 0, const T *coarse = nullptr, double *out64 = nullptr)
     {
         const bool zero = flags & SMOOTH_ZERO, from_tmp = (flags & SMOOTH_FROM_TMP) && !zero;
         T *e = mg(P.e, l), *tmp = mg(P.tmp, l);
@@ -222,6 +227,7 @@ struct Solver {
         if (h->amr[l].fused && n > 0) {
             // fused sweeps ping-pong e <-> tmp; a zero input is not read, so
             // the first sweep writes whichever buffer makes the last land in e
+            bool used64 = false;
             for (int k = 0; k < n; ++k) {
                 T *dst;
                 if (k == 0 && zero) {
@@ -230,14 +236,20 @@ struct Solver {
                                                 nullptr, 0, nullptr, GN, gE));
                 } else if (k == 0 && coarse) {
                     dst = cur == e ? tmp : e;
+                    used64 = k == n - 1 && out64;
                     OHM_TRY(launch_blk_sweep<T>(h, l, cur, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st, coarse,
-                                                h->dense_cells[1]));
+                                                h->dense_cells[1], nullptr, 0, nullptr, used64 ? out64 : nullptr));
                 } else {
                     dst = cur == e ? tmp : e;
+                    used64 = k == n - 1 && out64;
                     OHM_TRY(launch_blk_sweep<T>(h, l, cur, VN, mg(P.rhs, l), etaT(l), lam_dt, dst, active, st,
-                                                nullptr, 0, gB, GN, gE));
+                                                nullptr, 0, gB, GN, gE, used64 ? out64 : nullptr));
                 }
                 cur = dst;
+            }
+            if (used64) {
+                wrote64_ = true;   // the result is in out64; e is not needed any more
+                return OHM_OK;
             }
         } else {
             // two half-sweeps per sweep, each a full out-of-place pass
@@ -312,11 +324,11 @@ struct Solver {
             const T *e1 = ecur_of(1);
             if (h->amr[0].complete27 && nu2 > 0 && !(nu2 & 1)) {
                 // even count: the first sweep adds the correction as it loads
-                OHM_TRY(smooth_blk(0, nu2, 0, e1));
+                OHM_TRY(smooth_blk(0, nu2, 0, e1, out64_));
             } else if ((nu2 & 1) && h->amr[0].complete27) {
                 OHM_TRY(launch_prolong_blk<T>(h, -1, e1, h->dense_cells[1], mg(P.tmp, 0), VN, 3, 1, active, st,
                                               mg(P.e, 0)));
-                OHM_TRY(smooth_blk(0, nu2, SMOOTH_FROM_TMP));
+                OHM_TRY(smooth_blk(0, nu2, SMOOTH_FROM_TMP, nullptr, out64_));
             } else {
                 OHM_TRY(launch_prolong_blk<T>(h, -1, e1, h->dense_cells[1], mg(P.e, 0), VN, 3, 1, active, st));
                 OHM_TRY(smooth_blk(0, nu2));
@@ -375,7 +387,12 @@ struct Solver {
             for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(-d, false));
         }
         OHM_TRY(launch_prolong_blk<T>(h, -1, ecur_of(1), h->dense_cells[1], mg(P.e, 0), VN, 3, 0, active, st));
-        for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(0, false));
+        double *const o64 = out64_;
+        for (int v = 0; v < o->n_vcycles; ++v) {
+            out64_ = v == o->n_vcycles - 1 ? o64 : nullptr;
+            OHM_TRY(vcycle_base(0, false));
+        }
+        out64_ = nullptr;
         return OHM_OK;
     }
 
@@ -407,17 +424,25 @@ struct Solver {
             OHM_TRY(launch_reflux<T>(h, l - 1, nullptr, VN, etaT(l - 1), mg(P.e, l), VN, at<T>(P.mg_g) + P.LG[l] * NC,
                                      GN, etaT(l), etagT(l), neg_lam_dt, mg(P.rhs, l - 1), active, st));
         }
+        // one FP32 level: the last post-sweep writes the FP64 result directly
+        double *const o64 = (P.T32 && L == 1 && h->amr[0].complete27) ? at<double>(zo) : nullptr;
+        wrote64_ = false;
         if (o->cycle == 1) {
+            out64_ = o64;
             OHM_TRY(fmg_base());
         } else {
-            for (int v = 0; v < o->n_vcycles; ++v) OHM_TRY(vcycle_base(0, v == 0));
+            for (int v = 0; v < o->n_vcycles; ++v) {
+                out64_ = v == o->n_vcycles - 1 ? o64 : nullptr;
+                OHM_TRY(vcycle_base(0, v == 0));
+            }
         }
+        out64_ = nullptr;
         for (int l = 1; l < L; ++l) {
             OHM_TRY(launch_prolong_blk<T>(h, l - 1, mg(P.e, l - 1), VN, mg(P.e, l), VN, 3, 1, active, st));
             OHM_TRY(launch_fill_ghosts<T>(h, l, mg(P.e, l - 1), VN, at<T>(P.mg_g) + P.LG[l] * NC, GN, 3, active, st));
             OHM_TRY(smooth_blk(l, o->nu_post));
         }
-        if (!alias) OHM_TRY(vconvert<T, double>(at<T>(P.e), at<double>(zo), n, st));
+        if (!alias && !wrote64_) OHM_TRY(vconvert<T, double>(at<T>(P.e), at<double>(zo), n, st));
         rhs_b = e_b = nullptr;
         return OHM_OK;
     }

@@ -199,12 +199,13 @@ ohm_status launch_resid_restrict_blk0(const ohm_hier *h, const T *B, const T *Bg
 // have ghosts); B == nullptr sweeps a zero input, with zero ghost values,
 // without reading either; coarse != nullptr (level 0 only) sweeps
 // B + P(coarse), the trilinear prolongation of the first dense level's field,
-// without storing the corrected input
+// without storing the corrected input; out64 (FP32 sweeps of a complete level
+// with an input): the result is written as FP64 to out64 instead of out
 template <typename T>
 ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long cs, const T *S, const T *eta,
                             const double *coef_dev, T *out, const int *active, hipStream_t s,
                             const T *coarse = nullptr, long long ccs = 0, const T *Bg = nullptr, long long gcs = 0,
-                            const T *etag = nullptr);
+                            const T *etag = nullptr, double *out64 = nullptr);
 
 template <typename T>
 ohm_status launch_dense_stencil(const ohm_hier *h, int level, int mode, const T *B, const T *S,

@@ -3,6 +3,7 @@
 // edge halo staged in LDS), restriction, prolongation, coarse-fine ghost fill,
 // refluxing and per-problem norm reductions.
 #include "common.h"
+#include <type_traits>
 #include "stencil.h"
 #include "sweep.h"
 
@@ -248,15 +249,16 @@ struct GhostBlockAddr {
 
 // MODE 0: sweep B -> out; 1: zero input (B not read); 2: sweep of B plus the
 // prolonged correction from the first dense level (coarse), B -> out; MODE 3
-// and 4 as 0 and 1 on a level with coarse-fine ghost blocks (Bg, etag)
-template <typename T, int MODE>
+// and 4 as 0 and 1 on a level with coarse-fine ghost blocks (Bg, etag).  With
+// O64 (MODE 0 or 2 of an FP32 sweep) the result is written as FP64 to out64.
+template <typename T, int MODE, bool O64 = false>
 __global__ void __launch_bounds__(SWEEP_THREADS)
 k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ prob_of,
             const int *__restrict__ active, const double *__restrict__ inv_h2_p, const double *__restrict__ coef_p,
             const T *__restrict__ B, long long cs, const T *__restrict__ S, const T *__restrict__ eta,
             T *__restrict__ out, const int *__restrict__ ijk, const DenseProbDev *__restrict__ dp,
             const T *__restrict__ coarse, long long ccs, const T *__restrict__ Bg, long long gcs,
-            const T *__restrict__ etag)
+            const T *__restrict__ etag, double *__restrict__ out64 = nullptr)
 {
     __shared__ T sB[3][TC2];
     __shared__ T sE[TC2];
@@ -275,10 +277,16 @@ k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ p
         const BlockAddr A{snbr, b};
         TileCoarse<T> cor{coarse, ccs, dp[pr], 4 * ijk[3 * b] - 2, 4 * ijk[3 * b + 1] - 2, 4 * ijk[3 * b + 2] - 2,
                           sC, {}};
-        fused_sweep_tile<T, false>(A, B, cs, S, eta, out, cih2, sB, sE, cor);
+        if constexpr (O64)
+            fused_sweep_tile<T, false, BlockAddr, TileCoarse<T>, double>(A, B, cs, S, eta, out64, cih2, sB, sE, cor);
+        else
+            fused_sweep_tile<T, false>(A, B, cs, S, eta, out, cih2, sB, sE, cor);
     } else {
         const BlockAddr A{snbr, b};
-        fused_sweep_tile<T, MODE == 1>(A, B, cs, S, eta, out, cih2, sB, sE);
+        if constexpr (O64)
+            fused_sweep_tile<T, MODE == 1, BlockAddr, NoCoarse<T>, double>(A, B, cs, S, eta, out64, cih2, sB, sE);
+        else
+            fused_sweep_tile<T, MODE == 1>(A, B, cs, S, eta, out, cih2, sB, sE);
     }
 }
 
@@ -656,10 +664,35 @@ ohm_status launch_resid_restrict_blk0(const ohm_hier *h, const T *B, const T *Bg
 template <typename T>
 ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long cs, const T *S, const T *eta,
                             const double *coef_dev, T *out, const int *active, hipStream_t s, const T *coarse,
-                            long long ccs, const T *Bg, long long gcs, const T *etag)
+                            long long ccs, const T *Bg, long long gcs, const T *etag, double *out64)
 {
     const AmrLevelDev &L = h->amr[level];
     if (L.nb == 0) return OHM_OK;
+    if (out64) {
+        if constexpr (std::is_same<T, float>::value) {
+            if (!L.complete27 || !B)
+                return fail(OHM_ERR_ARG, "an FP64 result needs a complete level and an input");
+            if ((unsigned long long)L.nb * NC * sizeof(double) > 0xFFFFFFFFull)
+                return fail(OHM_ERR_ARG, "level %d: FP64 result array above 4 GiB", level);
+            if (((uintptr_t)B | (uintptr_t)eta | (uintptr_t)(cs * sizeof(T))) % (2 * sizeof(T)) != 0)
+                return fail(OHM_ERR_ARG, "level %d: fused sweep needs B, eta and the component stride %zu-byte "
+                                         "aligned", level, 2 * sizeof(T));
+            if (coarse) {
+                if (level != 0 || h->min_level > -1)
+                    return fail(OHM_ERR_ARG, "a fused coarse correction needs level 0 and a dense level below it");
+                k_blk_sweep<T, 2, true><<<L.nb, SWEEP_THREADS, 0, s>>>(
+                    L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta, out, L.ijk, h->dense[1].probs,
+                    coarse, ccs, nullptr, 0, nullptr, out64);
+            } else {
+                k_blk_sweep<T, 0, true><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev,
+                                                                       B, cs, S, eta, out, nullptr, nullptr, nullptr,
+                                                                       0, nullptr, 0, nullptr, out64);
+            }
+            return check_launch("fused sweep to FP64");
+        } else {
+            return fail(OHM_ERR_ARG, "an FP64 result is for FP32 sweeps");
+        }
+    }
     if (!L.fused)
         return fail(OHM_ERR_ARG, "fused sweep needs every neighbour block of level %d as a level or ghost block", level);
     const bool gh = !L.complete27;
@@ -782,7 +815,7 @@ ohm_status launch_reduce_problem(int nprob, int nrange, const long long *range_d
 #define INST(T)                                                                                                 \
     template ohm_status launch_blk_sweep<T>(const ohm_hier *, int, const T *, long long, const T *, const T *,   \
                                             const double *, T *, const int *, hipStream_t, const T *, long long, \
-                                            const T *, long long, const T *);                                   \
+                                            const T *, long long, const T *, double *);                         \
     template ohm_status launch_blk_stencil<T>(const ohm_hier *, int, int, const T *, const T *, long long,      \
                                               long long, const T *, const T *, const T *, const double *, T *,  \
                                               int, double *, const uint8_t *, const int *, hipStream_t,         \

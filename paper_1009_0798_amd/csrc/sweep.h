@@ -109,10 +109,12 @@ struct TileCoarse {
     }
 };
 
-template <typename T, bool ZERO, typename Addr, typename Coarse = NoCoarse<T>>
+// The result goes to `out` as TO (T, or double from an FP32 sweep), with the
+// same element offsets and component stride as the input.
+template <typename T, bool ZERO, typename Addr, typename Coarse = NoCoarse<T>, typename TO = T>
 __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restrict__ B, long long cs,
                                                  const T *__restrict__ S, const T *__restrict__ eta,
-                                                 T *__restrict__ out, const T cih2, T (*sB)[TC2], T *sE,
+                                                 TO *__restrict__ out, const T cih2, T (*sB)[TC2], T *sE,
                                                  Coarse cor = Coarse())
 {
     const int u = threadIdx.x;
@@ -240,10 +242,10 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
     {
         const int x = u & 7, y = (u >> 3) & 7, z = u >> 6;
         const int p = tix2(x, y, z);
-        const unsigned off = (unsigned)A.at(x, y, z) * (unsigned)sizeof(T);
-        store_at(out, off, sB[0][p]);
-        store_at(out + cs, off, sB[1][p]);
-        store_at(out + 2 * cs, off, sB[2][p]);
+        const unsigned off = (unsigned)A.at(x, y, z) * (unsigned)sizeof(TO);
+        store_at(out, off, TO(sB[0][p]));
+        store_at(out + cs, off, TO(sB[1][p]));
+        store_at(out + 2 * cs, off, TO(sB[2][p]));
     }
 }
 
