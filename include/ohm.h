@@ -159,10 +159,16 @@ ohm_status ohm_residual(ohm_hier *h, int32_t level, const void *B, const void *B
  * coarse cells that do not exist) one launch performs a whole sweep; it needs
  * B, eta and the ghost arrays aligned to 2 elements (OHM_ERR_ARG otherwise)
  * and each field or ghost array of the level below 4 GiB.
+ * ordering: 0 = the paper's red-black; 1 = four colour classes
+ * ((i+j) mod 2) + 2 ((j+k) mod 2), updated in that order with the same
+ * update.  No two cells of a class share a stencil term, so on grids of even
+ * extent a four-class sweep is an exact Gauss-Seidel sweep (red-black is a
+ * Jacobi step inside each colour: the in-plane edge terms join same-colour
+ * cells).  It takes four launches per sweep.  Other values: OHM_ERR_ARG.
  */
 ohm_status ohm_smooth(ohm_hier *h, int32_t level, void *B, const void *B_ghost, const void *S,
                       const void *eta, const void *eta_ghost, const double *lam_dt,
-                      int32_t nsweeps, void *tmp, ohm_dtype dtype, hipStream_t stream);
+                      int32_t nsweeps, int32_t ordering, void *tmp, ohm_dtype dtype, hipStream_t stream);
 
 /*
  * Averaging restriction (section 2.2): each cell of level fine_level-1 that
@@ -213,6 +219,9 @@ typedef struct {
                              each outer iteration as captured HIP graphs (kept in
                              the handle while workspace, eta pointers and options
                              stay the same)                                         */
+    int32_t ordering;     /* smoother ordering, as for ohm_smooth: 0 = red-black
+                             (fused sweeps), 1 = four colour classes (one launch per
+                             class on every level)                                  */
 } ohm_cn_opts;
 
 typedef struct {

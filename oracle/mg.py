@@ -113,22 +113,23 @@ def hierarchy(eta, h, lam_dt):
     return levels
 
 
-def vcycle(levels, r, nu1=2, nu2=2, l=0):
+def vcycle(levels, r, nu1=2, nu2=2, l=0, ordering=0):
     """Correction-scheme V(nu1, nu2) cycle for L e = r starting from e = 0.
-    The coarsest level is solved exactly (dense inverse)."""
+    The coarsest level is solved exactly (dense inverse).  ordering selects
+    the smoother's colour classes (``ref.smooth``)."""
     lv = levels[l]
     if l == len(levels) - 1:
         return lv.solve_exact(r)
     e = np.zeros_like(r)
-    e = ref.smooth(e, r, lv.eta, lv.h, lv.lam_dt, nu1)
+    e = ref.smooth(e, r, lv.eta, lv.h, lv.lam_dt, nu1, ordering)
     res = ref.residual(e, r, lv.eta, lv.h, lv.lam_dt)
-    ec = vcycle(levels, ref.restrict(res), nu1, nu2, l + 1)
+    ec = vcycle(levels, ref.restrict(res), nu1, nu2, l + 1, ordering)
     e = ref.prolong(ec, e)
-    e = ref.smooth(e, r, lv.eta, lv.h, lv.lam_dt, nu2)
+    e = ref.smooth(e, r, lv.eta, lv.h, lv.lam_dt, nu2, ordering)
     return e
 
 
-def fmg(levels, r, n_v=1, nu1=2, nu2=2):
+def fmg(levels, r, n_v=1, nu1=2, nu2=2, ordering=0):
     """Full multigrid for L e = r: restrict r to every level, solve the
     coarsest, then on each finer level start from the prolonged coarse
     solution and run n_v V-cycles on the residual equation."""
@@ -141,7 +142,7 @@ def fmg(levels, r, n_v=1, nu1=2, nu2=2):
         e = ref.prolong(e)
         for _ in range(n_v):
             res = ref.residual(e, rs[l], lv.eta, lv.h, lv.lam_dt)
-            e = e + vcycle(levels, res, nu1, nu2, l)
+            e = e + vcycle(levels, res, nu1, nu2, l, ordering)
     return e
 
 

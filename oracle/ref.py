@@ -116,11 +116,39 @@ def rb_halfsweep(B, S, eta, h, lam_dt, colour):
     return B
 
 
-def smooth(B, S, eta, h, lam_dt, nsweeps):
-    """``nsweeps`` red-black sweeps (red half first)."""
+def colour_classes(shape, ordering=0):
+    """Colour class of every cell (i, j, k) of a (nz, ny, nx) level, in level
+    indices.  ordering 0: the paper's red (0) and black (1), (i + j + k) mod 2.
+    ordering 1: four classes ((i + j) mod 2) + 2 ((j + k) mod 2), an ordering
+    the paper does not use, under which no two cells of a class share a
+    stencil term."""
+    k, j, i = np.indices(shape)
+    if ordering == 0:
+        return (i + j + k) % 2
+    return (i + j) % 2 + 2 * ((j + k) % 2)
+
+
+def class_update(B, S, eta, h, lam_dt, classes, m):
+    """The update of eq. (19), B_c += R_c / (1 + alpha_c) with R = S - L B of
+    the incoming field, on the cells of class m only; returns a new array."""
+    B = _c(B)
+    R = residual(B, S, eta, h, lam_dt)
+    al = alpha(eta, h, lam_dt)
+    return np.where((classes == m)[None], B + R / (1.0 + al), B)
+
+
+def smooth(B, S, eta, h, lam_dt, nsweeps, ordering=0):
+    """``nsweeps`` sweeps: red-black (red half first), or with ordering 1 the
+    four classes of ``colour_classes`` in the order 0, 1, 2, 3."""
+    if ordering == 0:
+        for _ in range(nsweeps):
+            B = rb_halfsweep(B, S, eta, h, lam_dt, 0)
+            B = rb_halfsweep(B, S, eta, h, lam_dt, 1)
+        return B
+    classes = colour_classes(np.shape(eta), ordering)
     for _ in range(nsweeps):
-        B = rb_halfsweep(B, S, eta, h, lam_dt, 0)
-        B = rb_halfsweep(B, S, eta, h, lam_dt, 1)
+        for m in range(4):
+            B = class_update(B, S, eta, h, lam_dt, classes, m)
     return B
 
 

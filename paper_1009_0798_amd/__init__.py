@@ -124,9 +124,10 @@ def ohm_residual(h: Hierarchy, level, B, S, eta, lam_dt, R=None, B_ghost=None, e
     return None
 
 
-def ohm_smooth(h: Hierarchy, level, B, S, eta, lam_dt, nsweeps, tmp, B_ghost=None, eta_ghost=None, stream=None):
+def ohm_smooth(h: Hierarchy, level, B, S, eta, lam_dt, nsweeps, tmp, B_ghost=None, eta_ghost=None, stream=None,
+               ordering=0):
     check(lib().ohm_smooth(h.h, level, dptr(B), dptr(B_ghost), dptr(S), dptr(eta), dptr(eta_ghost), _coef(h, lam_dt),
-                           int(nsweeps), dptr(tmp), _dtype_code(B), stream_ptr(stream)))
+                           int(nsweeps), int(ordering), dptr(tmp), _dtype_code(B), stream_ptr(stream)))
 
 
 def ohm_restrict(h: Hierarchy, fine_level, fine, coarse, stream=None):

@@ -37,7 +37,7 @@ class CnOpts(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("n_vcycles", ctypes.c_int32),
                 ("cycle", ctypes.c_int32), ("outer", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("coarse_sweeps", ctypes.c_int32), ("nu_coarse", ctypes.c_int32),
-                ("graph", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("ordering", ctypes.c_int32)]
 
 
 class CnStats(ctypes.Structure):
@@ -75,7 +75,7 @@ def lib() -> ctypes.CDLL:
             "ohm_fill_ghosts": [P, I32, P, P, I32, I32, P],
             "ohm_apply": [P, I32, P, P, P, P, DP, P, I32, P],
             "ohm_residual": [P, I32, P, P, P, P, P, DP, P, DP, I32, P],
-            "ohm_smooth": [P, I32, P, P, P, P, P, DP, I32, P, I32, P],
+            "ohm_smooth": [P, I32, P, P, P, P, P, DP, I32, I32, P, I32, P],
             "ohm_restrict": [P, I32, P, P, I32, I32, P],
             "ohm_prolong": [P, I32, P, P, I32, I32, I32, P],
             "ohm_reflux": [P, I32, P, P, P, P, P, P, DP, P, I32, I32, P],

@@ -169,13 +169,14 @@ ohm_status ohm_residual(ohm_hier *h, int32_t level, const void *B, const void *B
 }
 
 ohm_status ohm_smooth(ohm_hier *h, int32_t level, void *B, const void *B_ghost, const void *S, const void *eta,
-                      const void *eta_ghost, const double *lam_dt, int32_t nsweeps, void *tmp, ohm_dtype dtype,
-                      hipStream_t stream)
+                      const void *eta_ghost, const double *lam_dt, int32_t nsweeps, int32_t ordering, void *tmp,
+                      ohm_dtype dtype, hipStream_t stream)
 {
     OHM_TRY(check_level(h, level));
     OHM_TRY(check_dtype(dtype));
     if (!B || !S || !eta || !tmp) return fail(OHM_ERR_ARG, "NULL field");
     if (nsweeps < 0) return fail(OHM_ERR_ARG, "nsweeps must be >= 0");
+    if (ordering != 0 && ordering != 1) return fail(OHM_ERR_ARG, "ordering must be 0 (red-black) or 1 (four colours)");
     if (tmp == B) return fail(OHM_ERR_ARG, "tmp must not alias B");
     OHM_TRY(check_coef(h, lam_dt, "lam_dt"));
     OHM_TRY(need_ghosts(h, level, B_ghost, eta_ghost));
@@ -183,7 +184,7 @@ ohm_status ohm_smooth(ohm_hier *h, int32_t level, void *B, const void *B_ghost, 
     double *cd;
     int slot;
     OHM_TRY(coef_slot(h, lam_dt, stream, &cd, &slot));
-    if (level >= 0 && h->amr[level].fused) {
+    if (level >= 0 && h->amr[level].fused && ordering == 0) {
         const long long cs = level_cs(h, level), gcs = (long long)h->ng_host[level] * NC;
         for (int k = 0; k < nsweeps; ++k) {
             const void *src = (k & 1) ? tmp : B;
@@ -205,20 +206,25 @@ ohm_status ohm_smooth(ohm_hier *h, int32_t level, void *B, const void *B_ghost, 
     if (level < 0) {
         ohm_status st = dtype == OHM_F64
                             ? launch_dense_smooth<double>(h, level, (double *)B, (double *)tmp, (const double *)S,
-                                                          (const double *)eta, cd, nsweeps, true, nullptr, stream)
+                                                          (const double *)eta, cd, nsweeps, true, nullptr, stream, 0,
+                                                          nullptr, nullptr, ordering)
                             : launch_dense_smooth<float>(h, level, (float *)B, (float *)tmp, (const float *)S,
-                                                         (const float *)eta, cd, nsweeps, true, nullptr, stream);
+                                                         (const float *)eta, cd, nsweeps, true, nullptr, stream, 0,
+                                                         nullptr, nullptr, ordering);
         OHM_TRY(st);
         return coef_done(h, slot, stream);
     }
+    // one out-of-place launch per colour class, B -> tmp -> B ...: an even
+    // number per sweep, so each sweep ends in B
+    const int ncol = ordering ? 4 : 2, c0 = ordering ? 2 : 0;
     for (int k = 0; k < nsweeps; ++k) {
-        for (int colour = 0; colour < 2; ++colour) {
-            const void *src = colour == 0 ? B : tmp;
-            void *dst = colour == 0 ? tmp : B;
+        for (int c = 0; c < ncol; ++c) {
+            const void *src = (c & 1) ? tmp : B;
+            void *dst = (c & 1) ? B : tmp;
             ohm_status st =
                 dtype == OHM_F64
-                    ? stencil<double>(h, level, MODE_SMOOTH, src, B_ghost, S, eta, eta_ghost, cd, dst, colour, nullptr, stream)
-                    : stencil<float>(h, level, MODE_SMOOTH, src, B_ghost, S, eta, eta_ghost, cd, dst, colour, nullptr, stream);
+                    ? stencil<double>(h, level, MODE_SMOOTH, src, B_ghost, S, eta, eta_ghost, cd, dst, c0 + c, nullptr, stream)
+                    : stencil<float>(h, level, MODE_SMOOTH, src, B_ghost, S, eta, eta_ghost, cd, dst, c0 + c, nullptr, stream);
             OHM_TRY(st);
         }
     }

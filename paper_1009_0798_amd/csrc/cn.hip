@@ -105,7 +105,7 @@ bool valid_opts(const ohm_cn_opts *o)
     return o && o->lambda > 0.0 && o->lambda <= 1.0 && o->rtol > 0.0 && o->max_iters >= 1 && o->nu_pre >= 0 &&
            o->nu_post >= 0 && o->nu_pre + o->nu_post >= 1 && o->n_vcycles >= 1 && (o->cycle == 0 || o->cycle == 1) &&
            (o->outer == 0 || o->outer == 1) && (o->precision == 0 || o->precision == 1) && o->coarse_sweeps >= 0 &&
-           o->nu_coarse >= 0 && (o->graph == 0 || o->graph == 1);
+           o->nu_coarse >= 0 && (o->graph == 0 || o->graph == 1) && (o->ordering == 0 || o->ordering == 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -218,13 +218,17 @@ struct Solver {
     double *out64_ = nullptr;
     bool wrote64_ = false;
 
+    // fused sweeps are red-black; the four-colour ordering takes one class
+    // launch per colour (coarse and out64 are for fused sweeps only)
+    bool fused_blk(int l) const { return h->amr[l].fused && o->ordering == 0; }
     ohm_status smooth_blk(int l, int n, int flags = 0, const T *coarse = nullptr, double *out64 = nullptr)
     {
         const bool zero = flags & SMOOTH_ZERO, from_tmp = (flags & SMOOTH_FROM_TMP) && !zero;
         T *e = mg(P.e, l), *tmp = mg(P.tmp, l);
         T *cur = from_tmp ? tmp : e;
         const T *gB = at<T>(P.mg_g) + P.LG[l] * NC, *gE = etagT(l);
-        if (h->amr[l].fused && n > 0) {
+        if (coarse && !(fused_blk(l) && n > 0)) return fail(OHM_ERR_ARG, "fused coarse correction without fused sweeps");
+        if (fused_blk(l) && n > 0) {
             // fused sweeps ping-pong e <-> tmp; a zero input is not read, so
             // the first sweep writes whichever buffer makes the last land in e
             bool used64 = false;
@@ -252,14 +256,17 @@ struct Solver {
                 return OHM_OK;
             }
         } else {
-            // two half-sweeps per sweep, each a full out-of-place pass
+            // one launch per colour class (two red-black, four for the
+            // four-colour ordering), each a full out-of-place pass: a sweep
+            // returns to the buffer it started from
             if (zero) OHM_TRY(zero_level(P.e, l));
             T *oth = cur == e ? tmp : e;
+            const int ncol = o->ordering ? 4 : 2, c0 = o->ordering ? 2 : 0;
             for (int k = 0; k < n; ++k)
-                for (int c = 0; c < 2; ++c)
-                    OHM_TRY(launch_blk_stencil<T>(h, l, MODE_SMOOTH, c == 0 ? cur : oth, gB,
-                                                  VN, GN, mg(P.rhs, l), etaT(l), etagT(l), lam_dt, c == 0 ? oth : cur,
-                                                  c, nullptr, nullptr, active, st));
+                for (int c = 0; c < ncol; ++c)
+                    OHM_TRY(launch_blk_stencil<T>(h, l, MODE_SMOOTH, (c & 1) ? oth : cur, gB, VN, GN, mg(P.rhs, l),
+                                                  etaT(l), etagT(l), lam_dt, (c & 1) ? cur : oth, c0 + c, nullptr,
+                                                  nullptr, active, st));
         }
         if (cur != e)
             for (int c = 0; c < 3; ++c)
@@ -277,7 +284,7 @@ struct Solver {
                             T **last = nullptr)
     {
         return launch_dense_smooth<T>(h, -d, dv(P.d_e, d), dv(P.d_tmp, d), dv(P.d_rhs, d), dv(P.d_eta, d), lam_dt, n,
-                                      all, filter, st, flags, coarse, last);
+                                      all, filter, st, flags, coarse, last, o->ordering);
     }
     // where each dense level's current correction is: its e buffer, or its
     // tmp buffer when the post-smoothing sweeps ended there (no copy back)
@@ -322,10 +329,11 @@ struct Solver {
                                                   active, st));
             OHM_TRY(down_dense(1));
             const T *e1 = ecur_of(1);
-            if (h->amr[0].complete27 && nu2 > 0 && !(nu2 & 1)) {
+            const bool fz = h->amr[0].complete27 && o->ordering == 0;
+            if (fz && nu2 > 0 && !(nu2 & 1)) {
                 // even count: the first sweep adds the correction as it loads
                 OHM_TRY(smooth_blk(0, nu2, 0, e1, out64_));
-            } else if ((nu2 & 1) && h->amr[0].complete27) {
+            } else if ((nu2 & 1) && fz) {
                 OHM_TRY(launch_prolong_blk<T>(h, -1, e1, h->dense_cells[1], mg(P.tmp, 0), VN, 3, 1, active, st,
                                               mg(P.e, 0)));
                 OHM_TRY(smooth_blk(0, nu2, SMOOTH_FROM_TMP, nullptr, out64_));
@@ -344,7 +352,7 @@ struct Solver {
                                                dv(P.d_res, d), dv(P.d_rhs, d + 1), active, st));
         OHM_TRY(down_dense(d + 1));
         const T *ec = ecur_of(d + 1);
-        if (nuc2 > 0 && h->dense[d].nptile == 0 && (!(nuc2 & 1) || may_end_in_tmp(d))) {
+        if (nuc2 > 0 && h->dense[d].nptile == 0 && o->ordering == 0 && (!(nuc2 & 1) || may_end_in_tmp(d))) {
             // the first sweep adds the prolonged coarser correction as it
             // loads; the result stays where the last sweep put it
             T *last = nullptr;
@@ -425,7 +433,7 @@ struct Solver {
                                      GN, etaT(l), etagT(l), neg_lam_dt, mg(P.rhs, l - 1), active, st));
         }
         // one FP32 level: the last post-sweep writes the FP64 result directly
-        double *const o64 = (P.T32 && L == 1 && h->amr[0].complete27) ? at<double>(zo) : nullptr;
+        double *const o64 = (P.T32 && L == 1 && h->amr[0].complete27 && fused_blk(0)) ? at<double>(zo) : nullptr;
         wrote64_ = false;
         if (o->cycle == 1) {
             out64_ = o64;
@@ -685,7 +693,9 @@ struct Solver {
         if (!o->graph) return body();
         std::vector<const void *> key = {ws};
         for (int l = 0; l < nlev(); ++l) key.push_back(Euser[l]);
-        std::vector<char> ob((const char *)o, (const char *)o + sizeof(*o));
+        // the options' bytes up to the end of their last field (not the
+        // struct's tail padding, which callers need not initialise)
+        std::vector<char> ob((const char *)o, (const char *)&o->ordering + sizeof(o->ordering));
         ohm_hier::GraphSlot &G = h->graphs[kind];
         if (!G.exec || G.key != key || G.opts != ob) {
             if (G.exec) {
@@ -896,6 +906,7 @@ void ohm_cn_default_opts(ohm_cn_opts *o)
     o->coarse_sweeps = 16;
     o->nu_coarse = 0;
     o->graph = 1;
+    o->ordering = 0;
 }
 
 ohm_status ohm_cn_workspace_size(const ohm_hier *h, const ohm_cn_opts *opts, size_t *bytes)

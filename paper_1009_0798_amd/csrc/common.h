@@ -172,6 +172,20 @@ namespace ohm {
 // launchers implemented in the kernel translation units ----------------------
 enum { MODE_APPLY = 0, MODE_RESID = 1, MODE_SMOOTH = 2, MODE_RESID_RESTRICT = 3 };
 
+// Colour classes of the smoother's orderings, in level-global cell indices
+// (block-local indices have the same parities, block origins being multiples
+// of 8).  colour 0 / 1: red / black of eq. (19), (i + j + k) mod 2; same-colour
+// cells meet in the stencil's in-plane edge terms, so an update of one colour
+// is a Jacobi step inside it.  colour 2 + m, m = 0..3: the four classes
+// ((i + j) mod 2) + 2 ((j + k) mod 2), which give each of the 18 stencil
+// neighbours of a cell (6 faces, 12 in-plane edges) another class than the
+// cell's, so that on grids of even extent four class updates are one exact
+// Gauss-Seidel sweep.
+__device__ __forceinline__ bool in_colour(int i, int j, int k, int colour)
+{
+    return colour < 2 ? ((i + j + k) & 1) == colour : (((i + j) & 1) | (((j + k) & 1) << 1)) == colour - 2;
+}
+
 // Optional work fused into the block stencil kernel.  MODE_APPLY with ndot > 0
 // also writes per-block partial dot products of the output with dot_y[q]
 // (nullptr: with the output itself) to dot_part[block][ndot], summed in the
@@ -256,11 +270,13 @@ ohm_status launch_prolong_blk(const ohm_hier *h, int coarse_level, const T *coar
 // fused tiles need no final copy when the count allows it.  coarse: the first
 // sweep adds the trilinear prolongation of the next coarser level's field as
 // it loads (coarse and last need a level of whole tiles, an input and a sweep).
+// ordering 1: four-colour sweeps (four class launches each, see in_colour)
+// instead of red-black; coarse and last are then not accepted.
 enum { SMOOTH_ZERO = 1, SMOOTH_FROM_TMP = 2 };
 template <typename T>
 ohm_status launch_dense_smooth(const ohm_hier *h, int level, T *B, T *tmp, const T *S, const T *eta,
                                const double *coef_dev, int nsweeps, bool all, const int *active, hipStream_t s,
-                               int flags = 0, const T *coarse = nullptr, T **last = nullptr);
+                               int flags = 0, const T *coarse = nullptr, T **last = nullptr, int ordering = 0);
 // dense level -> next coarser: coarse = restriction of S - L B; res is scratch
 // for handles where some continuing problem is not made of 8^3 tiles
 template <typename T>

@@ -127,7 +127,7 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
                 mx[c] = fmax(mx[c], fabs(rd));
             } else {  // smoother half-sweep
                 T v = sB[c][p];
-                if (((x + y + z) & 1) == colour) v = relax_point(v, S[c * cs + gi], dvs[c], als[c], c8, c2);
+                if (in_colour(x, y, z, colour)) v = relax_point(v, S[c * cs + gi], dvs[c], als[c], c8, c2);
                 out[c * cs + gi] = v;
             }
         }

@@ -65,7 +65,7 @@ k_dense_stencil(const int *__restrict__ tiles, const DenseProbDev *__restrict__ 
             out[c * cs + gi] = S[c * cs + gi] - LB;
         } else {
             T v = bc[c][13];
-            if (((i + j + k) & 1) == colour) v = relax_point(v, S[c * cs + gi], dvs[c], als[c], c8, c2);
+            if (in_colour(i, j, k, colour)) v = relax_point(v, S[c * cs + gi], dvs[c], als[c], c8, c2);
             out[c * cs + gi] = v;
         }
     }
@@ -462,18 +462,46 @@ ohm_status launch_dense_stencil(const ohm_hier *h, int level, int mode, const T 
 // nsweeps red-black sweeps of dense level `level`: B holds the start and the
 // result, tmp is scratch of the same size.  Problems whose grid is a whole
 // number of 8^3 tiles get one fused launch per sweep, the others two
-// half-sweep launches.  all = every problem present, else the problems that
+// half-sweep launches; the four-colour ordering takes four class launches per
+// sweep on every problem.  all = every problem present, else the problems that
 // are not coarsest at this level.
 template <typename T>
 ohm_status launch_dense_smooth(const ohm_hier *h, int level, T *B, T *tmp, const T *S, const T *eta,
                                const double *coef_dev, int nsweeps, bool all, const int *active, hipStream_t s,
-                               int flags, const T *coarse, T **last)
+                               int flags, const T *coarse, T **last, int ordering)
 {
     const DenseLevelDev &D = h->dense[-level];
     const long long cs = D.ncells;
     const int nft = all ? D.nftile_all : D.nftile, npt = all ? D.nptile_all : D.nptile;
     const int *ft = all ? D.ftiles_all : D.ftiles, *pt = all ? D.ptiles_all : D.ptiles;
     const bool zero = flags & SMOOTH_ZERO, from_tmp = (flags & SMOOTH_FROM_TMP) && !zero;
+    if (ordering != 0) {
+        // four class launches per sweep over the 256-cell tiles of every
+        // problem concerned, each a full out-of-place pass: a sweep returns to
+        // the buffer it started from
+        if (ordering != 1 || coarse || last)
+            return fail(OHM_ERR_ARG, "dense level %d: ordering %d (0 or 1; 1 takes no fused coarse correction)",
+                        level, ordering);
+        const int nt = all ? D.ntile_all : D.ntile;
+        const int *tl = all ? D.tiles_all : D.tiles;
+        if (nt == 0) return OHM_OK;
+        T *cur = from_tmp ? tmp : B, *oth = from_tmp ? B : tmp;
+        if (zero) {
+            k_dense_run_copy<T><<<nt, 256, 0, s>>>(tl, D.probs, active, nullptr, B, cs);
+            OHM_TRY(check_launch("dense run zero"));
+        }
+        for (int k = 0; k < nsweeps; ++k)
+            for (int m = 0; m < 4; ++m) {
+                k_dense_stencil<T, MODE_SMOOTH><<<nt, 256, 0, s>>>(tl, D.probs, active, coef_dev, (m & 1) ? oth : cur,
+                                                                   S, eta, (m & 1) ? cur : oth, cs, 2 + m);
+                OHM_TRY(check_launch("dense colour-class update"));
+            }
+        if (cur != B) {
+            k_dense_run_copy<T><<<nt, 256, 0, s>>>(tl, D.probs, active, cur, B, cs);
+            OHM_TRY(check_launch("dense run copy"));
+        }
+        return OHM_OK;
+    }
     if (nft > 0 && (unsigned long long)cs * sizeof(T) > 0xFFFFFFFFull)
         return fail(OHM_ERR_ARG, "dense level %d: fused sweep addresses each field array with 32-bit offsets", level);
     if ((coarse || last) && (npt > 0 || zero || nsweeps < 1 || -level >= -h->min_level))
@@ -701,7 +729,7 @@ size_t coarse_job_bytes() { return sizeof(CoarseJob); }
 #define INST(T)                                                                                                \
     template ohm_status launch_dense_smooth<T>(const ohm_hier *, int, T *, T *, const T *, const T *,           \
                                                const double *, int, bool, const int *, hipStream_t, int,       \
-                                               const T *, T **);                                               \
+                                               const T *, T **, int);                                          \
     template ohm_status launch_dense_stencil<T>(const ohm_hier *, int, int, const T *, const T *, const T *,   \
                                                 const double *, T *, int, bool, const int *, hipStream_t);     \
     template ohm_status launch_dense_restrict<T>(const ohm_hier *, int, const T *, T *, int, const int *,      \

@@ -90,6 +90,59 @@ def test_cycle_schedules_against_oracle(nu_pre, nu_post, nu_coarse, precision):
     assert np.linalg.norm(got - ex) <= _bound(np.linalg.norm(S), ex)
 
 
+@pytest.mark.parametrize("ordering,precision,cycle", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)])
+def test_one_iteration_equals_the_oracle_cycle(ordering, precision, cycle):
+    """One iteration of eqs. (16)-(18), x1 = x0 + M(S - L x0) from x0 = b,
+    against the oracle's own V(2, 2) cycle or FMG on the same hierarchy
+    (32^3 -> 16^3 -> 8^3 -> 4^3, dense solve on 4^3): the GPU cycle's every
+    sweep, transfer and coarse solve, red-black and four-colour.  Bound: FP64
+    rounding of the correction (1e-11 of its size); mixed precision, FP32
+    rounding (2e-5)."""
+    import paper_1009_0798_amd as ohm
+    announce(f"cn one iteration ordering={ordering} precision={precision} cycle={cycle}")
+    n = 32
+    spec = gen.uniform_spec(n)
+    h = spec.dx0
+    eta = gen.lognormal_eta(n, 3.0, seed=27)
+    B = gen.divfree(n, 2.0, seed=28)
+    dt = gen.explicit_dt(h, 1.0, 60.0)
+    st, stats, got = _gpu_step(spec, B, eta, dt, precision=precision, outer=0, cycle=cycle, n_vcycles=1,
+                               nu_pre=2, nu_post=2, max_iters=1, rtol=1e-14, ordering=ordering)
+    assert st == ohm._lib.OHM_ERR_NOCONV and stats[0]["iters"] == 1
+    lam_dt = 0.5 * dt
+    S = ref.source(B, eta, h, dt)
+    levels = mg.hierarchy(eta, h, lam_dt)
+    assert [lv.eta.shape[0] for lv in levels] == [32, 16, 8, 4]
+    R0 = ref.residual(B, S, eta, h, lam_dt)
+    e = mg.vcycle(levels, R0, 2, 2, 0, ordering) if cycle == 0 else mg.fmg(levels, R0, 1, 2, 2, ordering)
+    err = np.abs(got - (B + e)).max() / np.abs(e).max()
+    print("stats", stats, "max err / max correction", err)
+    assert err <= (1e-11 if precision == 0 else 2e-5)
+    if ordering == 1:
+        # the four-colour cycle is not the red-black one
+        e0 = mg.vcycle(levels, R0, 2, 2, 0, 0) if cycle == 0 else mg.fmg(levels, R0, 1, 2, 2, 0)
+        assert np.abs(e - e0).max() >= 1e-4 * np.abs(e).max()
+
+
+@pytest.mark.parametrize("ordering,precision", [(1, 0), (1, 1)])
+def test_four_colour_step_against_oracle(ordering, precision):
+    """A whole step with the four-colour smoother reaches the oracle's answer
+    (BiCGStab around V(2, 2), 32^3 log-normal)."""
+    announce(f"cn four-colour step precision={precision}")
+    n = 32
+    spec = gen.uniform_spec(n)
+    h = spec.dx0
+    eta = gen.lognormal_eta(n, 4.0, seed=21)
+    B = gen.divfree(n, 2.0, seed=22)
+    dt = gen.explicit_dt(h, 1.0, 100.0)
+    st, stats, got = _gpu_step(spec, B, eta, dt, precision=precision, max_iters=400, ordering=ordering)
+    ex, _ = mg.cn_step(B, eta, h, dt, rtol=1e-13)
+    S = ref.source(B, eta, h, dt)
+    print("stats", stats, "rel err vs oracle", np.linalg.norm(got - ex) / np.linalg.norm(ex))
+    assert st == 0 and stats[0]["rel_res"] <= RTOL
+    assert np.linalg.norm(got - ex) <= _bound(np.linalg.norm(S), ex)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_backward_euler_against_oracle(precision):
     """lambda = 1 (eq. 7): S = b and L = I + dt div F."""
@@ -154,11 +207,12 @@ def test_amr_two_levels_against_oracle():
     assert np.linalg.norm(diff) <= 1.5 * RTOL * nS + 1e-12 * np.linalg.norm(exv)
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_amr_three_levels_corner_gap_against_oracle(precision):
+@pytest.mark.parametrize("precision,ordering", [(0, 0), (1, 0), (0, 1)])
+def test_amr_three_levels_corner_gap_against_oracle(precision, ordering):
     """Three levels whose finest level lacks one corner ghost: level 1 smooths
-    with one launch per sweep (ghosts on every side), level 2 with half-sweeps."""
-    announce(f"cn amr 3 levels corner gap precision={precision}")
+    with one launch per sweep (ghosts on every side), level 2 with half-sweeps;
+    with the four-colour ordering every level takes one launch per class."""
+    announce(f"cn amr 3 levels corner gap precision={precision} ordering={ordering}")
     spec = gen.config_corner_gap()
     C = amr.Composite(spec)
     Bb, eb = gen.amr_fields(spec, p=2.0, seed=7)
@@ -170,7 +224,8 @@ def test_amr_three_levels_corner_gap_against_oracle(precision):
     H = hier(spec)
     Bt = [cuda(dense_to_blocks(Bs[l], spec.levels[l])) for l in range(L)]
     Et = [cuda(dense_to_blocks(es[l], spec.levels[l])[None]) for l in range(L)]
-    st, stats = ohm.ohm_cn_step(H, Bt, Et, dt, ohm.default_opts(rtol=RTOL, max_iters=300, precision=precision))
+    st, stats = ohm.ohm_cn_step(H, Bt, Et, dt, ohm.default_opts(rtol=RTOL, max_iters=300, precision=precision,
+                                                                 ordering=ordering))
     print(stats)
     assert st == 0 and stats[0]["rel_res"] <= RTOL
     ex, _ = C.cn_step(Bs, es, dt, rtol=1e-13)

@@ -103,6 +103,12 @@ def test_uniform_apply_residual_smooth(dtype):
         gotS = blocks_to_dense(host(Bs), ijk, spec.cells(0))
         exS = ref.smooth(B, S, eta, h, lam_dt, ns)
         assert np.abs(gotS - exS).max() <= 4 * ns * tol * scale, ns
+        # four colour classes, one launch each
+        Bs = Bt.clone()
+        ohm.ohm_smooth(H, 0, Bs, St, Et, lam_dt, ns, tmp, ordering=1)
+        gotS = blocks_to_dense(host(Bs), ijk, spec.cells(0))
+        exS = ref.smooth(B, S, eta, h, lam_dt, ns, ordering=1)
+        assert np.abs(gotS - exS).max() <= 8 * ns * tol * scale, ns
 
 
 @pytest.mark.parametrize("dtype,bb", [("f64", (3, 2, 4)), ("f32", (3, 2, 4)), ("f64", (4, 4, 2)), ("f32", (4, 4, 2))])
@@ -157,6 +163,13 @@ def test_dense_levels_and_transfers(dtype, bb):
     Bs = c1.clone()
     ohm.ohm_smooth(H, -1, Bs, St1, et1, lam_dt, 2, torch.empty_like(c1))
     assert np.abs(host(Bs).reshape(ex1.shape) - ref.smooth(ex1, S1, e1, h1, lam_dt, 2)).max() <= 8 * tol * scale
+    for ns in (1, 2):
+        Bs = c1.clone()
+        ohm.ohm_smooth(H, -1, Bs, St1, et1, lam_dt, ns, torch.empty_like(c1), ordering=1)
+        ex = ref.smooth(ex1, S1, e1, h1, lam_dt, ns, ordering=1)
+        assert np.abs(host(Bs).reshape(ex1.shape) - ex).max() <= 8 * ns * tol * scale, ns
+    with pytest.raises(RuntimeError, match="ordering"):
+        ohm.ohm_smooth(H, -1, c1.clone(), St1, et1, lam_dt, 1, torch.empty_like(c1), ordering=2)
 
 
 def _amr_spec(three=False):
@@ -181,14 +194,15 @@ def _amr_fields(spec, seed):
     return Bs, es
 
 
-@pytest.mark.parametrize("nsweeps", [1, 2])
-def test_smoother_with_ghosts(nsweeps):
+@pytest.mark.parametrize("nsweeps,ordering", [(1, 0), (2, 0), (1, 1), (2, 1)])
+def test_smoother_with_ghosts(nsweeps, ordering):
     """Smoothing on AMR levels with ghost blocks held fixed.  Level 1 of this
-    hierarchy has ghosts on faces, edges and corners (one launch per sweep);
-    level 2 lacks one corner ghost (two half-sweep launches per sweep)."""
+    hierarchy has ghosts on faces, edges and corners (one launch per
+    red-black sweep); level 2 lacks one corner ghost (two half-sweep launches
+    per sweep); the four-colour ordering takes four class launches."""
     import torch
     import paper_1009_0798_amd as ohm
-    announce(f"smoother with ghosts nsweeps={nsweeps}")
+    announce(f"smoother with ghosts nsweeps={nsweeps} ordering={ordering}")
     spec = gen.config_corner_gap()
     C = amr.Composite(spec)
     Bs, es = _amr_fields(spec, 12)
@@ -208,14 +222,16 @@ def test_smoother_with_ghosts(nsweeps):
         S = np.random.default_rng(20 + l).standard_normal(Bs[l].shape)
         St = cuda(dense_to_blocks(S, spec.levels[l]))
         Bsm = Bt[l].clone()
-        ohm.ohm_smooth(H, l, Bsm, St, Et[l], coef, nsweeps, torch.empty_like(Bsm), B_ghost=g, eta_ghost=ge)
+        ohm.ohm_smooth(H, l, Bsm, St, Et[l], coef, nsweeps, torch.empty_like(Bsm), B_ghost=g, eta_ghost=ge,
+                       ordering=ordering)
         got = blocks_to_dense(host(Bsm), spec.levels[l], spec.cells(l))
         m = C.mask[l]
         x = Bfull[l].copy()
         ghost_vals = x.copy()
+        classes = ref.colour_classes(efull[l].shape, ordering)
         for _ in range(nsweeps):
-            for colour in (0, 1):
-                x = ref.rb_halfsweep(x, S, efull[l], h, coef, colour)
+            for colour in range(2 if ordering == 0 else 4):
+                x = ref.class_update(x, S, efull[l], h, coef, classes, colour)
                 x = np.where(m[None], x, ghost_vals)
         scale = _scale(Bfull[l][:, m], efull[l], coef, h)
         err = float(np.abs(got[:, m] - x[:, m]).max())
