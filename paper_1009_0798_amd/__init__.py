@@ -148,10 +148,16 @@ def ohm_reflux(h: Hierarchy, level, B_coarse, eta_coarse, B_fine, eta_fine, coef
 
 
 def default_opts(**kw) -> CnOpts:
+    """The library's default ohm_cn_opts with the given fields replaced
+    (``lam`` for lambda); an unknown name raises instead of being ignored."""
     o = CnOpts()
     lib().ohm_cn_default_opts(ctypes.byref(o))
+    names = {f[0] for f in CnOpts._fields_}
     for k, v in kw.items():
-        setattr(o, "lambda_" if k == "lam" else k, v)
+        name = "lambda_" if k == "lam" else k
+        if name not in names:
+            raise TypeError(f"unknown Crank-Nicolson option {k!r}")
+        setattr(o, name, v)
     return o
 
 

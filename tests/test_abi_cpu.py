@@ -96,3 +96,15 @@ def test_null_handle_errors():
     o = _lib.CnOpts()
     L.ohm_cn_default_opts(ctypes.byref(o))
     assert o.lambda_ == 0.5 and o.rtol == 1e-10
+
+
+def test_default_opts_fields_and_unknown_names():
+    """The binding's option structure matches the library's defaults field by
+    field (a shifted field would show here), and a misspelled option raises."""
+    import paper_1009_0798_amd as ohm
+    o = ohm.default_opts()
+    assert (o.lambda_, o.rtol, o.max_iters, o.nu_pre, o.nu_post, o.n_vcycles, o.cycle, o.outer, o.precision,
+            o.coarse_sweeps, o.nu_coarse, o.graph, o.ordering) == (0.5, 1e-10, 100, 2, 2, 1, 0, 1, 0, 16, 0, 1, 0)
+    assert ohm.default_opts(lam=1.0, ordering=1).ordering == 1
+    with pytest.raises(TypeError, match="nu_pree"):
+        ohm.default_opts(nu_pree=3)

@@ -237,17 +237,21 @@ def test_amr_three_levels_corner_gap_against_oracle(precision, ordering):
     assert np.linalg.norm(diff) <= 1.5 * RTOL * nS + 1e-12 * np.linalg.norm(exv)
 
 
-def test_nonfinite_input_is_reported():
-    """A NaN in B reaches the initial residual: the step stops with
-    OHM_ERR_NONFINITE before any iteration."""
+@pytest.mark.parametrize("where", ["B", "eta"])
+def test_nonfinite_input_is_reported(where):
+    """A NaN in B or in the resistivity reaches the source and the initial
+    residual: the step stops with OHM_ERR_NONFINITE before any iteration."""
     import paper_1009_0798_amd as ohm
     from paper_1009_0798_amd import _lib
-    announce("cn non-finite input")
+    announce(f"cn non-finite input in {where}")
     n = 16
     spec = gen.uniform_spec(n)
     B = gen.divfree(n, 2.0, seed=3)
     eta = gen.lognormal_eta(n, 1.0, seed=4)
-    B[1, 3, 4, 5] = np.nan
+    if where == "B":
+        B[1, 3, 4, 5] = np.nan
+    else:
+        eta[2, 5, 7] = np.nan
     H = hier(spec)
     Bt = [cuda(dense_to_blocks(B, spec.levels[0]))]
     Et = [cuda(dense_to_blocks(eta, spec.levels[0])[None])]
