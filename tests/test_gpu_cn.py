@@ -289,11 +289,13 @@ def test_large_step_undulation_and_monotone_decay(lam):
     assert np.abs(got[2] - g * B[2]).max() <= 1e-9
 
 
-def test_batched_equals_alone():
+@pytest.mark.parametrize("ordering", [0, 1])
+def test_batched_equals_alone(ordering):
     """Three problems of different sizes in one handle give the same answer as
-    each solved alone (per-problem reductions in a fixed order)."""
+    each solved alone (per-problem reductions in a fixed order), with either
+    smoother ordering (the 24^3 problem's dense levels are not whole tiles)."""
     import paper_1009_0798_amd as ohm
-    announce("cn batched vs alone")
+    announce(f"cn batched vs alone ordering={ordering}")
     sizes = [16, 24, 32]
     probs, Bs, Es, dts = [], [], [], []
     for i, n in enumerate(sizes):
@@ -306,13 +308,13 @@ def test_batched_equals_alone():
     Bcat = np.concatenate([dense_to_blocks(B, s.levels[0]) for B, s in zip(Bs, probs)], axis=1)
     Ecat = np.concatenate([dense_to_blocks(E, s.levels[0])[None] for E, s in zip(Es, probs)], axis=1)
     Bt, Et = [cuda(Bcat)], [cuda(Ecat)]
-    st, stats = ohm.ohm_cn_step(Hb, Bt, Et, dts, ohm.default_opts(rtol=RTOL))
+    st, stats = ohm.ohm_cn_step(Hb, Bt, Et, dts, ohm.default_opts(rtol=RTOL, ordering=ordering))
     assert st == 0
     out = host(Bt[0])
     o = 0
     for i, s in enumerate(probs):
         nb = len(s.levels[0])
-        st1, stats1, alone = _gpu_step(s, Bs[i], Es[i], dts[i])
+        st1, stats1, alone = _gpu_step(s, Bs[i], Es[i], dts[i], ordering=ordering)
         mine = blocks_to_dense(out[:, o:o + nb], s.levels[0], s.cells(0))
         o += nb
         assert stats1[0]["iters"] == stats[i]["iters"]
