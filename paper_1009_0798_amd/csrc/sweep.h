@@ -177,6 +177,18 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
     }
     __syncthreads();
     const T c8 = cih2 * T(0.125), c2 = cih2 * T(0.5);
+    // the black cell of this thread and its S values, loaded before the red
+    // half-sweep so that their latency overlaps it
+    int pb = -1;
+    T sbk[3];
+    if (u < 256) {
+        const int z = u >> 5, y = (u >> 2) & 7, x = 2 * (u & 3) + (1 - ((y + z) & 1));
+        pb = tix2(x, y, z);
+        const unsigned off = (unsigned)A.at(x, y, z) * (unsigned)sizeof(T);
+        sbk[0] = load_at(S0, off);
+        sbk[1] = load_at(S1, off);
+        sbk[2] = load_at(S2, off);
+    }
     // red half-sweep: thread u < 256 takes tile cell u of the red colour,
     // 256 <= u < 448 a red first-layer face cell
     T red[3];
@@ -222,21 +234,16 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
     // black half-sweep on the tile (threads 0..255)
     {
         T blk[3];
-        int p = -1;
         if (u < 256) {
-            const int z = u >> 5, y = (u >> 2) & 7, x = 2 * (u & 3) + (1 - ((y + z) & 1));
-            p = tix2(x, y, z);
-            const unsigned off = (unsigned)A.at(x, y, z) * (unsigned)sizeof(T);
-            const T s3[3] = {load_at(S0, off), load_at(S1, off), load_at(S2, off)};
             T dv[3], al[3];
-            divF_all<T, TW2>(sB[0], sB[1], sB[2], sE, p, dv, al);
+            divF_all<T, TW2>(sB[0], sB[1], sB[2], sE, pb, dv, al);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) blk[c] = relax_point(sB[c][p], s3[c], dv[c], al[c], c8, c2);
+            for (int c = 0; c < 3; ++c) blk[c] = relax_point(sB[c][pb], sbk[c], dv[c], al[c], c8, c2);
         }
         __syncthreads();
-        if (p >= 0)
+        if (pb >= 0)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) sB[c][p] = blk[c];
+            for (int c = 0; c < 3; ++c) sB[c][pb] = blk[c];
     }
     __syncthreads();
     {
