@@ -96,6 +96,29 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
     if (threadIdx.x < 27) snbr[threadIdx.x] = nbr_tab[27 * (long long)b + threadIdx.x];
     __syncthreads();
     load_tile_b_eta<T>(sB, sE[0], B, Bg, cs, gcs, eta, etag, snbr);
+    // values read per cell after the stencil (S, or the other vector of the
+    // first fused dot product that has one), loaded with the tile so that
+    // their latency overlaps it
+    constexpr bool HAS_S = MODE == MODE_RESID || MODE == MODE_RESID_RESTRICT || MODE == MODE_SMOOTH;
+    T pS[2][3];
+    double pY[2][3];
+    int qy = -1;
+    if (HAS_S) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pS[half][c] = S[c * cs + (long long)b * NC + threadIdx.x + 256 * half];
+    }
+    if (MODE == MODE_APPLY) {
+        for (int q = dots.ndot - 1; q >= 0; --q)
+            if (dots.dot_y[q]) qy = q;
+        if (qy >= 0)
+#pragma unroll
+            for (int half = 0; half < 2; ++half)
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    pY[half][c] = dots.dot_y[qy][c * cs + (long long)b * NC + threadIdx.x + 256 * half];
+    }
     __syncthreads();
     const T cih2 = T(coef_p[pr]) * T(inv_h2_p[pr]);
     const T c8 = cih2 * T(0.125), c2 = cih2 * T(0.5);
@@ -118,16 +141,16 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
                 o[half][c] = zero ? T(0) : LB;
                 out[c * cs + gi] = o[half][c];
             } else if (MODE == MODE_RESID_RESTRICT) {
-                o[half][c] = zero ? T(0) : S[c * cs + gi] - LB;
+                o[half][c] = zero ? T(0) : pS[half][c] - LB;
             } else if (MODE == MODE_RESID) {
-                T r = zero ? T(0) : S[c * cs + gi] - LB;
+                T r = zero ? T(0) : pS[half][c] - LB;
                 if (out) out[c * cs + gi] = r;
                 double rd = (double)r;
                 ss[c] += rd * rd;
                 mx[c] = fmax(mx[c], fabs(rd));
             } else {  // smoother half-sweep
                 T v = sB[c][p];
-                if (in_colour(x, y, z, colour)) v = relax_point(v, S[c * cs + gi], dvs[c], als[c], c8, c2);
+                if (in_colour(x, y, z, colour)) v = relax_point(v, pS[half][c], dvs[c], als[c], c8, c2);
                 out[c * cs + gi] = v;
             }
         }
@@ -143,7 +166,8 @@ k_blk_stencil(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__
 #pragma unroll
                 for (int half = 0; half < 2; ++half) {
                     const long long gi = (long long)b * NC + threadIdx.x + 256 * half;
-                    const double y = dots.dot_y[q] ? dots.dot_y[q][c * cs + gi] : (double)o[half][c];
+                    const double y = q == qy ? pY[half][c]
+                                     : (dots.dot_y[q] ? dots.dot_y[q][c * cs + gi] : (double)o[half][c]);
                     acc += (double)o[half][c] * y;
                 }
             for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);

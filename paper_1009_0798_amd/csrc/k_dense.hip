@@ -186,6 +186,16 @@ k_dense_resid_restrict(const int *__restrict__ ftiles, const DenseProbDev *__res
             sE[t] = v[k][3];
         }
     }
+    // S of this thread's two cells, loaded before the barrier so that its
+    // latency overlaps the tile's
+    T s2[2][3];
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+        const int cell = threadIdx.x + 256 * half;
+        const long long gi = A.at(cell & 7, (cell >> 3) & 7, cell >> 6);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s2[half][c] = S[c * cs + gi];
+    }
     __syncthreads();
     const T c8 = T(coef_p[pr]) * T(q.inv_h2) * T(0.125);
     T r[2][3];
@@ -194,11 +204,10 @@ k_dense_resid_restrict(const int *__restrict__ ftiles, const DenseProbDev *__res
         const int cell = threadIdx.x + 256 * half;
         const int x = cell & 7, y = (cell >> 3) & 7, z = cell >> 6;
         const int p = (x + 1) + W * ((y + 1) + W * (z + 1));
-        const long long gi = A.at(x, y, z);
         T dv[3], al[3];
         divF_all<T, W>(sB[0], sB[1], sB[2], sE, p, dv, al);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) r[half][c] = S[c * cs + gi] - fma(c8, dv[c], sB[c][p]);
+        for (int c = 0; c < 3; ++c) r[half][c] = s2[half][c] - fma(c8, dv[c], sB[c][p]);
     }
     __syncthreads();
 #pragma unroll
