@@ -7,6 +7,8 @@ import pytest
 import ohm_inputs as gen
 from oracle import closed, mg, ref
 
+from golden_values import paper
+
 
 def test_cn_step_matches_fft_closed_form():
     """Constant eta, periodic: the oracle's V-cycle-preconditioned BiCGStab
@@ -84,7 +86,8 @@ def test_heat_factor_and_paper_amplitude():
     exact = closed.continuum_decay(kx ** 2 + ky ** 2, 1.0, 4e-3)
     assert abs(exact - 0.4540) < 1e-4
     assert abs(amp - exact) < 5e-3
-    assert round(amp, 2) == 0.45
+    printed = paper("sinusoid_amplitude_t4e-3")
+    assert round(amp, printed["digits"]) == printed["value"]
 
 
 def _sinusoid_error(n_cells_per_unit, dt, t_end, lam):
@@ -112,10 +115,10 @@ def test_temporal_order():
     for lam in (0.5, 1.0):
         for dt in dts:
             errs[lam].append(_sinusoid_error(32, dt, 2e-3, lam)[1])
-    s_cn = np.log(errs[0.5][0] / errs[0.5][-1]) / np.log(dts[0] / dts[-1])
-    s_be = np.log(errs[1.0][0] / errs[1.0][-1]) / np.log(dts[0] / dts[-1])
-    assert 1.8 <= s_cn <= 2.2, s_cn
-    assert 0.9 <= s_be <= 1.1, s_be
+    order = paper("temporal_order")["value"]
+    for lam in (0.5, 1.0):
+        slope = np.log(errs[lam][0] / errs[lam][-1]) / np.log(dts[0] / dts[-1])
+        assert abs(slope - order[str(lam)]) <= 0.1 * order[str(lam)], (lam, slope)
 
 
 def test_spatial_order():
@@ -127,4 +130,4 @@ def test_spatial_order():
         dt = 2e-4 * (16 / n) ** 2
         errs.append(_sinusoid_error(n, dt, 4e-4, 0.5)[0])
     s = np.log(errs[0] / errs[-1]) / np.log(ns[-1] / ns[0])
-    assert 1.8 <= s <= 2.2, s
+    assert abs(s - paper("spatial_order")["value"]) <= 0.2, s
