@@ -22,7 +22,7 @@ HBM_PEAK_GBS = 8000.0
 # Cycle schedules (pre, post sweeps on the base grid; one sweep on the levels
 # below it) picked by the autotuner on MI355X, per precision of the cycle, for
 # the 128^3 log-normal workload, and for the two-level AMR workload
-SCHEDULE = {0: (2, 5), 1: (3, 4)}
+SCHEDULE = {0: (2, 5), 1: (2, 5)}
 NU_COARSE = 1
 AMR_SCHEDULE = (4, 4)
 SERVE_SCHEDULE = (2, 2, 0)   # (pre, post, below the base grid; 0 = as the base grid) for serving
