@@ -596,6 +596,7 @@ __global__ void k_zero_covered(int nblk, const uint8_t *__restrict__ cov, T *__r
                                int ncomp)
 {
     const int b = blockIdx.x;
+    if (b >= nblk) return;
     const uint8_t m = cov[b];
     if (!m) return;
     for (int cell = threadIdx.x; cell < NC; cell += blockDim.x) {
@@ -616,6 +617,7 @@ k_reduce_blocks(int nprob, int nrange, const long long *__restrict__ range, cons
 {
     __shared__ double sred[4];
     const int p = blockIdx.x / k, q = blockIdx.x % k;
+    if (p >= nprob) return;   // uniform per workgroup, before any barrier
     const bool sum = q < ksum;
     double v = 0.0;
     long long base = 0;   // running block count of the problem (thread striding is global over its ranges)
