@@ -48,19 +48,55 @@ inline uint64_t key3(int i, int j, int k)
     return ((uint64_t)(uint32_t)i << 42) | ((uint64_t)(uint32_t)j << 21) | (uint64_t)(uint32_t)k;
 }
 
-struct LevelMap {
-    std::unordered_map<uint64_t, int> idx;  // block coords -> local index
-    int box[3];
-    bool has(int i, int j, int k) const
+// i wrapped into [0, n); one conditional step for the usual offsets of a
+// neighbour or a parent, the general remainder otherwise
+inline int wrap1(int i, int n)
+{
+    if (i < 0) i += n;
+    else if (i >= n) i -= n;
+    return (i < 0 || i >= n) ? wrapi(i, n) : i;
+}
+
+// block coordinates -> index over a periodic box of blocks (-1 = none): a
+// dense table when the box has at most 2^24 positions, a hash map otherwise
+struct BoxIndex {
+    int box[3] = {0, 0, 0};
+    bool use_dense = false;
+    std::vector<int> dense;
+    std::unordered_map<uint64_t, int> sparse;
+    void init(int b0, int b1, int b2)
     {
-        return idx.count(key3(wrapi(i, box[0]), wrapi(j, box[1]), wrapi(k, box[2]))) != 0;
+        box[0] = b0;
+        box[1] = b1;
+        box[2] = b2;
+        const long long vol = (long long)b0 * b1 * b2;
+        use_dense = vol <= (1LL << 24);
+        if (use_dense) dense.assign((size_t)vol, -1);
     }
+    size_t lin(int i, int j, int k) const { return (size_t)i + (size_t)box[0] * ((size_t)j + (size_t)box[1] * k); }
     int get(int i, int j, int k) const
     {
-        auto it = idx.find(key3(wrapi(i, box[0]), wrapi(j, box[1]), wrapi(k, box[2])));
-        return it == idx.end() ? -1 : it->second;
+        i = wrap1(i, box[0]);
+        j = wrap1(j, box[1]);
+        k = wrap1(k, box[2]);
+        if (use_dense) return dense[lin(i, j, k)];
+        auto it = sparse.find(key3(i, j, k));
+        return it == sparse.end() ? -1 : it->second;
+    }
+    bool has(int i, int j, int k) const { return get(i, j, k) >= 0; }
+    // (i, j, k) inside the box; false if the position already has an index
+    bool insert(int i, int j, int k, int v)
+    {
+        if (use_dense) {
+            int &slot = dense[lin(i, j, k)];
+            if (slot >= 0) return false;
+            slot = v;
+            return true;
+        }
+        return sparse.emplace(key3(i, j, k), v).second;
     }
 };
+using LevelMap = BoxIndex;   // block coords -> local block index of one level
 
 bool coarsen_ok(const int n[3])
 {
@@ -107,7 +143,7 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
             if (d.nblocks[l] < 1 || !d.block_ijk[l])
                 return fail(OHM_ERR_ARG, "problem %d level %d: no blocks", p, l);
             LevelMap &M = maps[p][l];
-            for (int a = 0; a < 3; ++a) M.box[a] = d.base_blocks[a] << l;
+            M.init(d.base_blocks[0] << l, d.base_blocks[1] << l, d.base_blocks[2] << l);
             P.blocks[l].assign(d.block_ijk[l], d.block_ijk[l] + 3 * (size_t)d.nblocks[l]);
             P.nb[l] = d.nblocks[l];
             for (int b = 0; b < d.nblocks[l]; ++b) {
@@ -116,7 +152,7 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
                     if (q[a] < 0 || q[a] >= M.box[a])
                         return fail(OHM_ERR_LAYOUT, "problem %d level %d block %d: (%d,%d,%d) outside the box",
                                     p, l, b, q[0], q[1], q[2]);
-                if (!M.idx.emplace(key3(q[0], q[1], q[2]), b).second)
+                if (!M.insert(q[0], q[1], q[2], b))
                     return fail(OHM_ERR_LAYOUT, "problem %d level %d: duplicate block (%d,%d,%d)", p, l,
                                 q[0], q[1], q[2]);
             }
@@ -218,7 +254,8 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
             ohm_prob_host &P = H->probs[p];
             if (l >= P.nlevels) continue;
             const LevelMap &M = maps[p][l];
-            std::unordered_map<uint64_t, int> ghost_of;
+            BoxIndex ghost_of;   // wrapped position -> ghost block
+            ghost_of.init(M.box[0], M.box[1], M.box[2]);
             int lo3[3], hi3[3];
             for (int b = 0; b < P.nb[l]; ++b) {
                 int gb = (int)P.boff[l] + b;
@@ -252,20 +289,16 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
                     }
                     int w[3] = {wrapi(q[0] + dx, M.box[0]), wrapi(q[1] + dy, M.box[1]),
                                 wrapi(q[2] + dz, M.box[2])};
-                    uint64_t k = key3(w[0], w[1], w[2]);
-                    auto it = ghost_of.find(k);
-                    int g;
-                    if (it == ghost_of.end()) {
+                    int g = ghost_of.get(w[0], w[1], w[2]);
+                    if (g < 0) {
                         g = ng++;
-                        ghost_of.emplace(k, g);
+                        ghost_of.insert(w[0], w[1], w[2], g);
                         const LevelMap &C = maps[p][l - 1];
                         int pb = C.get(w[0] >> 1, w[1] >> 1, w[2] >> 1);
                         if (pb < 0) return fail(OHM_ERR_LAYOUT, "internal: ghost without parent");
                         gparent.push_back((int)P.boff[l - 1] + pb);
                         goctant.push_back((w[0] & 1) + 2 * (w[1] & 1) + 4 * (w[2] & 1));
                         gprob.push_back(p);
-                    } else {
-                        g = it->second;
                     }
                     nbr[27 * (size_t)gb + e] = -1 - g;
                 }
