@@ -8,7 +8,9 @@ becomes free, builds one multi-problem handle for them, and runs the step on
 its own HIP stream; a batch that arrives while another is on the GPU starts
 on the next free stream, so their work overlaps on the device.  Results stay
 bitwise equal to a solve alone: every reduction is per problem in a fixed
-order.
+order.  Fields travel through pinned host buffers in both directions; a
+request's ``result`` arrays are views of its batch's pinned output buffer,
+which stays allocated until every result of the batch has been released.
 
 All arithmetic runs in the HIP library; this module only schedules.
 """
