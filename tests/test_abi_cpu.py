@@ -108,3 +108,36 @@ def test_default_opts_fields_and_unknown_names():
     assert ohm.default_opts(lam=1.0, ordering=1).ordering == 1
     with pytest.raises(TypeError, match="nu_pree"):
         ohm.default_opts(nu_pree=3)
+
+
+def _slab_levels(depth, shift_last=0):
+    """64 x 1 x 1 base blocks; level l refines a 4-block-wide slab in x over all
+    of y and z, nested in level l-1 with a one-coarse-block margin (so every
+    level but the last is properly nested; shift_last = 1 moves the last one
+    to the edge of its parent slab)."""
+    bb = (64, 1, 1)
+    levels = [gen.full_level(bb)]
+    a = 10
+    for l in range(1, depth + 1):
+        a = 2 * a + 2 if l > 1 else a
+        x0 = a - (shift_last if l == depth else 0)
+        n = 1 << l
+        levels.append(np.array([(x, y, z) for z in range(n) for y in range(n) for x in range(x0, x0 + 4)],
+                               dtype=np.int32))
+        a = x0
+    return bb, levels
+
+
+def test_deep_levels_use_the_sparse_block_index():
+    """Level 7 of a 64 x 1 x 1-block base spans 8192 x 128 x 128 block
+    positions, more than the dense block index of the handle build holds
+    (2^24), so its lookups go through the hash map: a properly built chain is
+    accepted up to validation, a duplicate block there and a block whose
+    coarser cover is missing are still rejected."""
+    bb, levels = _slab_levels(7)
+    dup = levels[:-1] + [np.concatenate([levels[-1], levels[-1][5:6]])]
+    st, msg = _create([(bb, 1.0, dup)])
+    assert st == 2 and "duplicate" in msg and "level 7" in msg, msg
+    bb, bad = _slab_levels(7, shift_last=1)
+    st, msg = _create([(bb, 1.0, bad)])
+    assert st == 2 and "level 7" in msg and "not properly nested" in msg, msg
