@@ -410,3 +410,33 @@ def test_coarse_inverse_cache_follows_eta_and_dt():
         assert st == 0 and st2 == 0
         got = blocks_to_dense(host(Bt[0]), ijk, spec.cells(0))
         assert np.array_equal(got, fresh)
+
+
+def test_degenerate_inputs():
+    """B = 0: S = 0, the step returns zeros at once (relative residual 0, not
+    0/0).  eta = 0 everywhere: L = I and S = b, the initial residual is exactly
+    zero and B comes back bit for bit.  Zero smoothing sweeps leave B alone."""
+    import torch
+    import paper_1009_0798_amd as ohm
+    announce("cn degenerate inputs")
+    n = 16
+    spec = gen.uniform_spec(n)
+    eta = gen.lognormal_eta(n, 2.0, seed=71)
+    dt = gen.explicit_dt(spec.dx0, 1.0, 50.0)
+    st, stats, got = _gpu_step(spec, np.zeros((3, n, n, n)), eta, dt)
+    assert st == 0 and stats[0]["iters"] == 0 and stats[0]["rel_res"] == 0.0
+    assert not got.any()
+    B = gen.divfree(n, 2.0, seed=72)
+    for precision in (0, 1):
+        st, stats, got = _gpu_step(spec, B, np.zeros((n, n, n)), dt, precision=precision)
+        assert st == 0 and stats[0]["iters"] == 0 and stats[0]["rel_res"] == 0.0
+        assert np.array_equal(got, B)
+    H = hier(spec)
+    ijk = spec.levels[0]
+    Bt = cuda(dense_to_blocks(B, ijk))
+    Et = cuda(dense_to_blocks(eta, ijk)[None])
+    St = cuda(dense_to_blocks(ref.source(B, eta, spec.dx0, dt), ijk))
+    before = Bt.clone()
+    for ordering in (0, 1):
+        ohm.ohm_smooth(H, 0, Bt, St, Et, 0.5 * dt, 0, torch.empty_like(Bt), ordering=ordering)
+        assert torch.equal(Bt, before)
