@@ -156,9 +156,10 @@ ohm_status ohm_residual(ohm_hier *h, int32_t level, const void *B, const void *B
  * fixed.  `tmp` is caller scratch of the size of B; B holds the result.  On
  * levels where each of the 26 neighbour positions of every block is a level
  * block or a ghost block (all levels, unless some corner ghost would need
- * coarse cells that do not exist) one launch performs a whole sweep; it needs
- * B, eta and the ghost arrays aligned to 2 elements (OHM_ERR_ARG otherwise)
- * and each field or ghost array of the level below 4 GiB.
+ * coarse cells that do not exist) and whose field and ghost arrays are at
+ * most 4 GiB per component, one launch performs a whole sweep; it needs B, eta
+ * and the ghost arrays aligned to 2 elements (OHM_ERR_ARG otherwise).  Other
+ * levels take one launch per colour.
  * ordering: 0 = the paper's red-black; 1 = four colour classes
  * ((i+j) mod 2) + 2 ((j+k) mod 2), updated in that order with the same
  * update.  No two cells of a class share a stencil term, so on grids of even

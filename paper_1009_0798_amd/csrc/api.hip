@@ -184,7 +184,11 @@ ohm_status ohm_smooth(ohm_hier *h, int32_t level, void *B, const void *B_ghost, 
     double *cd;
     int slot;
     OHM_TRY(coef_slot(h, lam_dt, stream, &cd, &slot));
-    if (level >= 0 && h->amr[level].fused && ordering == 0) {
+    // one fused launch per sweep where the level's arrays fit the sweep's
+    // 32-bit offsets, else one launch per colour
+    const unsigned long long per = (unsigned long long)NC * (dtype == OHM_F64 ? 8 : 4), lim = 0xFFFFFFFFull;
+    if (level >= 0 && h->amr[level].fused && ordering == 0 && h->amr[level].nb * per <= lim &&
+        (h->amr[level].complete27 || h->amr[level].ng * per <= lim)) {
         const long long cs = level_cs(h, level), gcs = (long long)h->ng_host[level] * NC;
         for (int k = 0; k < nsweeps; ++k) {
             const void *src = (k & 1) ? tmp : B;

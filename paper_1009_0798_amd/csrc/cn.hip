@@ -218,9 +218,17 @@ struct Solver {
     double *out64_ = nullptr;
     bool wrote64_ = false;
 
-    // fused sweeps are red-black; the four-colour ordering takes one class
-    // launch per colour (coarse and out64 are for fused sweeps only)
-    bool fused_blk(int l) const { return h->amr[l].fused && o->ordering == 0; }
+    // fused sweeps are red-black and address each field (and ghost) array of
+    // the level with 32-bit byte offsets; the four-colour ordering, and levels
+    // above 4 GiB per component, take one launch per colour class (coarse and
+    // out64 are for fused sweeps only)
+    bool fused_blk(int l) const
+    {
+        const AmrLevelDev &A = h->amr[l];
+        const unsigned long long lim = 0xFFFFFFFFull, per = (unsigned long long)NC * sizeof(T);
+        return A.fused && o->ordering == 0 && (unsigned long long)A.nb * per <= lim &&
+               (A.complete27 || (unsigned long long)A.ng * per <= lim);
+    }
     ohm_status smooth_blk(int l, int n, int flags = 0, const T *coarse = nullptr, double *out64 = nullptr)
     {
         const bool zero = flags & SMOOTH_ZERO, from_tmp = (flags & SMOOTH_FROM_TMP) && !zero;
@@ -329,7 +337,7 @@ struct Solver {
                                                   active, st));
             OHM_TRY(down_dense(1));
             const T *e1 = ecur_of(1);
-            const bool fz = h->amr[0].complete27 && o->ordering == 0;
+            const bool fz = h->amr[0].complete27 && fused_blk(0);
             if (fz && nu2 > 0 && !(nu2 & 1)) {
                 // even count: the first sweep adds the correction as it loads
                 OHM_TRY(smooth_blk(0, nu2, 0, e1, out64_));
@@ -433,7 +441,10 @@ struct Solver {
                                      GN, etaT(l), etagT(l), neg_lam_dt, mg(P.rhs, l - 1), active, st));
         }
         // one FP32 level: the last post-sweep writes the FP64 result directly
-        double *const o64 = (P.T32 && L == 1 && h->amr[0].complete27 && fused_blk(0)) ? at<double>(zo) : nullptr;
+        double *const o64 = (P.T32 && L == 1 && h->amr[0].complete27 && fused_blk(0) &&
+                             (unsigned long long)h->amr[0].nb * NC * sizeof(double) <= 0xFFFFFFFFull)
+                                ? at<double>(zo)
+                                : nullptr;
         wrote64_ = false;
         if (o->cycle == 1) {
             out64_ = o64;
