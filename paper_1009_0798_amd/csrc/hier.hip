@@ -112,6 +112,7 @@ ohm_status upload(V **dptr, const std::vector<V> &h)
 {
     *dptr = nullptr;
     if (h.empty()) return OHM_OK;
+    std::lock_guard<std::mutex> lock(capture_mutex());   // device work outside any captured stream
     OHM_HIP(hipMalloc((void **)dptr, sizeof(V) * h.size()));
     OHM_HIP(hipMemcpyAsync(*dptr, h.data(), sizeof(V) * h.size(), hipMemcpyHostToDevice, g_up_stream));
     OHM_HIP(hipStreamSynchronize(g_up_stream));
@@ -512,6 +513,7 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
         OHM_TRY(upload(&D.probs, dp));
     }
     // ---- scratch ---------------------------------------------------------------
+    std::lock_guard<std::mutex> lock(capture_mutex());
     OHM_HIP(hipMalloc((void **)&H->d_scal, sizeof(double) * 4 * nprob));
     OHM_HIP(hipMalloc((void **)&H->d_norms, sizeof(double) * 8 * nprob));
     OHM_HIP(hipHostMalloc((void **)&H->h_dots, sizeof(double) * 8 * nprob, hipHostMallocDefault));
@@ -571,11 +573,13 @@ ohm_status ohm_hier_create(const ohm_problem_desc *probs, int32_t nprob, hipStre
     if (!probs || nprob < 1) return fail(OHM_ERR_ARG, "need at least one problem");
     ohm_hier *H = new (std::nothrow) ohm_hier();
     if (!H) return fail(OHM_ERR_NOMEM, "host allocation failed");
-    std::lock_guard<std::mutex> lock(capture_mutex());
+    // the host tables are built without the capture lock; each device
+    // allocation and upload takes it
     g_up_stream = stream;
     ohm_status st = build(H, probs, nprob);
     g_up_stream = nullptr;
     if (st != OHM_OK) {
+        std::lock_guard<std::mutex> lock(capture_mutex());
         free_all(H);
         delete H;
         return st;
