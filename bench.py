@@ -356,7 +356,7 @@ def main():
     ap.add_argument("--requests", type=int, default=64)
     ap.add_argument("--pool", type=int, default=8)
     ap.add_argument("--rate", type=float, default=200.0)
-    ap.add_argument("--streams", type=int, default=2)
+    ap.add_argument("--streams", type=int, default=4)
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--hbm-gb", type=float, default=64.0)
     ap.add_argument("--record-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
