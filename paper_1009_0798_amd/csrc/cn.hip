@@ -413,19 +413,22 @@ struct Solver {
     }
 
     // z = M(r): the multigrid cycle applied to an FP64 multi-level vector
-    ohm_status precond(size_t ro, size_t zo)
+    // FP64 single-level problems run the cycle directly on the Krylov vectors
+    // (the cycle only reads r and only writes z); otherwise r is copied, in
+    // the cycle's precision, into its right-hand side first
+    bool cycle_aliases() const { return !P.T32 && nlev() == 1; }
+    // rhs_ready: the vector kernel that produced r already wrote that copy
+    ohm_status precond(size_t ro, size_t zo, bool rhs_ready = false)
     {
         const long long n = 3 * P.NBt * NC;
         const int L = nlev();
-        // FP64 single-level problems run the cycle directly on the Krylov
-        // vectors (the cycle only reads r and only writes z); otherwise copy
-        const bool alias = !P.T32 && L == 1;
+        const bool alias = cycle_aliases();
         if (alias) {
             rhs_b = (T *)at<double>(ro);
             e_b = (T *)at<double>(zo);
         } else {
             rhs_b = e_b = nullptr;
-            OHM_TRY(vconvert<double, T>(at<double>(ro), at<T>(P.rhs), n, st));
+            if (!rhs_ready) OHM_TRY(vconvert<double, T>(at<double>(ro), at<T>(P.rhs), n, st));
         }
         // AMR levels, finest first: smooth with zero coarse-fine ghosts,
         // restrict the level residual under the finer blocks, and take the
@@ -645,16 +648,20 @@ struct Solver {
     {
             // beta and rho were formed by the scalar update that closed the
             // previous iteration (or the restart)
+            // p and s also go straight into the cycle's right-hand side
+            const bool cp = !cycle_aliases();
+            float *c32 = cp && P.T32 ? (float *)at<T>(P.rhs) : nullptr;
+            double *c64 = cp && !P.T32 ? (double *)at<T>(P.rhs) : nullptr;
             OHM_TRY(vbicg_p((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.r),
-                            at<double>(P.v), at<double>(P.p), st));
-            OHM_TRY(precond(P.p, P.ph));
+                            at<double>(P.v), at<double>(P.p), st, c32, c64));
+            OHM_TRY(precond(P.p, P.ph, cp));
             {
                 const double *xs[1] = {at<double>(P.rhat)}, *ys[1] = {at<double>(P.v)};
                 OHM_TRY(apply_dots(P.ph, P.v, xs, ys, 1, 2));
             }
             OHM_TRY(vbicg_s((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.r),
-                            at<double>(P.v), at<double>(P.s), st));
-            OHM_TRY(precond(P.s, P.sh));
+                            at<double>(P.v), at<double>(P.s), st, c32, c64));
+            OHM_TRY(precond(P.s, P.sh, cp));
             {
                 const double *xs[2] = {at<double>(P.t), at<double>(P.t)},
                              *ys[2] = {at<double>(P.s), at<double>(P.t)};

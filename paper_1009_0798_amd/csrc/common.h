@@ -316,10 +316,14 @@ ohm_status vdot(int nblk, const int *prob_of, const int *active, long long cs, c
                 const double *const *y, int nq, double *part, hipStream_t s, double *copy = nullptr);
 ohm_status vnorms(int nblk, const int *prob_of, const int *active, long long cs, const double *x, double *part,
                   hipStream_t s);
+// p = r + beta (p - omega v) and s = r - alpha v per problem; c32 / c64, when
+// given, also receive the result in FP32 / FP64 (the multigrid cycle's input)
 ohm_status vbicg_p(int nblk, const int *prob_of, const int *active, long long cs, const double *scal,
-                   const double *r, const double *v, double *p, hipStream_t s);
+                   const double *r, const double *v, double *p, hipStream_t s, float *c32 = nullptr,
+                   double *c64 = nullptr);
 ohm_status vbicg_s(int nblk, const int *prob_of, const int *active, long long cs, const double *scal,
-                   const double *r, const double *v, double *sv, hipStream_t s);
+                   const double *r, const double *v, double *sv, hipStream_t s, float *c32 = nullptr,
+                   double *c64 = nullptr);
 ohm_status vbicg_xr(int nblk, const int *prob_of, const int *active, long long cs, const double *scal, double *x,
                     const double *ph, const double *sh, const double *sv, const double *t, double *r,
                     const double *rhat, double *part, hipStream_t s);

@@ -116,11 +116,20 @@ k_norms(int nblk, const int *__restrict__ prob_of, const int *__restrict__ activ
 // Scalars per problem (double[SC_N]):
 enum { SC_RHO = 0, SC_ALPHA, SC_OMEGA, SC_BETA, SC_RHONEW, SC_RR, SC_SS, SC_N = 16 };
 
+// the result of a vector update, and optionally a copy of it in the
+// multigrid cycle's precision (c32 or c64, same layout)
+__device__ __forceinline__ void put(double *out, float *c32, double *c64, long long gi, double val)
+{
+    out[gi] = val;
+    if (c32) c32[gi] = (float)val;
+    if (c64) c64[gi] = val;
+}
+
 // p = r + beta (p - omega v)
 __global__ void __launch_bounds__(256)
 k_bicg_p(int nblk, const int *__restrict__ prob_of, const int *__restrict__ active, long long cs,
          const double *__restrict__ scal, const double *__restrict__ r, const double *__restrict__ v,
-         double *__restrict__ p)
+         double *__restrict__ p, float *__restrict__ c32, double *__restrict__ c64)
 {
     const int b = xcd_block2(blockIdx.x, nblk);
     const int pr = prob_of[b];
@@ -129,13 +138,13 @@ k_bicg_p(int nblk, const int *__restrict__ prob_of, const int *__restrict__ acti
     if (beta == 0.0) {   // restart: p = r; p and v are not read (they hold no state yet)
         for (int t = threadIdx.x; t < 3 * NC; t += 256) {
             const long long gi = (t / NC) * cs + (long long)b * NC + t % NC;
-            p[gi] = r[gi];
+            put(p, c32, c64, gi, r[gi]);
         }
         return;
     }
     for (int t = threadIdx.x; t < 3 * NC; t += 256) {
         const long long gi = (t / NC) * cs + (long long)b * NC + t % NC;
-        p[gi] = r[gi] + beta * (p[gi] - omega * v[gi]);
+        put(p, c32, c64, gi, r[gi] + beta * (p[gi] - omega * v[gi]));
     }
 }
 
@@ -143,7 +152,7 @@ k_bicg_p(int nblk, const int *__restrict__ prob_of, const int *__restrict__ acti
 __global__ void __launch_bounds__(256)
 k_bicg_s(int nblk, const int *__restrict__ prob_of, const int *__restrict__ active, long long cs,
          const double *__restrict__ scal, const double *__restrict__ r, const double *__restrict__ v,
-         double *__restrict__ s)
+         double *__restrict__ s, float *__restrict__ c32, double *__restrict__ c64)
 {
     const int b = xcd_block2(blockIdx.x, nblk);
     const int pr = prob_of[b];
@@ -151,7 +160,7 @@ k_bicg_s(int nblk, const int *__restrict__ prob_of, const int *__restrict__ acti
     const double alpha = scal[SC_N * pr + SC_ALPHA];
     for (int t = threadIdx.x; t < 3 * NC; t += 256) {
         const long long gi = (t / NC) * cs + (long long)b * NC + t % NC;
-        s[gi] = r[gi] - alpha * v[gi];
+        put(s, c32, c64, gi, r[gi] - alpha * v[gi]);
     }
 }
 
@@ -346,16 +355,16 @@ ohm_status vdot(int nblk, const int *prob_of, const int *active, long long cs, c
 }
 
 ohm_status vbicg_p(int nblk, const int *prob_of, const int *active, long long cs, const double *scal, const double *r,
-                   const double *v, double *p, hipStream_t s)
+                   const double *v, double *p, hipStream_t s, float *c32, double *c64)
 {
-    k_bicg_p<<<nblk, 256, 0, s>>>(nblk, prob_of, active, cs, scal, r, v, p);
+    k_bicg_p<<<nblk, 256, 0, s>>>(nblk, prob_of, active, cs, scal, r, v, p, c32, c64);
     return check_launch("bicg p");
 }
 
 ohm_status vbicg_s(int nblk, const int *prob_of, const int *active, long long cs, const double *scal, const double *r,
-                   const double *v, double *sv, hipStream_t s)
+                   const double *v, double *sv, hipStream_t s, float *c32, double *c64)
 {
-    k_bicg_s<<<nblk, 256, 0, s>>>(nblk, prob_of, active, cs, scal, r, v, sv);
+    k_bicg_s<<<nblk, 256, 0, s>>>(nblk, prob_of, active, cs, scal, r, v, sv, c32, c64);
     return check_launch("bicg s");
 }
 
