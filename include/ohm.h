@@ -262,8 +262,11 @@ ohm_status ohm_cn_step(ohm_hier *h, void *const B[], const void *const eta[], co
  * of their children after each stage):
  *   B* = B - dt div F(B),   B <- B - dt/2 (div F(B) + div F(B*)).
  *   B[l], eta[l] : as for ohm_cn_step (FP64, device)
- *   dt     : host double[nprob], > 0.  Stability is the caller's: the scheme is
- *            stable for dt below about h^2 / (6 eta_max) on the finest level.
+ *   dt     : host double[nprob], > 0.  Stability is the caller's: with constant
+ *            eta the largest eigenvalue of the flux divergence is 8 eta / h^2
+ *            and the scheme is stable exactly for dt <= h^2 / (4 eta); with
+ *            variable eta keep dt below about h^2 / (4 eta_max) on the finest
+ *            level.
  *   workspace : device memory of at least ohm_explicit_workspace_size bytes,
  *            256-byte aligned (the same layout as the Crank-Nicolson workspace)
  * Asynchronous except for a final synchronisation of `stream`.  Returns

@@ -88,3 +88,27 @@ def test_paper_comparison_cn_agrees_with_explicit():
     eb = np.linalg.norm(Bb - Bx) / np.linalg.norm(Bx)
     print("lambda=1/2:", ec, "lambda=1:", eb)
     assert ec < 3e-3 and eb > 4 * ec
+
+
+def test_heun_stability_limit():
+    """The largest eigenvalue of eta M(k) is 8 eta / h^2 (at k = (0, pi/h, pi/h):
+    there the central differences vanish and M is diagonal with 8/h^2 on the
+    x component), and Heun's factor 1 - dt mu + (dt mu)^2 / 2 has modulus at
+    most 1 exactly while dt mu <= 2: the scheme is stable up to dt = h^2 / (4
+    eta) for constant eta.  The oracle's step on that mode, B_x = (-1)^(j+k),
+    keeps its amplitude at the limit and multiplies it by 1.22 at 1.1 times it."""
+    n, eta0 = 8, 0.5
+    h = 1.0 / n
+    k = np.linspace(0, np.pi / h, 17)
+    K = np.meshgrid(k, k, k, indexing="ij")
+    mu = np.linalg.eigvalsh(eta0 * closed.symbol(*K, h)).max()
+    assert abs(mu - 8 * eta0 / h ** 2) <= 1e-9 * mu
+    z, y, x = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
+    b = np.zeros((3, n, n, n))
+    b[0] = (-1.0) ** (y + z)
+    eta = np.full((n, n, n), eta0)
+    dt_max = h * h / (4 * eta0)
+    for f, factor in ((1.0, 1.0), (1.1, 1 - 2.2 + 2.2 ** 2 / 2)):
+        got = explicit.heun_steps(b, eta, h, f * dt_max, 1)
+        assert np.abs(got - factor * b).max() <= 1e-12, f
+    assert 1 - 2.2 + 2.2 ** 2 / 2 > 1.2
