@@ -172,3 +172,26 @@ def test_restrict_and_prolong_special_cases():
     ex = sum(w[a] * w[b] * w[g] * cc[k + g * sk, j + b * sj, i + a * si]
              for a in (0, 1) for b in (0, 1) for g in (0, 1))
     assert abs(fv - ex) < 1e-15
+
+
+@pytest.mark.parametrize("r", [3.3, 16.7, 262.0])
+def test_step_operator_is_bounded_below_by_one(r):
+    """The whole-step bound |B - B*| <= |R| / sigma_min(L) uses sigma_min(L) >= 1.
+    Constant eta: A = (L - I) / (lam dt) is symmetric positive semi-definite
+    (its symbol is PSD), so every eigenvalue of L is at least 1.  Variable eta
+    (3 decades): A is not symmetric and the symmetric part of A can be
+    indefinite, yet the smallest singular value of L stays at 1 for every
+    ratio eta_max dt / h^2 of the workloads."""
+    rng = np.random.default_rng(11)
+    shape, h = (4, 4, 6), 0.2
+    lam_dt = r * h * h
+    L = mg.assemble(np.full(shape, 1.0), h, lam_dt).toarray()
+    A = (L - np.eye(len(L))) / lam_dt
+    assert np.linalg.eigvalsh((A + A.T) / 2).min() >= -1e-10 * np.abs(A).max()
+    assert np.linalg.eigvalsh((L + L.T) / 2).min() >= 1 - 1e-9
+    eta = 10.0 ** rng.uniform(-3, 0, shape)
+    L = mg.assemble(eta, h, lam_dt).toarray()
+    A = (L - np.eye(len(L))) / lam_dt
+    assert np.linalg.eigvalsh((A + A.T) / 2).min() < -1e-3 * np.abs(A).max()
+    sv = np.linalg.svd(L, compute_uv=False)
+    assert sv.min() >= 1 - 1e-9, sv.min()
