@@ -16,7 +16,8 @@ from ._lib import CnOpts, CnStats, OhmError, OHM_F32, OHM_F64, check, dptr, host
 
 BLOCK = 8
 __all__ = ["Hierarchy", "ohm_fill_ghosts", "ohm_apply", "ohm_residual", "ohm_smooth", "ohm_restrict",
-           "ohm_prolong", "ohm_reflux", "ohm_cn_step", "default_opts", "OhmError", "to_blocks", "from_blocks"]
+           "ohm_prolong", "ohm_reflux", "ohm_cn_step", "ohm_explicit_step", "default_opts", "Workspace", "CnOpts",
+           "OhmError", "to_blocks", "from_blocks"]
 
 
 def _dtype_code(t) -> int:

@@ -13,7 +13,6 @@ from golden_values import paper
 def test_cn_step_matches_fft_closed_form():
     """Constant eta, periodic: the oracle's V-cycle-preconditioned BiCGStab
     solution equals the exact discrete step G(k) b (FFT), 16^3, r = 3.33."""
-    cfg = gen.config_fourier32()
     n = 16
     h = 1.0 / n
     B = gen.divfree(n, 1.0, seed=11)
@@ -23,7 +22,6 @@ def test_cn_step_matches_fft_closed_form():
     ex = closed.cn_exact(B, 1.0, h, dt)
     assert hist[-1] <= 1e-13
     assert np.linalg.norm(out - ex) <= 1e-12 * np.linalg.norm(ex)
-    del cfg
 
 
 def test_config_fourier32_closed_form():
