@@ -45,6 +45,7 @@ class Request:
     result: list | None = None
     stats: dict | None = None
     status: int = -1
+    error: str = ""
 
     @property
     def cells(self) -> int:
@@ -74,7 +75,6 @@ class Server:
                  rtol: float = 1e-10, **schedule):
         """``schedule``: further ``ohm_cn_opts`` fields (nu_pre, nu_post,
         nu_coarse, cycle, outer) applied to every batch."""
-        import torch
         self.budget = int(hbm_budget)
         self.free = int(hbm_budget)
         self.n_streams = n_streams
@@ -85,7 +85,7 @@ class Server:
         self.admitted: deque = deque()      # admitted, not started
         self.finished: list = []
         self.closed = False
-        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.streams = None             # one HIP stream per worker, made by serve()
         self.t0 = time.perf_counter()
         self.fp: dict = {}
 
@@ -94,13 +94,22 @@ class Server:
 
     # -- admission -------------------------------------------------------------
     def submit(self, req: Request):
+        # sizing builds a throwaway handle: done outside the lock so that
+        # workers are not held up; a request the library rejects (blocks
+        # outside the base grid, improper nesting ...) finishes with its status
+        try:
+            fp, err = footprint(req, self.opts), None
+        except _lib.OhmError as e:
+            fp, err = None, e
         with self.lock:
-            self.fp[req.rid] = footprint(req, self.opts)
-            if self.fp[req.rid] > self.budget:
-                req.status = _lib.OHM_ERR_NOMEM
+            if err is None and fp > self.budget:
+                err = _lib.OhmError(_lib.OHM_ERR_NOMEM, f"footprint {fp} B exceeds the budget {self.budget} B")
+            if err is not None:
+                req.status, req.error = err.status, str(err)
                 req.done = self.now()
                 self.finished.append(req)
                 return
+            self.fp[req.rid] = fp
             self.waiting.append(req)
             self._admit()
             self.lock.notify_all()
@@ -148,33 +157,35 @@ class Server:
             r.started = t_start
         with torch.cuda.stream(stream):
             h = Hierarchy([(r.base_blocks, r.dx0, r.levels) for r in batch], stream)
-            nlev = max(len(r.levels) for r in batch)
-            # the requests' fields are gathered into pinned host buffers and
-            # copied asynchronously on this worker's stream (pageable copies
-            # run at a fraction of the link's rate); results come back the
-            # same way and are handed out as views of the pinned buffers
-            B, E = [], []
-            for l in range(nlev):
-                bl = [r.B[l] for r in batch if l < len(r.levels)]
-                el = [r.eta[l] for r in batch if l < len(r.levels)]
-                hb = torch.empty((3, sum(b.shape[1] for b in bl)) + bl[0].shape[2:], dtype=torch.float64,
-                                 pin_memory=True)
-                torch.cat([torch.from_numpy(b) for b in bl], dim=1, out=hb)
-                he = torch.empty((sum(e.shape[0] for e in el),) + el[0].shape[1:], dtype=torch.float64,
-                                 pin_memory=True)
-                torch.cat([torch.from_numpy(e) for e in el], dim=0, out=he)
-                he = he[None]
-                B.append(hb.to("cuda", non_blocking=True))
-                E.append(he.to("cuda", non_blocking=True))
-            st, stats = ohm_cn_step(h, B, E, [r.dt for r in batch], self.opts, ws, stream=stream)
-            pinned_out = []
-            for b in B:
-                o = torch.empty(b.shape, dtype=b.dtype, pin_memory=True)
-                o.copy_(b, non_blocking=True)
-                pinned_out.append(o)
-            stream.synchronize()
-            outs = [o.numpy() for o in pinned_out]
-            h.close()
+            try:
+                # the requests' fields are gathered into pinned host buffers and
+                # copied asynchronously on this worker's stream (pageable copies
+                # run at a fraction of the link's rate); results come back the
+                # same way and are handed out as views of the pinned buffers
+                nlev = max(len(r.levels) for r in batch)
+                B, E = [], []
+                for l in range(nlev):
+                    bl = [r.B[l] for r in batch if l < len(r.levels)]
+                    el = [r.eta[l] for r in batch if l < len(r.levels)]
+                    hb = torch.empty((3, sum(b.shape[1] for b in bl)) + bl[0].shape[2:], dtype=torch.float64,
+                                     pin_memory=True)
+                    torch.cat([torch.from_numpy(b) for b in bl], dim=1, out=hb)
+                    he = torch.empty((sum(e.shape[0] for e in el),) + el[0].shape[1:], dtype=torch.float64,
+                                     pin_memory=True)
+                    torch.cat([torch.from_numpy(e) for e in el], dim=0, out=he)
+                    he = he[None]
+                    B.append(hb.to("cuda", non_blocking=True))
+                    E.append(he.to("cuda", non_blocking=True))
+                st, stats = ohm_cn_step(h, B, E, [r.dt for r in batch], self.opts, ws, stream=stream)
+                pinned_out = []
+                for b in B:
+                    o = torch.empty(b.shape, dtype=b.dtype, pin_memory=True)
+                    o.copy_(b, non_blocking=True)
+                    pinned_out.append(o)
+                stream.synchronize()
+                outs = [o.numpy() for o in pinned_out]
+            finally:
+                h.close()           # hipFree inside waits for the device
         off = [0] * nlev
         done = self.now()
         for i, r in enumerate(batch):
@@ -186,6 +197,9 @@ class Server:
             r.stats = stats[i]
             r.status = 0 if stats[i]["rel_res"] <= self.opts.rtol else _lib.OHM_ERR_NOCONV
             r.done = done
+
+    def _finish(self, batch):
+        """Return the batch's budget, record its requests, admit what now fits."""
         with self.lock:
             for r in batch:
                 self.free += self.fp[r.rid]
@@ -199,12 +213,24 @@ class Server:
             batch = self._take_batch()
             if batch is None:
                 return
-            self._run_batch(batch, self.streams[k], ws)
+            try:
+                self._run_batch(batch, self.streams[k], ws)
+            except Exception as e:
+                # a batch that raises ends each of its requests with the error;
+                # the worker and the batch's budget stay in service
+                now = self.now()
+                for r in batch:
+                    r.status = getattr(e, "status", _lib.OHM_ERR_HIP)
+                    r.error, r.result, r.stats, r.done = str(e), None, None, now
+            self._finish(batch)
             ws.buf = None       # release the workspace between batches
 
     def serve(self, requests, arrival_times):
         """Feed ``requests`` at ``arrival_times`` (seconds from now) and serve
         them; returns the finished requests."""
+        import torch
+        if self.streams is None:
+            self.streams = [torch.cuda.Stream() for _ in range(self.n_streams)]
         self.t0 = time.perf_counter()
         workers = [threading.Thread(target=self._worker, args=(k,), daemon=True) for k in range(self.n_streams)]
         for w in workers:
