@@ -26,5 +26,7 @@ closed   -- closed forms used as pins: the Fourier symbol of the discrete
 Parity status: every function is pinned by a test in tests/test_oracle_*.py,
 except the coarse-fine ghost interpolation rule itself (trilinear), which the
 paper does not specify: that choice is "parity unpinned" against the paper and
-pinned only by invariants (linear fields, conservation, uniform refinement).
+pinned by invariants (linear fields, conservation, uniform refinement) and by
+the second-order convergence in the cell width that the paper reports on its
+half-refined sinusoid test (Fig. 5).
 """

@@ -13,7 +13,8 @@ Composite operator (section 2.1 extended to the hierarchy):
  2. every level-l cell outside the level's blocks (a ghost) gets the
     cell-centred trilinear interpolant of level l-1 -- for B and for eta.
     The paper does not state its coarse-fine interpolation; this reading is
-    "parity unpinned" against the paper (pinned only by invariants);
+    "parity unpinned" against the paper (pinned by invariants and by the
+    paper's second-order convergence on its half-refined test, Fig. 5);
  3. face fluxes on each level by eqs. (4)-(6), (9)-(11);
  4. refluxing (section 4): on every coarse face next to a covered cell the
     coarse flux is the mean of the 4 fine fluxes on that face;
