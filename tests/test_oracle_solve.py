@@ -1,6 +1,6 @@
 """Pins of the oracle's Crank-Nicolson solve: the FFT closed form of the
 discrete step, a sparse direct solve, the paper's convergence orders (section
-3.1) and its printed amplitude."""
+3.1), its printed amplitude and its one-iteration residual (Fig. 6)."""
 import numpy as np
 import pytest
 
@@ -129,3 +129,36 @@ def test_spatial_order():
         errs.append(_sinusoid_error(n, dt, 4e-4, 0.5)[0])
     s = np.log(errs[0] / errs[-1]) / np.log(ns[-1] / ns[0])
     assert abs(s - paper("spatial_order")["value"]) <= 0.2, s
+
+
+def test_one_iteration_residual_fig6():
+    """Fig. 6 (section 3.1) on the unrefined sinusoid box: one iteration of
+    eqs. (16)-(18) from B^n, the multigrid step being FMG with Table 1's first
+    schedule (4 V-cycles, 4 + 4 sweeps), leaves max|R| below 1e-5 for
+    eta dt / h^2 from 0.1 to 16.4 (N = 8 and 16, dt = 4e-3 and 1e-4, both
+    lambda); lambda = 1/2 ends lower than lambda = 1, and a smaller
+    eta dt / h^2 lower than a larger one, as the paper observes."""
+    row = paper("table1_schedules")["value"]["FMG on AMR"]
+    bound = paper("one_iteration_max_residual")["value"]
+    r1 = {}
+    for N in (8, 16):
+        h = 1.0 / (4 * N)
+        nx, ny, nz = 4 * N, 2 * N, N
+        z, y, x = np.meshgrid((np.arange(nz) + 0.5) * h, (np.arange(ny) + 0.5) * h,
+                              (np.arange(nx) + 0.5) * h, indexing="ij")
+        B = np.zeros((3, nz, ny, nx))
+        B[2] = np.sin(2 * np.pi * x + 4 * np.pi * y)
+        eta = np.ones((nz, ny, nx))
+        for dt in (4e-3, 1e-4):
+            for lam in (0.5, 1.0):
+                S = ref.source(B, eta, h, dt, lam)
+                lv = mg.hierarchy(eta, h, lam * dt)
+                R0 = S - lv[0].L(B)
+                X = B + mg.fmg(lv, R0, n_v=row["v_cycles"], nu1=row["pre"], nu2=row["post"])
+                r1[N, dt, lam] = np.abs(S - lv[0].L(X)).max()
+                assert np.abs(R0).max() > 1e3 * bound
+                assert r1[N, dt, lam] < bound, (N, dt, lam, r1[N, dt, lam])
+    for N in (8, 16):
+        assert r1[N, 4e-3, 0.5] < r1[N, 4e-3, 1.0], r1
+        for lam in (0.5, 1.0):
+            assert r1[N, 1e-4, lam] < r1[N, 4e-3, lam], r1
