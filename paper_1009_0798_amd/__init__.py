@@ -178,6 +178,22 @@ class Workspace:
         return base + off, self.buf.numel() - off
 
 
+def _level_fields(h: Hierarchy, B, eta):
+    """The step entry points read one B and one eta pointer per level of the
+    handle: check the lists and tensors before their pointers are passed."""
+    import torch
+    if len(B) != h.nlevels or len(eta) != h.nlevels:
+        raise ValueError(f"B and eta need one tensor per level ({h.nlevels}); got {len(B)} and {len(eta)}")
+    for l, (b, e) in enumerate(zip(B, eta)):
+        nb = h.level_info(l)[0]
+        for name, t, n in (("B", b, 3 * nb * BLOCK ** 3), ("eta", e, nb * BLOCK ** 3)):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+                raise ValueError(f"{name}[{l}] must be a contiguous float64 GPU tensor of {n} elements; got "
+                                 f"{t.dtype}, {t.device}, contiguous={t.is_contiguous()}, {t.numel()} elements")
+    return ((ctypes.c_void_p * len(B))(*[b.data_ptr() for b in B]),
+            (ctypes.c_void_p * len(eta))(*[e.data_ptr() for e in eta]))
+
+
 def ohm_cn_step(h: Hierarchy, B, eta, dt, opts: CnOpts | None = None, workspace: Workspace | None = None,
                 stream=None):
     """One CN step in place on the per-level FP64 fields ``B`` (list) with
@@ -187,9 +203,8 @@ def ohm_cn_step(h: Hierarchy, B, eta, dt, opts: CnOpts | None = None, workspace:
     nb = ctypes.c_size_t()
     check(L.ohm_cn_workspace_size(h.h, ctypes.byref(opts), ctypes.byref(nb)))
     ws = workspace if workspace is not None else Workspace()
+    Bp, Ep = _level_fields(h, B, eta)
     ptr, size = ws.get(nb.value)
-    Bp = (ctypes.c_void_p * len(B))(*[b.data_ptr() for b in B])
-    Ep = (ctypes.c_void_p * len(eta))(*[e.data_ptr() for e in eta])
     stats = (CnStats * h.nprob)()
     st = L.ohm_cn_step(h.h, Bp, Ep, _coef(h, dt), ctypes.byref(opts), ctypes.c_void_p(ptr), size, stats,
                        stream_ptr(stream))
@@ -206,9 +221,8 @@ def ohm_explicit_step(h: Hierarchy, B, eta, dt, nsteps: int, workspace: Workspac
     nb = ctypes.c_size_t()
     check(L.ohm_explicit_workspace_size(h.h, ctypes.byref(nb)))
     ws = workspace if workspace is not None else Workspace()
+    Bp, Ep = _level_fields(h, B, eta)
     ptr, size = ws.get(nb.value)
-    Bp = (ctypes.c_void_p * len(B))(*[b.data_ptr() for b in B])
-    Ep = (ctypes.c_void_p * len(eta))(*[e.data_ptr() for e in eta])
     check(L.ohm_explicit_step(h.h, Bp, Ep, _coef(h, dt), int(nsteps), ctypes.c_void_p(ptr), size,
                               stream_ptr(stream)))
 

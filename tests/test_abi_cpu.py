@@ -141,3 +141,30 @@ def test_deep_levels_use_the_sparse_block_index():
     bb, bad = _slab_levels(7, shift_last=1)
     st, msg = _create([(bb, 1.0, bad)])
     assert st == 2 and "level 7" in msg and "not properly nested" in msg, msg
+
+
+def test_step_bindings_check_the_level_lists():
+    """The step entry points take one B and one eta pointer per level of the
+    handle; the binding refuses a list of the wrong length (the library would
+    read past it) and a tensor of the wrong type, place or size, before any
+    pointer is passed.  A stand-in handle (two levels of 5 and 3 blocks)
+    serves, so no device is needed."""
+    import torch
+    import paper_1009_0798_amd as ohm
+
+    class Handle:
+        nlevels = 2
+
+        def level_info(self, l):
+            return (5, 5 * 512, 0) if l == 0 else (3, 3 * 512, 0)
+
+    h = Handle()
+    B = [torch.zeros(3, 5, 8, 8, 8, dtype=torch.float64), torch.zeros(3, 3, 8, 8, 8, dtype=torch.float64)]
+    E = [torch.ones(1, 5, 8, 8, 8, dtype=torch.float64), torch.ones(1, 3, 8, 8, 8, dtype=torch.float64)]
+    with pytest.raises(ValueError, match="one tensor per level"):
+        ohm._level_fields(h, B[:1], E)
+    with pytest.raises(ValueError, match="one tensor per level"):
+        ohm._level_fields(h, B, E + E[:1])
+    # host tensors are refused (the library takes device pointers)
+    with pytest.raises(ValueError, match=r"B\[0\] must be a contiguous float64 GPU tensor of 7680"):
+        ohm._level_fields(h, B, E)
