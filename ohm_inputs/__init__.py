@@ -344,26 +344,6 @@ def config_batched(nprob=256, seed=6, sizes=(16, 24, 32, 48, 64), decades=2.0, m
     return out
 
 
-def trilinear_up(coarse):
-    """Cell-centred trilinear interpolation of a periodic (ncomp, z, y, x)
-    array to twice the resolution (used only to sample smooth inputs on fine
-    AMR levels cheaply)."""
-    c = coarse[None] if coarse.ndim == 3 else coarse
-    out = np.zeros((c.shape[0],) + tuple(2 * s for s in c.shape[1:]))
-    for oz in (0, 1):
-        for oy in (0, 1):
-            for ox in (0, 1):
-                acc = 0.0
-                for cz in (0, 1):
-                    for cy in (0, 1):
-                        for cx in (0, 1):
-                            w = (0.25 if cz else 0.75) * (0.25 if cy else 0.75) * (0.25 if cx else 0.75)
-                            sh = (-(2 * oz - 1) * cz, -(2 * oy - 1) * cy, -(2 * ox - 1) * cx)
-                            acc = acc + w * np.roll(c, shift=sh, axis=(1, 2, 3))
-                out[:, oz::2, oy::2, ox::2] = acc
-    return out[0] if coarse.ndim == 3 else out
-
-
 class FourierField:
     """A few random Fourier modes on the unit periodic box, evaluated at any
     points: B = sum_j a_j |k_j|^-p sin(2 pi k_j.x + phi_j) with polarisation a_j

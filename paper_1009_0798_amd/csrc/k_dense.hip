@@ -343,7 +343,12 @@ k_coarse_check(const CoarseJob *__restrict__ jobs, const int *__restrict__ force
 }
 
 // Gauss-Jordan inversion with partial pivoting, one 32x32 workgroup per job.
-// Step k only touches columns k .. n+k of the augmented matrix [A | I].
+// Without a row exchange, step k only meets columns k .. n+k of the augmented
+// matrix [A | I] (the identity entries of the rows below k lie further right
+// and are untouched).  A row exchange brings row p's identity entry, at column
+// n+p, into the pivot row, so from the first exchange on every step works on
+// all columns k .. 2n-1.  The pivot is read only after the exchange has been
+// written and a barrier has passed.
 __global__ void __launch_bounds__(1024)
 k_coarse_invert(const CoarseJob *__restrict__ jobs, const int *__restrict__ flags, double *__restrict__ aug,
                 double *__restrict__ inv)
@@ -356,7 +361,8 @@ k_coarse_invert(const CoarseJob *__restrict__ jobs, const int *__restrict__ flag
     __shared__ double sval[1024];
     __shared__ int sidx[1024];
     __shared__ double sfac[COARSE_MAX_DEV];
-    __shared__ double srow[COARSE_MAX_DEV + 1];
+    __shared__ double srow[2 * COARSE_MAX_DEV];
+    bool swapped = false;   // uniform over the workgroup: every thread reads the same sidx[0]
     for (int k = 0; k < n; ++k) {
         double best = -1.0;
         int bi = k;
@@ -379,22 +385,29 @@ k_coarse_invert(const CoarseJob *__restrict__ jobs, const int *__restrict__ flag
             __syncthreads();
         }
         const int p = sidx[0];
-        // swap rows k and p over the live columns, scale the pivot row
-        const double d = 1.0 / A[p * w + k];
-        for (int cc = tid; cc <= n; cc += 1024) {
-            const int c = k + cc;
-            const double vk = A[k * w + c], vp = A[p * w + c];
-            srow[cc] = vp * d;
-            if (p != k) A[p * w + c] = vk;
+        swapped = swapped || p != k;
+        // live columns k .. k + ncol - 1
+        const int ncol = swapped ? w - k : n + 1;
+        if (p != k) {
+            for (int cc = tid; cc < ncol; cc += 1024) {
+                const int c = k + cc;
+                const double vk = A[k * w + c], vp = A[p * w + c];
+                A[k * w + c] = vp;
+                A[p * w + c] = vk;
+            }
         }
         __syncthreads();
-        for (int cc = tid; cc <= n; cc += 1024) A[k * w + k + cc] = srow[cc];
+        // scale the pivot row into LDS, then write it back; the multipliers of
+        // the other rows are read in the same phase (column k only)
+        const double d = 1.0 / A[k * w + k];
+        for (int cc = tid; cc < ncol; cc += 1024) srow[cc] = A[k * w + k + cc] * d;
         for (int r = tid; r < n; r += 1024) sfac[r] = (r == k) ? 0.0 : A[r * w + k];
         __syncthreads();
+        for (int cc = tid; cc < ncol; cc += 1024) A[k * w + k + cc] = srow[cc];
         for (int r = ty; r < n; r += 32) {
             const double f = sfac[r];
             if (f == 0.0) continue;
-            for (int cc = tx; cc <= n; cc += 32) A[r * w + k + cc] -= f * srow[cc];
+            for (int cc = tx; cc < ncol; cc += 32) A[r * w + k + cc] -= f * srow[cc];
         }
         __syncthreads();
     }
@@ -687,8 +700,11 @@ ohm_status ensure_coarse_storage(ohm_hier *h)
     coarse_sizes(h, &inv_elems, &aug_elems);
     if (inv_elems == 0 || h->d_coarse_inv) return OHM_OK;
     OHM_HIP(hipMalloc((void **)&h->d_coarse_inv, sizeof(double) * inv_elems));
-    // saved resistivity: one cells-sized slot at inv_off / n3 per job
-    OHM_HIP(hipMalloc((void **)&h->d_coarse_eta, sizeof(double) * inv_elems));
+    // saved resistivity: one slot of the coarsest grid's cells per job, at
+    // the job's eta_off
+    size_t eta_elems = 0;
+    for (const CoarseJob &J : coarse_jobs(h, nullptr, 0)) eta_elems += (size_t)(J.n3 / 3);
+    OHM_HIP(hipMalloc((void **)&h->d_coarse_eta, sizeof(double) * eta_elems));
     OHM_HIP(hipMalloc((void **)&h->d_coarse_flags, sizeof(int) * (size_t)h->nprob));
     return OHM_OK;
 }

@@ -319,6 +319,10 @@ def test_batched_equals_alone(ordering):
         o += nb
         assert stats1[0]["iters"] == stats[i]["iters"]
         assert np.array_equal(mine, alone), i
+        # and each batched answer is the oracle's (whole-step bound)
+        ex, _ = mg.cn_step(Bs[i], Es[i], s.dx0, dts[i], rtol=1e-13)
+        S = ref.source(Bs[i], Es[i], s.dx0, dts[i])
+        assert np.linalg.norm(mine - ex) <= _bound(np.linalg.norm(S), ex), i
 
 
 def test_noconv_reports_and_keeps_last_iterate():
@@ -440,3 +444,56 @@ def test_degenerate_inputs():
     for ordering in (0, 1):
         ohm.ohm_smooth(H, 0, Bt, St, Et, 0.5 * dt, 0, torch.empty_like(Bt), ordering=ordering)
         assert torch.equal(Bt, before)
+
+
+def _row_exchanges(A):
+    """Row exchanges that Gauss-Jordan elimination with partial pivoting makes
+    on A (a strictly larger entry below the diagonal is taken as pivot)."""
+    A = A.copy()
+    n, cnt = A.shape[0], 0
+    for k in range(n):
+        p = k + int(np.argmax(np.abs(A[k:, k])))
+        if abs(A[p, k]) > abs(A[k, k]):
+            cnt += 1
+            A[[k, p]] = A[[p, k]]
+        A[k] /= A[k, k]
+        for r in range(n):
+            if r != k:
+                A[r] -= A[r, k] * A[k]
+    return cnt
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_coarsest_solve_with_row_exchanges(precision):
+    """The dense coarsest solve pivots.  A 16^3 box whose resistivity is
+    constant on 4^3-cell cubes, with values spread over 4 decades, gives the
+    4^3 coarsest grid exactly those values (means of equal children); at
+    eta dt / h^2 = 100 on that grid its operator needs row exchanges (checked
+    here on the oracle's assembled matrix).  One iteration of eqs. (16)-(18)
+    with V(2, 2) must equal the oracle's cycle, whose coarsest solve is an
+    exact inverse."""
+    import paper_1009_0798_amd as ohm
+    announce(f"cn coarsest solve with row exchanges precision={precision}")
+    n = 16
+    spec = gen.uniform_spec(n)
+    h = spec.dx0
+    rng = np.random.default_rng(2024)
+    ec = 10.0 ** rng.uniform(-4.0, 0.0, (4, 4, 4))
+    eta = np.repeat(np.repeat(np.repeat(ec, 4, axis=0), 4, axis=1), 4, axis=2)
+    hc = 4 * h
+    lam_dt = 100.0 * hc * hc / ec.max()
+    dt = 2.0 * lam_dt
+    levels = mg.hierarchy(eta, h, lam_dt)
+    assert [lv.eta.shape[0] for lv in levels] == [16, 8, 4]
+    assert np.allclose(levels[-1].eta, ec, rtol=1e-14, atol=0)
+    assert _row_exchanges(mg.assemble(levels[-1].eta, hc, lam_dt).toarray()) > 0
+    B = gen.divfree(n, 2.0, seed=2025)
+    st, stats, got = _gpu_step(spec, B, eta, dt, precision=precision, outer=0, cycle=0, n_vcycles=1,
+                               nu_pre=2, nu_post=2, nu_coarse=0, max_iters=1, rtol=1e-14)
+    assert st == ohm._lib.OHM_ERR_NOCONV and stats[0]["iters"] == 1
+    S = ref.source(B, eta, h, dt)
+    R0 = ref.residual(B, S, eta, h, lam_dt)
+    e = mg.vcycle(levels, R0, 2, 2)
+    err = np.abs(got - (B + e)).max() / np.abs(e).max()
+    print("stats", stats, "max err / max correction", err)
+    assert err <= (1e-11 if precision == 0 else 2e-5)

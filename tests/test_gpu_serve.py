@@ -52,6 +52,55 @@ def test_served_equals_alone(precision):
         assert st == 0
         for l in range(len(r.levels)):
             assert np.array_equal(alone[l], r.result[l]), (r.rid, l)
+        rel = _oracle_rel_residual(r)
+        print(r.rid, "oracle rel. residual", rel, "library", r.stats["rel_res"])
+        assert rel <= 1.01e-10
+
+
+def _oracle_rel_residual(r):
+    """|S - L B|_2 / |S|_2 of a served result by the oracle's composite
+    operator (leaf cells of every level; S from the request's input)."""
+    from oracle import amr
+    spec = gen.HierSpec(tuple(r.base_blocks), r.dx0, list(r.levels))
+    C = amr.Composite(spec)
+    L = spec.nlevels
+    b = [C.to_dense(l, r.B[l]) for l in range(L)]
+    e = [C.to_dense(l, r.eta[l]) for l in range(L)]
+    got = [C.to_dense(l, np.asarray(r.result[l])) for l in range(L)]
+    S = C.source(b, e, r.dt)
+    R = C.residual(got, S, e, 0.5 * r.dt)
+    return float(np.linalg.norm(C.pack(R)) / np.linalg.norm(C.pack(S)))
+
+
+def _pool_request(n0, L, seed):
+    """A request of the serving workload's recipe (1-3 levels, each finer level
+    one compact patch of about 1/8 of its parent, eta up to 4 decades, dt
+    10-100x the finest explicit limit) at a given base size."""
+    from paper_1009_0798_amd.serve import Request
+    rng = np.random.default_rng(seed)
+    d = gen.amr_request(rng, n0, L, float(rng.uniform(2, 4)), float(np.exp(rng.uniform(np.log(10), np.log(100)))))
+    s = d["spec"]
+    assert s.nlevels == L
+    return Request(rid=0, arrival=0.0, base_blocks=s.base_blocks, dx0=s.dx0, levels=s.levels, B=d["B"],
+                   eta=d["eta"], dt=d["dt"])
+
+
+@pytest.mark.parametrize("n0,L", [(192, 1), (184, 2), (96, 3)])
+def test_served_full_size_against_oracle(n0, L):
+    """Full-size requests of the serving workload (base up to 192^3, 1-3
+    levels), served in mixed precision: the oracle's composite residual of each
+    served answer meets the tolerance (a property that holds at any size; the
+    oracle's composite operator holds every level as a dense box, so the
+    three-level case uses a 96^3 base, whose finest level is 384^3)."""
+    from paper_1009_0798_amd.serve import Server
+    announce(f"serve: full-size request base {n0}^3, {L} levels")
+    r = _pool_request(n0, L, seed=700 + n0 + L)
+    srv = Server(hbm_budget=64 << 30, n_streams=1, max_batch=1, precision=1)
+    done = srv.serve([r], [0.0])
+    assert done[0].status == 0, done[0].error
+    rel = _oracle_rel_residual(done[0])
+    print("oracle rel. residual", rel, "library", done[0].stats)
+    assert rel <= 1.01e-10
 
 
 def test_admission_by_footprint():
