@@ -149,6 +149,27 @@ ohm_status ohm_residual(ohm_hier *h, int32_t level, const void *B, const void *B
                         hipStream_t stream);
 
 /*
+ * ohm_residual for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops and harnesses that forbid hipMalloc): the same
+ * residual R (when R is not NULL) and the same norms, with every scratch
+ * buffer in one static device array of 4 MiB per device, which the library
+ * holds until the process ends.  Differences from ohm_residual:
+ *   norms  : DEVICE double[nprob][3][2] (sum R_c^2, max |R_c|), written
+ *            asynchronously on `stream`; the call never synchronises;
+ *   lam_dt : host double[nprob], copied to the device before the call returns.
+ * Returns OHM_ERR_NOMEM, before any launch, when the level needs more scratch
+ * than the array holds: 48 bytes per block of `level` plus about 72 bytes per
+ * problem with norms (about 87,000 blocks, 4.4e7 cells, for one problem).
+ * Calls on one device share the array and keep the last call's contents:
+ * calls that overlap on one device (several streams or host threads) race.
+ * Nothing in the array needs to start at zero.
+ */
+ohm_status ohm_residual_noalloc(ohm_hier *h, int32_t level, const void *B, const void *B_ghost,
+                                const void *S, const void *eta, const void *eta_ghost,
+                                const double *lam_dt, void *R, double *norms, ohm_dtype dtype,
+                                hipStream_t stream);
+
+/*
  * Red-black smoother, eq. (19) with alpha of eqs. (21)-(23): `nsweeps` sweeps,
  * each a red half-sweep ((i+j+k) even in level-global cell indices) then a
  * black one.  All cells of a colour update together from the state at the

@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import CnOpts, CnStats, OhmError, OHM_F32, OHM_F64, check, dptr, host_doubles, lib, stream_ptr
 
 BLOCK = 8
-__all__ = ["Hierarchy", "ohm_fill_ghosts", "ohm_apply", "ohm_residual", "ohm_smooth", "ohm_restrict",
+__all__ = ["Hierarchy", "ohm_fill_ghosts", "ohm_apply", "ohm_residual", "ohm_residual_noalloc", "ohm_smooth", "ohm_restrict",
            "ohm_prolong", "ohm_reflux", "ohm_cn_step", "ohm_explicit_step", "default_opts", "Workspace", "CnOpts",
            "OhmError", "to_blocks", "from_blocks"]
 
@@ -123,6 +123,20 @@ def ohm_residual(h: Hierarchy, level, B, S, eta, lam_dt, R=None, B_ghost=None, e
     if norms:
         return np.array(nrm[:]).reshape(h.nprob, 3, 2)
     return None
+
+
+def ohm_residual_noalloc(h: Hierarchy, level, B, S, eta, lam_dt, R=None, norms=None, B_ghost=None, eta_ghost=None,
+                         stream=None):
+    """``ohm_residual`` with its scratch in the library's static device array:
+    ``norms`` (optional) is a float64 GPU tensor of nprob * 6 elements that
+    receives (sum R^2, max |R|) per problem and component without a
+    synchronisation."""
+    if norms is not None:
+        import torch
+        if norms.dtype != torch.float64 or not norms.is_cuda or not norms.is_contiguous() or norms.numel() < 6 * h.nprob:
+            raise ValueError(f"norms must be a contiguous float64 GPU tensor of at least {6 * h.nprob} elements")
+    check(lib().ohm_residual_noalloc(h.h, level, dptr(B), dptr(B_ghost), dptr(S), dptr(eta), dptr(eta_ghost),
+                                     _coef(h, lam_dt), dptr(R), dptr(norms), _dtype_code(B), stream_ptr(stream)))
 
 
 def ohm_smooth(h: Hierarchy, level, B, S, eta, lam_dt, nsweeps, tmp, B_ghost=None, eta_ghost=None, stream=None,

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "OHM_OK", 1: "OHM_ERR_ARG", 2: "OHM_ERR_LAYOUT", 3: "OHM_ERR_
 EXPORTS = ["ohm_hier_create", "ohm_hier_destroy", "ohm_hier_level_info", "ohm_hier_problem_info",
            "ohm_last_error", "ohm_fill_ghosts", "ohm_apply", "ohm_residual", "ohm_smooth", "ohm_restrict",
            "ohm_prolong", "ohm_reflux", "ohm_cn_default_opts", "ohm_cn_workspace_size", "ohm_cn_step",
-           "ohm_explicit_workspace_size", "ohm_explicit_step"]
+           "ohm_explicit_workspace_size", "ohm_explicit_step", "ohm_residual_noalloc"]
 
 
 class ProblemDesc(ctypes.Structure):
@@ -75,6 +75,7 @@ def lib() -> ctypes.CDLL:
             "ohm_fill_ghosts": [P, I32, P, P, I32, I32, P],
             "ohm_apply": [P, I32, P, P, P, P, DP, P, I32, P],
             "ohm_residual": [P, I32, P, P, P, P, P, DP, P, DP, I32, P],
+            "ohm_residual_noalloc": [P, I32, P, P, P, P, P, DP, P, P, I32, P],
             "ohm_smooth": [P, I32, P, P, P, P, P, DP, I32, I32, P, I32, P],
             "ohm_restrict": [P, I32, P, P, I32, I32, P],
             "ohm_prolong": [P, I32, P, P, I32, I32, I32, P],
