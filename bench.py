@@ -28,70 +28,95 @@ AMR_SCHEDULE = (4, 4)
 SERVE_SCHEDULE = (2, 2, 0)   # (pre, post, below the base grid; 0 = as the base grid) for serving
 
 
-def sweep_source_hash() -> str:
-    """Hash of the fused-sweep kernel source (the block kernel, the tile body
-    and the stencil it uses); the counter traffic recorded under profiles/ is
-    valid only for that source."""
+def kernel_source_hash() -> str:
+    """Hash of the sources of the block-level stencil kernels (the block
+    kernels, the sweep body and the stencil they use); the counter traffic
+    recorded under profiles/ is valid only for that source."""
     import hashlib
     csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1009_0798_amd", "csrc")
-    src = open(os.path.join(csrc, "k_block.hip")).read()
-    a = src.index("k_blk_sweep(")
-    a = src.rindex("template <typename T", 0, a)
-    b = src.index("\n}\n", a) + 3
-    body = src[a:b] + "".join(open(os.path.join(csrc, f)).read() for f in ("sweep.h", "stencil.h"))
+    body = "".join(open(os.path.join(csrc, f)).read() for f in ("k_block.hip", "sweep.h", "stencil.h"))
     return hashlib.sha256(body.encode()).hexdigest()[:16]
 
 
-def counter_traffic(tag: str):
-    """HBM bytes per launch from the committed counter runs (FETCH_SIZE and
-    WRITE_SIZE, calibrated on a 256 MiB device copy), or None if the kernel
-    changed since they were taken."""
+# kernels whose HBM traffic --record-counters extracts from the counter runs of
+# --roofline-only: tag -> (kernel name prefix, algorithmic bytes per cell,
+# dispatches to average: the first k of that name, or all when None)
+COUNTED = {
+    "sweep_f64": ("k_blk_sweep<double, 0, false>", 80, 12),
+    "sweep_f32": ("k_blk_sweep<float, 0, false>", 40, 12),
+    "apply_f64": ("k_blk_stencil<double, 0>", 56, 12),
+    "resid_f64": ("k_blk_stencil<double, 1>", 80, 12),
+    "resid_restrict_f64": ("k_blk_stencil<double, 3>", 59, None),
+}
+
+
+def counter_traffic(tag: str, n: int):
+    """HBM bytes per launch of kernel `tag` on the n^3 level-0 blocks from the
+    committed counter runs (FETCH_SIZE and WRITE_SIZE, calibrated on a 256 MiB
+    device copy), or None if none were taken at that size or the kernel
+    source changed since."""
     root = os.path.dirname(os.path.abspath(__file__))
     try:
         with open(os.path.join(root, "profiles", "roofline_counters.json")) as f:
-            rec = json.load(f)["kernels"][tag]
+            rec = json.load(f)["kernels"][f"{tag}@{n}"]
     except (OSError, KeyError, ValueError):
         return None
-    return rec["hbm_bytes"] if rec["source_sha256_16"] == sweep_source_hash() else None
+    return rec["hbm_bytes"] if rec["source_sha256_16"] == kernel_source_hash() else None
 
 
-def record_counters(fetch_dir: str, write_dir: str) -> dict:
-    """Write profiles/roofline_counters.json from the two rocprofv3 --pmc runs
-    of `bench.py --roofline-only` (FETCH_SIZE, then WRITE_SIZE): the 256 MiB
-    device copy calibrates each counter, the sweep dispatches are averaged."""
+def record_counters(fetch_dir: str, write_dir: str, n: int) -> dict:
+    """Add to profiles/roofline_counters.json the per-launch traffic of the
+    COUNTED kernels at n^3 from the two rocprofv3 --pmc runs of
+    `bench.py --roofline-only --n n` (FETCH_SIZE, then WRITE_SIZE): the
+    256 MiB device copy calibrates each counter."""
     import csv
     import glob
     root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "roofline_counters.json")
 
     def per_kernel(d, counter):
-        vals = {}
+        rows = []
         for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
             for r in csv.DictReader(open(f)):
                 if r["Counter_Name"] == counter:
-                    vals.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
-        return vals
+                    rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+        rows.sort()
+        return rows
 
     copy_kib = 256 * 1024
-    out = {"calibration": {"copy_KiB": copy_kib}, "kernels": {}}
-    res = {}
+    try:
+        out = json.load(open(path))
+        out["kernels"] = {k: v for k, v in out.get("kernels", {}).items() if "@" in k}
+    except (OSError, ValueError):
+        out = {"kernels": {}}
+    cal, res = {"copy_KiB": copy_kib}, {}
     for tag, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
-        vals = per_kernel(d, counter)
-        cal = max(v for k, vs in vals.items() if "copyBuffer" in k for v in vs)
-        out["calibration"][f"{tag}_read_KiB"] = cal
-        out["calibration"][f"{tag}_factor"] = copy_kib / cal
-        res[tag] = (vals, copy_kib / cal)
-    for prec, tname in (("f64", "double"), ("f32", "float")):
-        rec = {"kernel": f"k_blk_sweep<{tname}>", "source_sha256_16": sweep_source_hash()}
+        rows = per_kernel(d, counter)
+        c = max(v for _, k, v in rows if "copyBuffer" in k)
+        cal[f"{tag}_read_KiB"] = c
+        cal[f"{tag}_factor"] = copy_kib / c
+        res[tag] = (rows, copy_kib / c)
+    out["calibration"] = cal
+    cells = n ** 3
+    for name, (prefix, bpc, first) in COUNTED.items():
+        rec = {"kernel": prefix, "cells": cells, "source_sha256_16": kernel_source_hash(),
+               "algorithmic_bytes": bpc * cells}
         tot = 0.0
         for tag in ("fetch", "write"):
-            vals, factor = res[tag]
-            xs = [v for k, vs in vals.items() if f"k_blk_sweep<{tname}" in k for v in vs]
+            rows, factor = res[tag]
+            xs = [v for _, k, v in rows if prefix in k]
+            if first:
+                xs = xs[:first]
+            if not xs:
+                break
             rec[f"{tag}_KiB"] = sum(xs) / len(xs)
             rec["dispatches"] = len(xs)
             tot += rec[f"{tag}_KiB"] * factor * 1024
-        rec["hbm_bytes"] = tot
-        out["kernels"][prec] = rec
-    with open(os.path.join(root, "profiles", "roofline_counters.json"), "w") as f:
+        else:
+            rec["hbm_bytes"] = tot
+            rec["ratio"] = tot / rec["algorithmic_bytes"]
+            out["kernels"][f"{name}@{n}"] = rec
+    with open(path, "w") as f:
         json.dump(out, f, indent=1)
     return out
 
@@ -136,13 +161,33 @@ def smoother_rate(ohm, H, B, S, E, lam_dt, dtype, nsweeps=10):
     return ev0.elapsed_time(ev1) / 1e3 / nsweeps
 
 
-def cpu_baseline(cfg, n_sample, min_seconds=10.0):
-    """The oracle (FP64, V(2,2)-preconditioned BiCGStab to 1e-10) on consecutive
-    CN steps of the same workload family at n_sample^3 (r = eta_max dt / h^2 =
-    16.7), as many as fit in about min_seconds (at least one)."""
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_steps(n_sample, min_seconds):
+    """Consecutive CN steps of the oracle (FP64, V(2,2)-preconditioned
+    BiCGStab to 1e-10) on the n_sample^3 log-normal workload (4 decades,
+    dt = 100x explicit), as many as fit in about min_seconds (at least one).
+    Returns (cells/s, steps, iterations, seconds, threads)."""
     import ohm_inputs as gen
     from oracle import mg, ref
-    c = cfg if n_sample == 128 else gen.config_lognormal128(n_sample)
+    c = gen.config_lognormal128(n_sample)
     B = c["B"]
     steps = iters = 0
     t0 = time.perf_counter()
@@ -153,9 +198,33 @@ def cpu_baseline(cfg, n_sample, min_seconds=10.0):
         t = time.perf_counter() - t0
         if t >= min_seconds or t * (steps + 1) / steps > 3 * min_seconds:
             break
-    return {"value": steps * n_sample ** 3 / t, "unit": "cells/s", "cores": ref.threads(), "kind": "oracle",
+    return steps * n_sample ** 3 / t, steps, iters, t, ref.threads()
+
+
+def cpu_baseline(n_sample, min_seconds=8.0, repeats=3, n_single=32):
+    """The oracle timed on the host: the median of `repeats` runs with every
+    host thread on the n_sample^3 sample, and one run limited to one thread
+    (OpenMP and BLAS) on the n_single^3 sample."""
+    from threadpoolctl import threadpool_limits
+    from oracle import ref
+    runs = [oracle_steps(n_sample, min_seconds) for _ in range(repeats)]
+    runs.sort(key=lambda r: r[0])
+    v, steps, iters, t, thr = runs[len(runs) // 2]
+    nthr = ref.threads()
+    ref.set_threads(1)
+    try:
+        with threadpool_limits(limits=1):
+            single = oracle_steps(n_single, min_seconds)
+    finally:
+        ref.set_threads(nthr)
+    return {"value": v, "unit": "cells/s", "cores": thr, "kind": "oracle",
             "sample": f"{steps} consecutive CN steps of the {n_sample}^3 log-normal workload (eta 4 decades, dt 100x "
-                      f"explicit), FP64 V(2,2)-BiCGStab to 1e-10, {iters} iterations, {t:.1f} s"}
+                      f"explicit), FP64 V(2,2)-BiCGStab to 1e-10, {iters} iterations, {t:.1f} s; median of "
+                      f"{repeats} runs",
+            "runs_cells_per_s": [r[0] for r in runs], "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "single_thread": {"value": single[0], "unit": "cells/s", "cores": single[4],
+                              "sample": f"{single[1]} consecutive CN steps of the {n_single}^3 log-normal workload, "
+                                        f"{single[2]} iterations, {single[3]:.1f} s"}}
 
 
 def bench_batched(args):
@@ -319,9 +388,56 @@ def bench_e8(args):
             "speedup_to_solution_vs_explicit": t_exp / out["implicit_lambda_0.5"]["seconds"]}
 
 
+def stencil_rate(ohm, H, B, S, E, coef, kind, nlaunch=10):
+    """Average duration of one launch of the level-0 operator apply
+    (out = B + coef div F(B)) or residual (R = S - L B, no norms), measured
+    with HIP events on the stream the library launches on."""
+    import torch
+    out = torch.empty_like(B)
+
+    def once():
+        if kind == "apply":
+            ohm.ohm_apply(H, 0, B, E, coef, out)
+        else:
+            ohm.ohm_residual(H, 0, B, S, E, coef, R=out)
+
+    once()
+    once()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(nlaunch):
+        once()
+    ev1.record()
+    torch.cuda.synchronize()
+    return ev0.elapsed_time(ev1) / 1e3 / nlaunch
+
+
+def random_level(n, seed=11):
+    """Hierarchy and resident level-0 fields of an n^3 periodic box filled on
+    the device with seeded random values (B, S standard normal, eta
+    log-uniform over 4 decades): the stencil kernels' timing does not depend on
+    the values."""
+    import torch
+    import ohm_inputs as gen
+    import paper_1009_0798_amd as ohm
+    spec = gen.uniform_spec(n)
+    H = ohm.Hierarchy([(spec.base_blocks, spec.dx0, spec.levels)])
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    nb = len(spec.levels[0])
+    B = torch.randn((3, nb, 8, 8, 8), dtype=torch.float64, device="cuda", generator=g)
+    S = torch.randn((3, nb, 8, 8, 8), dtype=torch.float64, device="cuda", generator=g)
+    E = 10.0 ** (-4.0 * torch.rand((1, nb, 8, 8, 8), dtype=torch.float64, device="cuda", generator=g))
+    return spec, H, B, S, E, gen.explicit_dt(spec.dx0, 1.0, 100.0)
+
+
 def roofline_probe(args):
-    """A plain device copy of 256 MiB (calibrates the HBM byte counters) and
-    ten smoother launches on the level-0 blocks of the 128^3 workload."""
+    """For the counter runs: a plain device copy of 256 MiB (calibrates the
+    HBM byte counters), then on the level-0 blocks of the n^3 log-normal
+    workload 12 launches each of the FP64 and FP32 fused sweeps, the FP64
+    operator apply and the FP64 residual, then one FP64 CN step (its residual
+    with restriction to the first coarse level)."""
     import torch
     import ohm_inputs as gen
     import paper_1009_0798_amd as ohm
@@ -336,9 +452,17 @@ def roofline_probe(args):
     B0 = ohm.to_blocks(torch.from_numpy(cfg["B"]), ijk).cuda()
     E = ohm.to_blocks(torch.from_numpy(cfg["eta"])[None], ijk).cuda()
     S = torch.randn_like(B0)
+    lam_dt = 0.5 * cfg["dt"]
     for dt in (torch.float64, torch.float32):
-        t = smoother_rate(ohm, H, B0, S, E, 0.5 * cfg["dt"], dt, nsweeps=10)
+        t = smoother_rate(ohm, H, B0, S, E, lam_dt, dt, nsweeps=10)
         _log(f"smoother {dt}: {t * 1e6:.2f} us per launch")
+    for kind in ("apply", "resid"):
+        t = stencil_rate(ohm, H, B0, S, E, lam_dt, kind)
+        _log(f"{kind} float64: {t * 1e6:.2f} us per launch")
+    opts = ohm.default_opts(rtol=1e-10, max_iters=200, nu_pre=SCHEDULE[0][0], nu_post=SCHEDULE[0][1],
+                            nu_coarse=NU_COARSE)
+    st, stats = ohm.ohm_cn_step(H, [B0.clone()], [E], cfg["dt"], opts)
+    _log(f"cn step: status {st}, {stats[0]['iters']} iterations")
     torch.cuda.synchronize()
 
 
@@ -349,6 +473,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--cpu-sample", type=int, default=64, help="grid edge of the oracle sample (0: skip)")
+    ap.add_argument("--hbm-n", type=int, default=256,
+                    help="grid edge of the second roofline leg, a working set above the last-level cache (0: skip)")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--workload", default="lognormal128", choices=["lognormal128", "batched", "serve", "amr", "e8"])
     ap.add_argument("--nu", type=int, default=None, help="pre and post sweeps of the AMR workload's cycle")
@@ -360,9 +486,10 @@ def main():
     ap.add_argument("--max-batch", type=int, default=8)
     ap.add_argument("--hbm-gb", type=float, default=64.0)
     ap.add_argument("--record-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
-                    help="write profiles/roofline_counters.json from two rocprofv3 --pmc runs of --roofline-only")
+                    help="add to profiles/roofline_counters.json the kernels' traffic at --n from two rocprofv3 --pmc "
+                         "runs of --roofline-only --n")
     ap.add_argument("--roofline-only", action="store_true",
-                    help="run only a known-size copy and the level-0 smoother launches (for counter runs)")
+                    help="run only a known-size copy and the level-0 stencil kernels at --n (for counter runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path",
@@ -373,7 +500,7 @@ def main():
     import paper_1009_0798_amd as ohm
 
     if args.record_counters:
-        print(json.dumps(record_counters(*args.record_counters), indent=1))
+        print(json.dumps(record_counters(*args.record_counters, args.n), indent=1))
         return
     if args.roofline_only:
         roofline_probe(args)
@@ -410,7 +537,10 @@ def main():
 
     f64 = res["f64"]
     value = cells * args.steps / f64["t"]
-    # roofline of the dominant kernel: red-black half-sweep on the level-0 blocks
+    # roofline of the dominant kernel, the fused red-black sweep on the
+    # level-0 blocks: on the workload itself, whose 168 MB sweep working set
+    # fits the 256 MB last-level cache, and on a 256^3 level (1.34 GB) that
+    # streams from HBM
     S = torch.randn_like(B0)
     lam_dt = 0.5 * cfg["dt"]
     t_sw = smoother_rate(ohm, H, B0, S, E, lam_dt, torch.float64)
@@ -427,9 +557,29 @@ def main():
                    "iterations_per_step": f64["iters"]},
         "roofline": {"kernel": "k_blk_sweep<double> (one fused red-black sweep, level 0)",
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic("f64"),
-                     "us_per_launch": t_sw * 1e6, "bytes_per_launch": bytes_sw},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic("sweep_f64", n),
+                     "us_per_launch": t_sw * 1e6, "bytes_per_launch": bytes_sw,
+                     "residency": f"{n}^3: {bytes_sw / 1e6:.0f} MB working set"
+                                  + (", inside the 256 MB last-level cache" if bytes_sw < 256e6 else "")},
     }
+    if args.hbm_n:
+        nh = args.hbm_n
+        _, Hh, Bh, Sh, Eh, dth = random_level(nh)
+        ch = nh ** 3
+        t_h = smoother_rate(ohm, Hh, Bh, Sh, Eh, 0.5 * dth, torch.float64)
+        leg = {"kernel": "k_blk_sweep<double> (one fused red-black sweep, level 0)", "bound": "hbm",
+               "achieved": ch * 80 / t_h / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": ch * 80 / t_h / 1e9 / HBM_PEAK_GBS, "traffic": counter_traffic("sweep_f64", nh),
+               "us_per_launch": t_h * 1e6, "bytes_per_launch": ch * 80,
+               "residency": f"{nh}^3: {ch * 80 / 1e9:.2f} GB working set, streamed from HBM", "others": {}}
+        for kind, tag, bpc in (("apply", "apply_f64", 56), ("resid", "resid_f64", 80)):
+            t_k = stencil_rate(ohm, Hh, Bh, Sh, Eh, 0.5 * dth, kind)
+            leg["others"][tag] = {"us_per_launch": t_k * 1e6, "bytes_per_launch": ch * bpc,
+                                  "achieved": ch * bpc / t_k / 1e9, "frac": ch * bpc / t_k / 1e9 / HBM_PEAK_GBS,
+                                  "traffic": counter_traffic(tag, nh)}
+        out["roofline_hbm"] = leg
+        _log(f"{nh}^3 sweep: {t_h * 1e6:.1f} us per launch, {leg['achieved']:.0f} GB/s algorithmic")
+        del Hh, Bh, Sh, Eh
     if "mixed" in res:
         mx = res["mixed"]
         diff = (mx["B"] - f64["B"]).norm().item() / f64["B"].norm().item()
@@ -440,7 +590,7 @@ def main():
                         "smoother_f32_GBs": cells * 10 * 4 / t32 / 1e9}
     if args.cpu_sample:
         _log(f"timing the oracle on a {args.cpu_sample}^3 sample")
-        out["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
     print(json.dumps(out), flush=True)
 
 

@@ -223,6 +223,8 @@ void oref_prolong_add(int nxc, int nyc, int nzc, int ncomp, const double *coarse
 #ifdef _OPENMP
 #include <omp.h>
 int oref_threads(void) { return omp_get_max_threads(); }
+void oref_set_threads(int n) { omp_set_num_threads(n); }
 #else
 int oref_threads(void) { return 1; }
+void oref_set_threads(int n) { (void)n; }
 #endif

@@ -39,12 +39,19 @@ def lib():
             f.restype = None
         _lib.oref_threads.argtypes = []
         _lib.oref_threads.restype = ctypes.c_int
+        _lib.oref_set_threads.argtypes = [_I]
+        _lib.oref_set_threads.restype = None
     return _lib
 
 
 def threads() -> int:
     """OpenMP threads of the C primitives."""
     return int(lib().oref_threads())
+
+
+def set_threads(n: int) -> None:
+    """Set the OpenMP threads of the C primitives (timing only)."""
+    lib().oref_set_threads(int(n))
 
 
 def _p(a: np.ndarray):
