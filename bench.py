@@ -92,7 +92,7 @@ def record_counters(fetch_dir: str, write_dir: str, n: int) -> dict:
     cal, res = {"copy_KiB": copy_kib}, {}
     for tag, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         rows = per_kernel(d, counter)
-        c = max(v for _, k, v in rows if "copyBuffer" in k)
+        c = next(v for _, k, v in rows if "copyBuffer" in k)   # the probe's first kernel after its fill
         cal[f"{tag}_read_KiB"] = c
         cal[f"{tag}_factor"] = copy_kib / c
         res[tag] = (rows, copy_kib / c)
