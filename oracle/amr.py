@@ -179,3 +179,124 @@ class Composite:
     def cn_step(self, bs, etas, dt, lam=0.5, rtol=1e-13):
         Ss = self.source(bs, etas, dt, lam)
         return self.solve(Ss, etas, lam * dt, x0s=bs, rtol=rtol)
+
+
+class AMRMultigrid:
+    """Multigrid for the composite correction equation L_comp e = r on an AMR
+    hierarchy (section 2.2 and Table 1; the paper delegates the mechanics to
+    its SFUMATO reference, which is not available, so the steps below are this
+    project's reading, shared with the GPU solver).
+
+    A composite V-cycle on levels 0..top, for the correction d of a current
+    composite approximation z with residual t = r - L_comp z:
+      down, m = top .. 1: nu sweeps on level m from d_m = 0 with zero
+        coarse-fine ghosts; the level residual of d_m, restricted (mean of the
+        8 children), becomes the right-hand side of the covered cells of level
+        m - 1; the leaf cells of level m - 1 next to level m lose the change
+        that d_m makes to the refluxed fluxes of their coarse-fine faces (the
+        coarse correction is still zero there);
+      level 0: the base-grid multigrid (uniform periodic level, mg.fmg with
+        n_base V-cycles of nu_base sweeps, or mg.vcycle) on the whole base grid;
+      up, m = 1 .. top: d_m += trilinear prolongation of d_{m-1}; nu sweeps on
+        level m with coarse-fine ghosts interpolated from d_{m-1}.
+    FMG over the AMR levels (Table 1, first row): the right-hand side restricted
+    to every level under finer blocks, the base grid solved alone, then for
+    each finer level in turn the correction interpolated onto it and n_fmg
+    composite V-cycles on the levels up to it; at the finest level n_mlat more
+    composite V-cycles follow (second row).  Each composite V-cycle starts
+    from the composite residual of the current approximation."""
+
+    def __init__(self, comp: Composite, etas, lam_dt, nu=4, n_base=2, nu_base=2, base_fmg=True):
+        self.C = comp
+        self.etas = etas
+        self.lam_dt = lam_dt
+        self.L = comp.L
+        self.nu = nu
+        self.ef = comp.fill_ghosts(etas)
+        self.base = mg.hierarchy(self.ef[0], comp.spec.dx(0), lam_dt)
+        self.n_base, self.nu_base, self.base_fmg = n_base, nu_base, base_fmg
+        # the composite operator of the levels 0..top, for every top
+        self.sub = [Composite(HierSpec(comp.spec.base_blocks, comp.spec.dx0, comp.spec.levels[:top + 1]))
+                    for top in range(self.L)]
+
+    def smooth(self, m, d, t, ghost, n):
+        """n red-black sweeps (eq. 19) on the cells of level m, ghosts fixed."""
+        mask = self.C.mask[m][None]
+        x = np.where(mask, d, ghost)
+        for _ in range(n):
+            for colour in (0, 1):
+                x = ref.rb_halfsweep(x, t, self.ef[m], self.C.spec.dx(m), self.lam_dt, colour)
+                x = np.where(mask, x, ghost)
+        return np.where(mask, x, 0.0)
+
+    def base_solve(self, t0):
+        if self.base_fmg:
+            return mg.fmg(self.base, t0, self.n_base, self.nu_base, self.nu_base)
+        e = np.zeros_like(t0)
+        for _ in range(self.n_base):
+            e = e + mg.vcycle(self.base, t0 - self.base[0].L(e), self.nu_base, self.nu_base)
+        return e
+
+    def reflux_change(self, m, dm):
+        """lam_dt times the divergence, at the leaf cells of level m - 1, of the
+        refluxed coarse-fine face fluxes that a level-m correction dm alone
+        produces (every other level zero)."""
+        C = self.C
+        Xs = [np.zeros((3,) + C.mask[l].shape) for l in range(self.L)]
+        Xs[m] = dm
+        F, _, _ = C.fluxes(Xs, self.etas)
+        cov = C.covered[m - 1]
+        Fm = []
+        for dd in range(3):
+            nbr = np.roll(cov, -1, axis=2 - dd)
+            Fm.append(np.where((cov | nbr)[None], F[m - 1][dd], 0.0))
+        D = ref.div(Fm, C.spec.dx(m - 1))
+        return np.where(C.leaf[m - 1][None], self.lam_dt * D, 0.0)
+
+    def vcycle(self, t, top):
+        """Correction d on levels 0..top for the composite residual t."""
+        C = self.C
+        t = [x.copy() for x in t]
+        d = [np.zeros_like(x) for x in t]
+        for m in range(top, 0, -1):
+            zero = np.zeros_like(d[m])
+            d[m] = self.smooth(m, zero, t[m], zero, self.nu)
+            res = t[m] - ref.apply(d[m], self.ef[m], C.spec.dx(m), self.lam_dt)
+            rr = ref.restrict(np.where(C.mask[m][None], res, 0.0))
+            t[m - 1] = np.where(C.covered[m - 1][None], rr, t[m - 1] - self.reflux_change(m, d[m]))
+        d[0] = self.base_solve(t[0])
+        for m in range(1, top + 1):
+            g = ref.prolong(d[m - 1])
+            d[m] = self.smooth(m, np.where(C.mask[m][None], d[m] + g, 0.0), t[m], g, self.nu)
+        return d
+
+    def residual(self, z, rf, top):
+        """rf - L_comp z on the leaf cells of levels 0..top (level top has no
+        finer level; its cells under finer blocks hold their own unknowns)."""
+        S = self.sub[top]
+        R = S.residual(z[:top + 1], rf[:top + 1], self.etas[:top + 1], self.lam_dt)
+        return R + [np.zeros_like(x) for x in z[top + 1:]]
+
+    def fmg(self, r, n_fmg=4, n_mlat=2):
+        """e = L_comp^{-1} r by FMG over the AMR levels (see the class notes)."""
+        C = self.C
+        rf = [x.copy() for x in r]
+        for m in range(self.L - 1, 0, -1):
+            rr = ref.restrict(np.where(C.mask[m][None], rf[m], 0.0))
+            rf[m - 1] = np.where(C.covered[m - 1][None], rr, rf[m - 1])
+        z = [np.zeros_like(x) for x in r]
+        z[0] = self.base_solve(rf[0])
+        for top in range(1, self.L):
+            z[top] = np.where(C.mask[top][None], ref.prolong(z[top - 1]), 0.0)
+            for _ in range(n_fmg + (n_mlat if top == self.L - 1 else 0)):
+                d = self.vcycle(self.residual(z, rf, top), top)
+                z = [z[l] + d[l] if l <= top else z[l] for l in range(self.L)]
+        return z
+
+    def vcycles(self, r, n):
+        """n composite V-cycles on all levels from a zero approximation."""
+        z = [np.zeros_like(x) for x in r]
+        for _ in range(n):
+            d = self.vcycle(self.residual(z, r, self.L - 1), self.L - 1)
+            z = [z[l] + d[l] for l in range(self.L)]
+        return z

@@ -2,7 +2,10 @@
 single level, linear fields are reproduced exactly through the coarse-fine
 ghosts and the refluxed faces, refluxing conserves the volume integral
 (section 4), the composite solve matches a sparse direct solve, and on the
-paper's half-refined box the step is second order in the cell width (Fig. 5)."""
+paper's half-refined box the step is second order in the cell width (Fig. 5).
+The oracle's AMR multigrid (FMG over the AMR levels, Table 1) meets Fig. 6's
+one-iteration residual bound on that box and converges to the composite
+solution."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -172,3 +175,70 @@ def test_second_order_in_space_on_the_refined_grid(lam):
         measured = np.log2(err[0][l] / err[1][l])
         assert abs(measured - order) <= 0.3, (l, measured, err)
     assert all(e[0] > e[1] for e in err), err
+
+
+def _half_refined_sinusoid(N):
+    """Section 3.1's refined box with B_z = sin(2 pi x + 4 pi y), eta = 1."""
+    spec = _half_refined(N)
+    C = amr.Composite(spec)
+    es = [np.ones(C.mask[l].shape) for l in range(2)]
+    return spec, C, C.average_down(_sinusoid(spec, 1.0)), es
+
+
+def _max_leaf(C, R):
+    return max(np.abs(R[l][:, C.leaf[l]]).max() for l in range(C.L))
+
+
+@pytest.mark.parametrize("dt", [4e-3, 1e-4])
+@pytest.mark.parametrize("lam", [0.5, 1.0])
+def test_amr_fmg_one_iteration_fig6(dt, lam):
+    """Fig. 6 (section 3.1) on the half-refined grid: one iteration of eqs.
+    (16)-(18) from B^n, the multigrid step being FMG over the AMR levels with
+    Table 1's schedules (4 composite V-cycles of 4 + 4 sweeps on the refined
+    level, then 2 more (MLAT-FAS row), the base grid by FMG with 2 V-cycles of
+    2 + 2), takes max|R| from about 1 (dt = 4e-3) or 3e-2 (dt = 1e-4) below
+    1e-5 at N = 8.  A single composite V-cycle does not (the first iteration
+    then leaves the coarse-fine interface residual)."""
+    tab = paper("table1_schedules")["value"]
+    bound = paper("one_iteration_max_residual")["value"]
+    spec, C, B0, es = _half_refined_sinusoid(8)
+    S = C.source(B0, es, dt, lam)
+    R0 = C.residual(B0, S, es, lam * dt)
+    M = amr.AMRMultigrid(C, es, lam * dt, nu=tab["FMG on AMR"]["pre"], n_base=tab["FMG on base grid"]["v_cycles"],
+                         nu_base=tab["FMG on base grid"]["pre"])
+    e = M.fmg(R0, n_fmg=tab["FMG on AMR"]["v_cycles"], n_mlat=tab["MLAT-FAS on AMR"]["v_cycles"])
+    X = C.average_down([B0[l] + np.where(C.leaf[l][None], e[l], 0.0) for l in range(2)])
+    r0, r1 = _max_leaf(C, R0), _max_leaf(C, C.residual(X, S, es, lam * dt))
+    print("max|R|", r0, "->", r1)
+    assert r0 > 1e3 * bound and r1 < bound
+    one = M.vcycles(R0, 1)
+    X1 = C.average_down([B0[l] + np.where(C.leaf[l][None], one[l], 0.0) for l in range(2)])
+    assert _max_leaf(C, C.residual(X1, S, es, lam * dt)) > 10 * bound
+
+
+def test_amr_multigrid_iteration_reaches_the_composite_solution():
+    """Iterating x <- x + M(S - L_comp x) with one composite V-cycle converges
+    to the composite solution of the sparse-direct-checked solver, on the
+    hierarchy of the composite-solve pin (variable eta, 3 decades)."""
+    spec = gen.HierSpec((2, 2, 2), 1.0 / 16,
+                        [gen.full_level((2, 2, 2)), np.array([[1, 1, 1], [2, 1, 1]], dtype=np.int32)])
+    C = amr.Composite(spec)
+    rng = np.random.default_rng(17)
+    Bs = C.average_down([C.to_dense(l, rng.standard_normal((3, len(spec.levels[l]), 8, 8, 8))) for l in range(2)])
+    es = [C.to_dense(l, 10 ** rng.uniform(-3, 0, (len(spec.levels[l]), 8, 8, 8))) for l in range(2)]
+    es = [np.where(np.isnan(e), 1.0, e) for e in es]
+    dt = gen.explicit_dt(spec.dx(1), 1.0, 40.0)
+    S = C.source(Bs, es, dt)
+    ex, _ = C.solve(S, es, 0.5 * dt, rtol=1e-13)
+    M = amr.AMRMultigrid(C, es, 0.5 * dt, nu=2, n_base=1, nu_base=2)
+    x = [b.copy() for b in Bs]
+    nS = np.linalg.norm(C.pack(S))
+    for it in range(60):
+        R = C.residual(x, S, es, 0.5 * dt)
+        if np.linalg.norm(C.pack(R)) <= 1e-12 * nS:
+            break
+        e = M.vcycles(R, 1)
+        x = C.average_down([x[l] + np.where(C.leaf[l][None], e[l], 0.0) for l in range(2)])
+    print("iterations", it)
+    assert it < 60
+    assert np.linalg.norm(C.pack(x) - C.pack(ex)) <= 1e-10 * np.linalg.norm(C.pack(ex))
