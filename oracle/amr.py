@@ -193,8 +193,8 @@ class AMRMultigrid:
         coarse-fine ghosts; the level residual of d_m, restricted (mean of the
         8 children), becomes the right-hand side of the covered cells of level
         m - 1; the leaf cells of level m - 1 next to level m lose the change
-        that d_m makes to the refluxed fluxes of their coarse-fine faces (the
-        coarse correction is still zero there);
+        that d_m makes to the refluxed fluxes of their coarse-fine faces, taken
+        with the same zero ghosts (the coarse correction is still zero);
       level 0: the base-grid multigrid (uniform periodic level, mg.fmg with
         n_base V-cycles of nu_base sweeps, or mg.vcycle) on the whole base grid;
       up, m = 1 .. top: d_m += trilinear prolongation of d_{m-1}; nu sweeps on
@@ -239,12 +239,13 @@ class AMRMultigrid:
 
     def reflux_change(self, m, dm):
         """lam_dt times the divergence, at the leaf cells of level m - 1, of the
-        refluxed coarse-fine face fluxes that a level-m correction dm alone
-        produces (every other level zero)."""
+        refluxed coarse-fine face fluxes (mean of the 4 fine fluxes, eq. 11 and
+        section 4) of a level-m correction dm taken with zero coarse-fine ghost
+        values, the coarse correction being zero at that point of the cycle."""
         C = self.C
         Xs = [np.zeros((3,) + C.mask[l].shape) for l in range(self.L)]
-        Xs[m] = dm
-        F, _, _ = C.fluxes(Xs, self.etas)
+        Xs[m] = np.where(C.mask[m][None], dm, 0.0)
+        F, _, _ = C.fluxes(Xs, self.ef, complete=True)
         cov = C.covered[m - 1]
         Fm = []
         for dd in range(3):
