@@ -244,6 +244,25 @@ typedef struct {
     int32_t ordering;     /* smoother ordering, as for ohm_smooth: 0 = red-black
                              (fused sweeps), 1 = four colour classes (one launch per
                              class on every level)                                  */
+    /* Multigrid over the AMR levels (hierarchies with more than one level;
+       section 2.2, Table 1).  A composite V-cycle smooths each AMR level from
+       zero with zero coarse-fine ghosts, restricts its residual under its
+       blocks and takes its refluxed face fluxes out of the coarser leaf
+       residual, solves the base grid (cycle, n_vcycles, nu_pre, nu_post), then
+       prolongs and post-smooths each AMR level with ghosts from the coarser
+       correction.                                                           */
+    int32_t amr_fmg;      /* 0 = amr_vcycles composite V-cycles per multigrid
+                             application; 1 = full multigrid over the AMR levels:
+                             the base grid alone on the restricted right-hand
+                             side, then per finer level the interpolated
+                             correction and amr_vcycles composite V-cycles     */
+    int32_t amr_vcycles;  /* >= 1; Table 1 "FMG on AMR": 4                       */
+    int32_t amr_mlat;     /* further composite V-cycles on all levels (Table 1
+                             "MLAT-FAS on AMR": 2); every composite V-cycle after
+                             the first of an application starts from the FP64
+                             composite residual of the correction so far       */
+    int32_t nu_amr;       /* sweeps before and after on AMR levels >= 1 (0 =
+                             nu_pre / nu_post)                                   */
 } ohm_cn_opts;
 
 typedef struct {

@@ -37,7 +37,8 @@ class CnOpts(ctypes.Structure):
                 ("nu_pre", ctypes.c_int32), ("nu_post", ctypes.c_int32), ("n_vcycles", ctypes.c_int32),
                 ("cycle", ctypes.c_int32), ("outer", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("coarse_sweeps", ctypes.c_int32), ("nu_coarse", ctypes.c_int32),
-                ("graph", ctypes.c_int32), ("ordering", ctypes.c_int32)]
+                ("graph", ctypes.c_int32), ("ordering", ctypes.c_int32), ("amr_fmg", ctypes.c_int32),
+                ("amr_vcycles", ctypes.c_int32), ("amr_mlat", ctypes.c_int32), ("nu_amr", ctypes.c_int32)]
 
 
 class CnStats(ctypes.Structure):

@@ -30,6 +30,7 @@ struct Plan {
     size_t rhs, e, tmp, res, mg_g, eta_t, eta_tg;
     size_t d_rhs[16], d_e[16], d_tmp[16], d_res[16], d_eta[16], d_eta64[16];
     size_t inv, aug, jobs, force, part, dots, scal, ranges, mlprob, active, cmask, coefs;
+    size_t rf;                  // FMG over AMR levels: right-hand side restricted under finer blocks
     size_t inv_elems = 0, aug_elems = 0;
 };
 
@@ -61,6 +62,7 @@ Plan make_plan(const ohm_hier *h, const ohm_cn_opts *o)
     P.ph = take(8 * V);
     P.sh = take(8 * V);
     P.S = take(8 * V);
+    P.rf = take(o->amr_fmg && h->nlev > 1 ? 8 * V : 8);
     P.og = take(8 * G + 8);
     P.oeg = take(8 * G / 3 + 8);
     P.rhs = take(tb * V);
@@ -105,7 +107,8 @@ bool valid_opts(const ohm_cn_opts *o)
     return o && o->lambda > 0.0 && o->lambda <= 1.0 && o->rtol > 0.0 && o->max_iters >= 1 && o->nu_pre >= 0 &&
            o->nu_post >= 0 && o->nu_pre + o->nu_post >= 1 && o->n_vcycles >= 1 && (o->cycle == 0 || o->cycle == 1) &&
            (o->outer == 0 || o->outer == 1) && (o->precision == 0 || o->precision == 1) && o->coarse_sweeps >= 0 &&
-           o->nu_coarse >= 0 && (o->graph == 0 || o->graph == 1) && (o->ordering == 0 || o->ordering == 1);
+           o->nu_coarse >= 0 && (o->graph == 0 || o->graph == 1) && (o->ordering == 0 || o->ordering == 1) &&
+           (o->amr_fmg == 0 || o->amr_fmg == 1) && o->amr_vcycles >= 1 && o->amr_mlat >= 0 && o->nu_amr >= 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -147,9 +150,12 @@ struct Solver {
     // ---- outer composite operator (FP64) --------------------------------------
     // y = L x (mode APPLY, coef) or y = S - L x (mode RESID) on leaf cells;
     // covered cells of y are zero.
-    ohm_status composite(size_t xo, size_t yo, int mode, const double *coef, const double *reflux_coef, size_t So)
+    // top >= 0: the composite operator of levels 0..top only (level top is
+    // then the finest: its cells under finer blocks are its own unknowns)
+    ohm_status composite(size_t xo, size_t yo, int mode, const double *coef, const double *reflux_coef, size_t So,
+                         int top = -1)
     {
-        const int L = nlev();
+        const int L = top >= 0 ? top + 1 : nlev();
         for (int l = L - 1; l >= 1; --l)
             OHM_TRY(launch_restrict_blk<double>(h, l, vec(xo, l), VN, vec(xo, l - 1), VN, 3, active, st));
         for (int l = 1; l < L; ++l)
@@ -417,38 +423,15 @@ struct Solver {
     // (the cycle only reads r and only writes z); otherwise r is copied, in
     // the cycle's precision, into its right-hand side first
     bool cycle_aliases() const { return !P.T32 && nlev() == 1; }
-    // rhs_ready: the vector kernel that produced r already wrote that copy
-    ohm_status precond(size_t ro, size_t zo, bool rhs_ready = false)
+    int nu_amr_pre() const { return o->nu_amr > 0 ? o->nu_amr : o->nu_pre; }
+    int nu_amr_post() const { return o->nu_amr > 0 ? o->nu_amr : o->nu_post; }
+    // more than one composite V-cycle per application, or FMG over the levels
+    bool amr_general() const { return nlev() > 1 && (o->amr_fmg || o->amr_vcycles > 1 || o->amr_mlat > 0); }
+
+    // the base-grid multigrid on rhs(0) -> e(0); o64: FP64 output of a single
+    // level's last post-sweep (or null)
+    ohm_status base_cycle(double *o64)
     {
-        const long long n = 3 * P.NBt * NC;
-        const int L = nlev();
-        const bool alias = cycle_aliases();
-        if (alias) {
-            rhs_b = (T *)at<double>(ro);
-            e_b = (T *)at<double>(zo);
-        } else {
-            rhs_b = e_b = nullptr;
-            if (!rhs_ready) OHM_TRY(vconvert<double, T>(at<double>(ro), at<T>(P.rhs), n, st));
-        }
-        // AMR levels, finest first: smooth with zero coarse-fine ghosts,
-        // restrict the level residual under the finer blocks, and take the
-        // refluxed fluxes of the level's correction out of the residual of the
-        // coarser leaf cells next to it (the coarser correction is still zero
-        // there): the coarser level then solves the composite residual
-        if (L > 1 && P.NGt > 0) OHM_TRY(vfill<T>(at<T>(P.mg_g), 3 * P.NGt * NC, T(0), st));
-        for (int l = L - 1; l >= 1; --l) {
-            OHM_TRY(smooth_blk(l, o->nu_pre, SMOOTH_ZERO));
-            OHM_TRY(resid_blk(l));
-            OHM_TRY(launch_restrict_blk<T>(h, l, mg(P.res, l), VN, mg(P.rhs, l - 1), VN, 3, active, st));
-            OHM_TRY(launch_reflux<T>(h, l - 1, nullptr, VN, etaT(l - 1), mg(P.e, l), VN, at<T>(P.mg_g) + P.LG[l] * NC,
-                                     GN, etaT(l), etagT(l), neg_lam_dt, mg(P.rhs, l - 1), active, st));
-        }
-        // one FP32 level: the last post-sweep writes the FP64 result directly
-        double *const o64 = (P.T32 && L == 1 && h->amr[0].complete27 && fused_blk(0) &&
-                             (unsigned long long)h->amr[0].nb * NC * sizeof(double) <= 0xFFFFFFFFull)
-                                ? at<double>(zo)
-                                : nullptr;
-        wrote64_ = false;
         if (o->cycle == 1) {
             out64_ = o64;
             OHM_TRY(fmg_base());
@@ -459,13 +442,107 @@ struct Solver {
             }
         }
         out64_ = nullptr;
-        for (int l = 1; l < L; ++l) {
+        return OHM_OK;
+    }
+
+    // one composite V-cycle from a zero correction on levels 0..top, for the
+    // right-hand side in rhs (precision T, levels 0..top); the correction is
+    // left in e.  AMR levels, finest first: smooth with zero coarse-fine
+    // ghosts, restrict the level residual under the finer blocks, and take
+    // the refluxed fluxes of the level's correction out of the residual of
+    // the coarser leaf cells next to it (the coarser correction is still zero
+    // there): the coarser level then solves the composite residual
+    ohm_status amr_vcycle(int top, double *o64)
+    {
+        if (top >= 1 && P.NGt > 0) OHM_TRY(vfill<T>(at<T>(P.mg_g), 3 * P.NGt * NC, T(0), st));
+        for (int l = top; l >= 1; --l) {
+            OHM_TRY(smooth_blk(l, nu_amr_pre(), SMOOTH_ZERO));
+            OHM_TRY(resid_blk(l));
+            OHM_TRY(launch_restrict_blk<T>(h, l, mg(P.res, l), VN, mg(P.rhs, l - 1), VN, 3, active, st));
+            OHM_TRY(launch_reflux<T>(h, l - 1, nullptr, VN, etaT(l - 1), mg(P.e, l), VN, at<T>(P.mg_g) + P.LG[l] * NC,
+                                     GN, etaT(l), etagT(l), neg_lam_dt, mg(P.rhs, l - 1), active, st));
+        }
+        wrote64_ = false;
+        OHM_TRY(base_cycle(o64));
+        for (int l = 1; l <= top; ++l) {
             OHM_TRY(launch_prolong_blk<T>(h, l - 1, mg(P.e, l - 1), VN, mg(P.e, l), VN, 3, 1, active, st));
             OHM_TRY(launch_fill_ghosts<T>(h, l, mg(P.e, l - 1), VN, at<T>(P.mg_g) + P.LG[l] * NC, GN, 3, active, st));
-            OHM_TRY(smooth_blk(l, o->nu_post));
+            OHM_TRY(smooth_blk(l, nu_amr_post()));
         }
+        return OHM_OK;
+    }
+
+    // levels 0..top of a multi-level vector: FP64 src -> precision-T dst
+    // (per component, the levels are contiguous from block 0)
+    template <typename S, typename D>
+    ohm_status convert_upto(const S *src, D *dst, int top)
+    {
+        const long long n = (top + 1 < nlev() ? P.LB[top + 1] : P.NBt) * NC;
+        for (int c = 0; c < 3; ++c) OHM_TRY(vconvert<S, D>(src + c * VN, dst + c * VN, n, st));
+        return OHM_OK;
+    }
+
+    ohm_status precond(size_t ro, size_t zo, bool rhs_ready = false)
+    {
+        if (amr_general()) return precond_amr(ro, zo);
+        const long long n = 3 * P.NBt * NC;
+        const int L = nlev();
+        const bool alias = cycle_aliases();
+        if (alias) {
+            rhs_b = (T *)at<double>(ro);
+            e_b = (T *)at<double>(zo);
+        } else {
+            rhs_b = e_b = nullptr;
+            if (!rhs_ready) OHM_TRY(vconvert<double, T>(at<double>(ro), at<T>(P.rhs), n, st));
+        }
+        // one FP32 level: the last post-sweep writes the FP64 result directly
+        double *const o64 = (P.T32 && L == 1 && h->amr[0].complete27 && fused_blk(0) &&
+                             (unsigned long long)h->amr[0].nb * NC * sizeof(double) <= 0xFFFFFFFFull)
+                                ? at<double>(zo)
+                                : nullptr;
+        OHM_TRY(amr_vcycle(L - 1, o64));
         if (!alias && !wrote64_) OHM_TRY(vconvert<T, double>(at<T>(P.e), at<double>(zo), n, st));
         rhs_b = e_b = nullptr;
+        return OHM_OK;
+    }
+
+    // several composite V-cycles per application, or FMG over the AMR levels
+    // (section 2.2, Table 1): every composite V-cycle after the first takes
+    // the FP64 composite residual of the correction z so far (levels 0..top)
+    // as its right-hand side and adds its correction to z.  The vector t is
+    // free during an application in both outer iterations.
+    ohm_status precond_amr(size_t ro, size_t zo)
+    {
+        const int L = nlev();
+        rhs_b = e_b = nullptr;
+        double *z = at<double>(zo), *t = at<double>(P.t);
+        OHM_TRY(vfill<double>(z, 3 * VN, 0.0, st));
+        auto cycle = [&](int top, size_t so) -> ohm_status {
+            OHM_TRY(composite(zo, P.t, MODE_RESID, lam_dt, neg_lam_dt, so, top));
+            OHM_TRY(convert_upto<double, T>(t, at<T>(P.rhs), top));
+            OHM_TRY(amr_vcycle(top, nullptr));
+            OHM_TRY(convert_upto<T, double>(at<T>(P.e), t, top));
+            const int nblk = (int)(top + 1 < L ? P.LB[top + 1] : P.NBt);
+            return vaxpy1(nblk, mlprob, active, VN, z, t, st);
+        };
+        if (!o->amr_fmg) {
+            for (int k = 0; k < o->amr_vcycles + o->amr_mlat; ++k) OHM_TRY(cycle(L - 1, ro));
+            return OHM_OK;
+        }
+        // FMG: the right-hand side restricted under the finer blocks (finest
+        // first), the base grid alone, then level by level
+        double *rf = at<double>(P.rf);
+        OHM_TRY(vconvert<double, double>(at<double>(ro), rf, 3 * VN, st));
+        for (int l = L - 1; l >= 1; --l)
+            OHM_TRY(launch_restrict_blk<double>(h, l, vec(P.rf, l), VN, vec(P.rf, l - 1), VN, 3, active, st));
+        OHM_TRY(convert_upto<double, T>(rf, at<T>(P.rhs), 0));
+        OHM_TRY(base_cycle(nullptr));
+        OHM_TRY(convert_upto<T, double>(at<T>(P.e), z, 0));
+        for (int top = 1; top < L; ++top) {
+            OHM_TRY(launch_prolong_blk<double>(h, top - 1, vec(zo, top - 1), VN, vec(zo, top), VN, 3, 0, active, st));
+            const int n = o->amr_vcycles + (top == L - 1 ? o->amr_mlat : 0);
+            for (int k = 0; k < n; ++k) OHM_TRY(cycle(top, P.rf));
+        }
         return OHM_OK;
     }
 
@@ -713,7 +790,7 @@ struct Solver {
         for (int l = 0; l < nlev(); ++l) key.push_back(Euser[l]);
         // the options' bytes up to the end of their last field (not the
         // struct's tail padding, which callers need not initialise)
-        std::vector<char> ob((const char *)o, (const char *)&o->ordering + sizeof(o->ordering));
+        std::vector<char> ob((const char *)o, (const char *)&o->nu_amr + sizeof(o->nu_amr));
         ohm_hier::GraphSlot &G = h->graphs[kind];
         if (!G.exec || G.key != key || G.opts != ob) {
             if (G.exec) {
@@ -925,6 +1002,10 @@ void ohm_cn_default_opts(ohm_cn_opts *o)
     o->nu_coarse = 0;
     o->graph = 1;
     o->ordering = 0;
+    o->amr_fmg = 0;
+    o->amr_vcycles = 1;
+    o->amr_mlat = 0;
+    o->nu_amr = 0;
 }
 
 ohm_status ohm_cn_workspace_size(const ohm_hier *h, const ohm_cn_opts *opts, size_t *bytes)

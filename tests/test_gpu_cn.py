@@ -497,3 +497,45 @@ def test_coarsest_solve_with_row_exchanges(precision):
     err = np.abs(got - (B + e)).max() / np.abs(e).max()
     print("stats", stats, "max err / max correction", err)
     assert err <= (1e-11 if precision == 0 else 2e-5)
+
+
+@pytest.mark.parametrize("fmg,precision", [(1, 0), (1, 1), (0, 0)])
+def test_amr_multigrid_one_iteration_equals_the_oracle(fmg, precision):
+    """One iteration of eqs. (16)-(18) on the three-level hierarchy (dense-core
+    eta over four decades) with the multigrid over the AMR levels: FMG over
+    the levels with 2 composite V-cycles per stage and 1 more at the finest
+    (fmg = 1), or 3 composite V-cycles (fmg = 0); 3 + 3 sweeps on the AMR
+    levels, the base grid by FMG with 1 V-cycle of 2 + 2.  The GPU iterate
+    equals the oracle's AMR multigrid (every sweep, transfer, refluxed
+    coarse-fine update and base solve) to FP64 rounding of the correction, or
+    FP32 rounding in mixed precision."""
+    import paper_1009_0798_amd as ohm
+    announce(f"cn amr multigrid one iteration fmg={fmg} precision={precision}")
+    spec = gen.config_corner_gap()
+    C = amr.Composite(spec)
+    L = spec.nlevels
+    Bb, eb = gen.amr_fields_fourier(spec, seed=29)
+    Bs = C.average_down([C.to_dense(l, Bb[l]) for l in range(L)])
+    es = [C.to_dense(l, eb[l]) for l in range(L)]
+    dt = 20.0 * spec.dx(L - 1) ** 2 / (6 * 10.0)
+    H = hier(spec)
+    Bt = [cuda(dense_to_blocks(Bs[l], spec.levels[l])) for l in range(L)]
+    Et = [cuda(dense_to_blocks(es[l], spec.levels[l])[None]) for l in range(L)]
+    opts = dict(outer=0, max_iters=1, rtol=1e-14, precision=precision, amr_fmg=fmg,
+                amr_vcycles=2 if fmg else 3, amr_mlat=1 if fmg else 0, nu_amr=3, cycle=1, n_vcycles=1,
+                nu_pre=2, nu_post=2, nu_coarse=0)
+    st, stats = ohm.ohm_cn_step(H, Bt, Et, dt, ohm.default_opts(**opts))
+    assert st == ohm._lib.OHM_ERR_NOCONV and stats[0]["iters"] == 1
+    got = [blocks_to_dense(host(Bt[l]), spec.levels[l], spec.cells(l)) for l in range(L)]
+    lam_dt = 0.5 * dt
+    S = C.source(Bs, es, dt)
+    R0 = C.residual(Bs, S, es, lam_dt)
+    M = amr.AMRMultigrid(C, es, lam_dt, nu=3, n_base=1, nu_base=2)
+    e = M.fmg(R0, n_fmg=2, n_mlat=1) if fmg else M.vcycles(R0, 3)
+    X = C.average_down([Bs[l] + np.where(C.leaf[l][None], e[l], 0.0) for l in range(L)])
+    emax = max(np.abs(e[l][:, C.leaf[l]]).max() for l in range(L))
+    err = max(np.abs(got[l][:, C.leaf[l]] - X[l][:, C.leaf[l]]).max() for l in range(L))
+    r1 = C.residual(X, S, es, lam_dt)
+    print("stats", stats, "max err / max correction", err / emax,
+          "oracle max|R|", max(np.abs(R0[l]).max() for l in range(L)), "->", max(np.abs(r1[l]).max() for l in range(L)))
+    assert err <= (1e-11 if precision == 0 else 2e-5) * emax
