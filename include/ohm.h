@@ -94,6 +94,12 @@ ohm_status ohm_hier_create(const ohm_problem_desc *probs, int32_t nprob, hipStre
                            ohm_hier **out);
 ohm_status ohm_hier_destroy(ohm_hier *h);
 
+/* Device bytes the handle itself holds: its block tables and reduction
+ * scratch, plus the per-problem coefficient slots and the coarsest-grid
+ * inverses that its first calls allocate (caller memory -- fields and the
+ * step's workspace -- is not included). */
+ohm_status ohm_hier_device_bytes(const ohm_hier *h, size_t *bytes);
+
 /* Totals over all problems at `level` (>= 0: AMR level, < 0: multigrid level):
  * *nblocks (0 for level < 0), *ncells, and *nghost = coarse-fine ghost blocks. */
 ohm_status ohm_hier_level_info(const ohm_hier *h, int32_t level, int64_t *nblocks,

@@ -73,6 +73,12 @@ class Hierarchy:
         check(lib().ohm_hier_problem_info(self.h, prob, level, ctypes.byref(off), dims, None))
         return off.value, tuple(dims)
 
+    def device_bytes(self):
+        """Device bytes the handle itself holds (``ohm_hier_device_bytes``)."""
+        n = ctypes.c_size_t()
+        check(lib().ohm_hier_device_bytes(self.h, ctypes.byref(n)))
+        return n.value
+
     def field(self, level, ncomp=3, dtype=None, fill=0.0):
         """A zero field of ``level`` in the library's layout."""
         import torch

@@ -21,6 +21,7 @@ STATUS_NAMES = {0: "OHM_OK", 1: "OHM_ERR_ARG", 2: "OHM_ERR_LAYOUT", 3: "OHM_ERR_
                 5: "OHM_ERR_NOCONV", 6: "OHM_ERR_NONFINITE"}
 
 EXPORTS = ["ohm_hier_create", "ohm_hier_destroy", "ohm_hier_level_info", "ohm_hier_problem_info",
+           "ohm_hier_device_bytes",
            "ohm_last_error", "ohm_fill_ghosts", "ohm_apply", "ohm_residual", "ohm_smooth", "ohm_restrict",
            "ohm_prolong", "ohm_reflux", "ohm_cn_default_opts", "ohm_cn_workspace_size", "ohm_cn_step",
            "ohm_explicit_workspace_size", "ohm_explicit_step", "ohm_residual_noalloc"]
@@ -73,6 +74,7 @@ def lib() -> ctypes.CDLL:
             "ohm_hier_destroy": [P],
             "ohm_hier_level_info": [P, I32, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64)],
             "ohm_hier_problem_info": [P, I32, I32, ctypes.POINTER(I64), ctypes.POINTER(I32), ctypes.POINTER(I32)],
+            "ohm_hier_device_bytes": [P, ctypes.POINTER(ctypes.c_size_t)],
             "ohm_fill_ghosts": [P, I32, P, P, I32, I32, P],
             "ohm_apply": [P, I32, P, P, P, P, DP, P, I32, P],
             "ohm_residual": [P, I32, P, P, P, P, P, DP, P, DP, I32, P],

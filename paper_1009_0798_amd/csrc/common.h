@@ -136,6 +136,7 @@ struct ohm_hier {
     double *d_part = nullptr;        // reduction partials
     size_t part_cap = 0;
     double *d_norms = nullptr;       // [nprob * 6]
+    size_t table_bytes = 0;          // device bytes of the tables and scratch above
     double *h_dots = nullptr;        // pinned host copy of an iteration's norms [8 * nprob]
     char *h_stage = nullptr;         // pinned staging of a step's host-built tables
     size_t stage_bytes = 0;
@@ -299,6 +300,7 @@ size_t coarse_job_bytes();
 // Scratch `aug` holds sum 2 n3^2 doubles.
 void coarse_plan(ohm_hier *h, const double *lam_dt_host, void *jobs_host, int *force_host, int *njobs);
 ohm_status ensure_coarse_storage(ohm_hier *h);   // the handle's inverse storage (before any capture)
+size_t coarse_storage_bytes(const ohm_hier *h);  // device bytes ensure_coarse_storage allocates
 ohm_status launch_coarse_build(ohm_hier *h, const double *const *eta_dense, const void *jobs_dev,
                                const int *force_dev, const int *njobs, double *aug, hipStream_t s);
 template <typename T>

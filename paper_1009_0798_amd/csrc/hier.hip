@@ -106,6 +106,8 @@ bool coarsen_ok(const int n[3])
 
 // stream of the handle being built (uploads are ordered on it, then synchronised)
 thread_local hipStream_t g_up_stream = nullptr;
+// device bytes of the tables uploaded for the handle being built
+thread_local size_t g_up_bytes = 0;
 
 template <typename V>
 ohm_status upload(V **dptr, const std::vector<V> &h)
@@ -114,6 +116,7 @@ ohm_status upload(V **dptr, const std::vector<V> &h)
     if (h.empty()) return OHM_OK;
     std::lock_guard<std::mutex> lock(capture_mutex());   // device work outside any captured stream
     OHM_HIP(hipMalloc((void **)dptr, sizeof(V) * h.size()));
+    g_up_bytes += sizeof(V) * h.size();
     OHM_HIP(hipMemcpyAsync(*dptr, h.data(), sizeof(V) * h.size(), hipMemcpyHostToDevice, g_up_stream));
     OHM_HIP(hipStreamSynchronize(g_up_stream));
     return OHM_OK;
@@ -521,6 +524,7 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
     for (int l = 0; l < H->nlev; ++l) maxnb = std::max(maxnb, (size_t)H->nb_host[l]);
     H->part_cap = maxnb * 8 + 2 * (size_t)nprob * OHM_MAX_LEVELS + 64;
     OHM_HIP(hipMalloc((void **)&H->d_part, sizeof(double) * H->part_cap));
+    H->table_bytes = g_up_bytes + sizeof(double) * (4 * (size_t)nprob + 8 * (size_t)nprob + H->part_cap);
     H->cinv_off.assign(nprob, -1);
     H->cinv_n.assign(nprob, 0);
     H->cinv_lamdt.assign(nprob, -1.0);
@@ -576,6 +580,7 @@ ohm_status ohm_hier_create(const ohm_problem_desc *probs, int32_t nprob, hipStre
     // the host tables are built without the capture lock; each device
     // allocation and upload takes it
     g_up_stream = stream;
+    g_up_bytes = 0;
     ohm_status st = build(H, probs, nprob);
     g_up_stream = nullptr;
     if (st != OHM_OK) {
@@ -594,6 +599,16 @@ ohm_status ohm_hier_destroy(ohm_hier *h)
     std::lock_guard<std::mutex> lock(capture_mutex());
     free_all(h);
     delete h;
+    return OHM_OK;
+}
+
+ohm_status ohm_hier_device_bytes(const ohm_hier *h, size_t *bytes)
+{
+    if (!h || !bytes) return fail(OHM_ERR_ARG, "NULL argument");
+    // tables and reduction scratch, plus what the first calls allocate: the
+    // coefficient slots of the per-operation calls and the coarsest-grid
+    // inverses of the step
+    *bytes = h->table_bytes + sizeof(double) * 64 * (size_t)h->nprob + coarse_storage_bytes(h);
     return OHM_OK;
 }
 

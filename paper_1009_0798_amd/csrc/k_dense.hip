@@ -694,6 +694,15 @@ void coarse_plan(ohm_hier *h, const double *lam_dt_host, void *jobs_host, int *f
     }
 }
 
+size_t coarse_storage_bytes(const ohm_hier *h)
+{
+    size_t inv_elems = 0, aug_elems = 0, eta_elems = 0;
+    coarse_sizes(h, &inv_elems, &aug_elems);
+    if (inv_elems == 0) return 0;
+    for (const CoarseJob &J : coarse_jobs(h, nullptr, 0)) eta_elems += (size_t)(J.n3 / 3);
+    return sizeof(double) * (inv_elems + eta_elems) + sizeof(int) * (size_t)h->nprob;
+}
+
 ohm_status ensure_coarse_storage(ohm_hier *h)
 {
     size_t inv_elems = 0, aug_elems = 0;

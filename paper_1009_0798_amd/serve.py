@@ -1,16 +1,26 @@
 """Request server for Crank-Nicolson solves with continuous batching.
 
-Requests (an AMR hierarchy, B and eta per level, dt) arrive over time.  A
-request is admitted once its device footprint (fields plus solver workspace)
-fits in the HBM budget that completed requests have released.  Each of
-``n_streams`` workers takes every admitted request that is waiting when it
-becomes free, builds one multi-problem handle for them, and runs the step on
-its own HIP stream; a batch that arrives while another is on the GPU starts
-on the next free stream, so their work overlaps on the device.  Results stay
-bitwise equal to a solve alone: every reduction is per problem in a fixed
-order.  Fields travel through pinned host buffers in both directions; a
-request's ``result`` arrays are views of its batch's pinned output buffer,
-which stays allocated until every result of the batch has been released.
+Requests (an AMR hierarchy, B and eta per level, dt) arrive over time.  The
+server keeps *slots* resident in HBM: a slot is a single-problem handle for
+one request shape (base box, cell width, block lists), device buffers for B
+and eta of that shape, and the step's workspace.  A request is admitted when
+an idle slot of its shape exists, or when the HBM budget left over by every
+resident slot (busy or idle) fits a new one, after evicting idle slots of
+other shapes, least recently used first.  Admission is first come, first
+served.
+
+``n_streams`` workers, each with its own HIP stream, take admitted requests
+one at a time: the request's fields go into its slot through pinned host
+memory (asynchronous copies on the worker's stream), the step runs, the result
+comes back the same way.  The step synchronises its stream once per outer
+iteration, so the outer iterations of all requests in flight interleave on
+the device: a request that arrives while others are being solved starts as
+soon as a worker is free, and its iterations run between theirs.  A slot keeps
+its workspace and field pointers, so the step's captured graphs are replayed
+for every request of that shape and repeated shapes build no handle.  Each
+result equals the same request solved alone (same single-problem handle,
+every reduction per problem in a fixed order); a request's ``result`` arrays
+are views of pinned host buffers of its own.
 
 All arithmetic runs in the HIP library; this module only schedules.
 """
@@ -20,7 +30,7 @@ import ctypes
 import dataclasses
 import threading
 import time
-from collections import deque
+from collections import OrderedDict, deque
 
 import numpy as np
 
@@ -46,6 +56,7 @@ class Request:
     stats: dict | None = None
     status: int = -1
     error: str = ""
+    slot_reused: bool = False
 
     @property
     def cells(self) -> int:
@@ -58,49 +69,120 @@ class Request:
         return tot
 
 
-def footprint(req: Request, opts) -> int:
-    """Device bytes of one request solved alone: B and eta per level plus the
-    solver workspace."""
-    import torch
-    h = Hierarchy([(req.base_blocks, req.dx0, req.levels)], torch.cuda.current_stream())
+def shape_key(req: Request):
+    """Requests with equal keys share slots: same base box, cell width and
+    block lists."""
+    blk = b"".join(np.ascontiguousarray(l, dtype=np.int32).tobytes() + b"|" for l in req.levels)
+    return (tuple(int(b) for b in req.base_blocks), float(req.dx0), blk)
+
+
+def _workspace_bytes(h: Hierarchy, opts) -> int:
     nb = ctypes.c_size_t()
     _lib.check(_lib.lib().ohm_cn_workspace_size(h.h, ctypes.byref(opts), ctypes.byref(nb)))
-    h.close()
-    fields = sum(4 * len(blk) * 512 * 8 for blk in req.levels)
-    return int(nb.value) + fields
+    return int(nb.value)
+
+
+def _field_bytes(req: Request) -> int:
+    return sum(4 * len(blk) * 512 * 8 for blk in req.levels)
+
+
+def footprint(req: Request, opts) -> int:
+    """Device bytes of a slot for the request's shape: the handle's own
+    memory, B and eta, and the step's workspace (a throwaway handle sizes it)."""
+    import torch
+    h = Hierarchy([(req.base_blocks, req.dx0, req.levels)], torch.cuda.current_stream())
+    try:
+        return h.device_bytes() + _field_bytes(req) + _workspace_bytes(h, opts) + 256
+    finally:
+        h.close()
+
+
+class Slot:
+    """A resident single-problem handle with B, eta and workspace on the device
+    and pinned host staging for the inputs."""
+
+    def __init__(self, req: Request, opts, stream):
+        import torch
+        self.key = shape_key(req)
+        self.h = Hierarchy([(req.base_blocks, req.dx0, req.levels)], stream)
+        nb = [len(l) for l in req.levels]
+        self.B = [torch.empty((3, n, 8, 8, 8), dtype=torch.float64, device="cuda") for n in nb]
+        self.E = [torch.empty((1, n, 8, 8, 8), dtype=torch.float64, device="cuda") for n in nb]
+        self.pin_B = [torch.empty((3, n, 8, 8, 8), dtype=torch.float64, pin_memory=True) for n in nb]
+        self.pin_E = [torch.empty((1, n, 8, 8, 8), dtype=torch.float64, pin_memory=True) for n in nb]
+        self.ws = Workspace()
+        self.ws.get(_workspace_bytes(self.h, opts))
+        self.bytes = self.h.device_bytes() + _field_bytes(req) + self.ws.buf.numel()
+        self.last_used = 0.0
+
+    def solve(self, req: Request, opts, stream):
+        """The request's step in this slot on `stream`; returns (status,
+        stats, results as views of new pinned buffers)."""
+        import torch
+        with torch.cuda.stream(stream):
+            for l in range(len(self.B)):
+                self.pin_B[l].copy_(torch.from_numpy(np.ascontiguousarray(req.B[l])))
+                self.pin_E[l][0].copy_(torch.from_numpy(np.ascontiguousarray(req.eta[l])))
+                self.B[l].copy_(self.pin_B[l], non_blocking=True)
+                self.E[l].copy_(self.pin_E[l], non_blocking=True)
+            st, stats = ohm_cn_step(self.h, self.B, self.E, req.dt, opts, self.ws, stream=stream)
+            out = []
+            for b in self.B:
+                o = torch.empty(b.shape, dtype=b.dtype, pin_memory=True)
+                o.copy_(b, non_blocking=True)
+                out.append(o)
+            stream.synchronize()
+        return st, stats, [o.numpy() for o in out]
+
+    def close(self):
+        self.h.close()
+        self.B = self.E = self.pin_B = self.pin_E = None
+        self.ws.buf = None
 
 
 class Server:
-    def __init__(self, hbm_budget: int, n_streams: int = 2, max_batch: int = 32, precision: int = 1,
-                 rtol: float = 1e-10, **schedule):
+    def __init__(self, hbm_budget: int, n_streams: int = 4, precision: int = 1, rtol: float = 1e-10, **schedule):
         """``schedule``: further ``ohm_cn_opts`` fields (nu_pre, nu_post,
-        nu_coarse, cycle, outer) applied to every batch."""
+        nu_coarse, cycle, outer, ...) applied to every request."""
         self.budget = int(hbm_budget)
-        self.free = int(hbm_budget)
+        self.resident = 0                   # bytes of resident slots (busy, idle or being built)
         self.n_streams = n_streams
-        self.max_batch = max_batch
         self.opts = default_opts(rtol=rtol, precision=precision, max_iters=300, **schedule)
         self.lock = threading.Condition()
         self.waiting: deque = deque()       # arrived, not admitted
         self.admitted: deque = deque()      # admitted, not started
+        self.assigned: dict = {}            # rid -> idle slot it will reuse (None: a new slot)
+        self.idle: OrderedDict = OrderedDict()   # (key, id) -> idle slot, least recently used first
+        self.to_close: list = []            # evicted slots, closed by a worker
         self.finished: list = []
         self.closed = False
-        self.streams = None             # one HIP stream per worker, made by serve()
+        self.streams = None                 # one HIP stream per worker, made by serve()
         self.t0 = time.perf_counter()
-        self.fp: dict = {}
+        self.fp: dict = {}                  # shape key -> slot bytes
+        self.keys: dict = {}                # rid -> shape key
+        self.built = 0                      # slots built
+        self.reused = 0                     # requests served by an idle slot
+
+    @property
+    def free(self) -> int:
+        return self.budget - self.resident
 
     def now(self) -> float:
         return time.perf_counter() - self.t0
 
     # -- admission -------------------------------------------------------------
     def submit(self, req: Request):
-        # sizing builds a throwaway handle: done outside the lock so that
-        # workers are not held up; a request the library rejects (blocks
-        # outside the base grid, improper nesting ...) finishes with its status
-        try:
-            fp, err = footprint(req, self.opts), None
-        except _lib.OhmError as e:
-            fp, err = None, e
+        # sizing builds a throwaway handle for a shape seen the first time:
+        # done outside the lock so that workers are not held up; a request the
+        # library rejects (blocks outside the base grid, improper nesting ...)
+        # finishes with its status
+        key = shape_key(req)
+        fp, err = self.fp.get(key), None
+        if fp is None:
+            try:
+                fp = footprint(req, self.opts)
+            except _lib.OhmError as e:
+                err = e
         with self.lock:
             if err is None and fp > self.budget:
                 err = _lib.OhmError(_lib.OHM_ERR_NOMEM, f"footprint {fp} B exceeds the budget {self.budget} B")
@@ -109,27 +191,52 @@ class Server:
                 req.done = self.now()
                 self.finished.append(req)
                 return
-            self.fp[req.rid] = fp
+            self.fp[key] = fp
+            self.keys[req.rid] = key
             self.waiting.append(req)
             self._admit()
             self.lock.notify_all()
 
+    def _idle_of(self, key):
+        for k in self.idle:
+            if k[0] == key:
+                return k
+        return None
+
     def _admit(self):
-        while self.waiting and self.fp[self.waiting[0].rid] <= self.free:
-            r = self.waiting.popleft()
-            self.free -= self.fp[r.rid]
+        """First come, first served: the head request takes an idle slot of
+        its shape, or room for a new one (idle slots of other shapes are
+        evicted, least recently used first)."""
+        while self.waiting:
+            r = self.waiting[0]
+            key = self.keys[r.rid]
+            k = self._idle_of(key)
+            if k is not None:
+                slot = self.idle.pop(k)
+                self.assigned[r.rid] = slot
+            else:
+                need = self.fp[key]
+                while self.free < need and self.idle:
+                    _, old = self.idle.popitem(last=False)
+                    self.resident -= old.bytes
+                    self.to_close.append(old)
+                if self.free < need:
+                    return
+                self.resident += need
+                self.assigned[r.rid] = None
+            self.waiting.popleft()
             r.admitted = self.now()
             self.admitted.append(r)
 
     def cancel(self, rid: int) -> bool:
-        """Drop a request that has not started; its budget is released."""
+        """Drop a request that has not started; a slot it had is released."""
         with self.lock:
             for q in (self.waiting, self.admitted):
                 for r in list(q):
                     if r.rid == rid:
                         q.remove(r)
                         if q is self.admitted:
-                            self.free += self.fp[rid]
+                            self._release(r, self.assigned.pop(rid))
                         r.status = -2
                         r.done = self.now()
                         self.finished.append(r)
@@ -138,100 +245,95 @@ class Server:
                         return True
         return False
 
+    def _release(self, r, slot):
+        """Back into the idle pool (a slot), or the reservation returned."""
+        if slot is None:
+            self.resident -= self.fp[self.keys[r.rid]]
+        else:
+            slot.last_used = self.now()
+            self.idle[(slot.key, id(slot))] = slot
+
     # -- workers ---------------------------------------------------------------
-    def _take_batch(self):
+    def _take(self):
         with self.lock:
             while not self.admitted and not (self.closed and not self.waiting):
                 self.lock.wait(timeout=0.05)
             if not self.admitted:
-                return None
-            batch = []
-            while self.admitted and len(batch) < self.max_batch:
-                batch.append(self.admitted.popleft())
-            return batch
+                return None, None, []
+            r = self.admitted.popleft()
+            slot = self.assigned.pop(r.rid)
+            if slot is None:
+                # a slot of its shape may have become idle since admission:
+                # take it and return the reservation
+                k = self._idle_of(self.keys[r.rid])
+                if k is not None:
+                    slot = self.idle.pop(k)
+                    self.resident -= self.fp[self.keys[r.rid]]
+            closing, self.to_close = self.to_close, []
+            return r, slot, closing
 
-    def _run_batch(self, batch, stream, ws):
-        import torch
-        t_start = self.now()
-        for r in batch:
-            r.started = t_start
-        with torch.cuda.stream(stream):
-            h = Hierarchy([(r.base_blocks, r.dx0, r.levels) for r in batch], stream)
-            try:
-                # the requests' fields are gathered into pinned host buffers and
-                # copied asynchronously on this worker's stream (pageable copies
-                # run at a fraction of the link's rate); results come back the
-                # same way and are handed out as views of the pinned buffers
-                nlev = max(len(r.levels) for r in batch)
-                B, E = [], []
-                for l in range(nlev):
-                    bl = [r.B[l] for r in batch if l < len(r.levels)]
-                    el = [r.eta[l] for r in batch if l < len(r.levels)]
-                    hb = torch.empty((3, sum(b.shape[1] for b in bl)) + bl[0].shape[2:], dtype=torch.float64,
-                                     pin_memory=True)
-                    torch.cat([torch.from_numpy(b) for b in bl], dim=1, out=hb)
-                    he = torch.empty((sum(e.shape[0] for e in el),) + el[0].shape[1:], dtype=torch.float64,
-                                     pin_memory=True)
-                    torch.cat([torch.from_numpy(e) for e in el], dim=0, out=he)
-                    he = he[None]
-                    B.append(hb.to("cuda", non_blocking=True))
-                    E.append(he.to("cuda", non_blocking=True))
-                st, stats = ohm_cn_step(h, B, E, [r.dt for r in batch], self.opts, ws, stream=stream)
-                pinned_out = []
-                for b in B:
-                    o = torch.empty(b.shape, dtype=b.dtype, pin_memory=True)
-                    o.copy_(b, non_blocking=True)
-                    pinned_out.append(o)
-                stream.synchronize()
-                outs = [o.numpy() for o in pinned_out]
-            finally:
-                h.close()           # hipFree inside waits for the device
-        off = [0] * nlev
-        done = self.now()
-        for i, r in enumerate(batch):
-            r.result = []
-            for l in range(len(r.levels)):
-                nb = len(r.levels[l])
-                r.result.append(outs[l][:, off[l]:off[l] + nb])
-                off[l] += nb
-            r.stats = stats[i]
-            r.status = 0 if stats[i]["rel_res"] <= self.opts.rtol else _lib.OHM_ERR_NOCONV
-            r.done = done
+    def _make_slot(self, req, stream):
+        return Slot(req, self.opts, stream)
 
-    def _finish(self, batch):
-        """Return the batch's budget, record its requests, admit what now fits."""
-        with self.lock:
-            for r in batch:
-                self.free += self.fp[r.rid]
-                self.finished.append(r)
-            self._admit()
-            self.lock.notify_all()
+    def _solve(self, req, slot, stream):
+        return slot.solve(req, self.opts, stream)
 
     def _worker(self, k):
-        ws = Workspace()
+        stream = self.streams[k]
         while True:
-            batch = self._take_batch()
-            if batch is None:
+            r, slot, closing = self._take()
+            for s in closing:
+                s.close()
+            if r is None:
                 return
+            r.started = self.now()
+            reused = slot is not None
+            built = False
             try:
-                self._run_batch(batch, self.streams[k], ws)
+                if slot is None:
+                    slot = self._make_slot(r, stream)
+                    built = True
+                    with self.lock:
+                        # the reservation becomes the slot's own size
+                        self.resident += slot.bytes - self.fp[self.keys[r.rid]]
+                        self.built += 1
+                st, stats, out = self._solve(r, slot, stream)
+                r.result, r.stats = out, stats[0]
+                r.status = 0 if stats[0]["rel_res"] <= self.opts.rtol else _lib.OHM_ERR_NOCONV
+                r.slot_reused = reused
             except Exception as e:
-                # a batch that raises ends each of its requests with the error;
-                # the worker and the batch's budget stay in service
-                now = self.now()
-                for r in batch:
-                    r.status = getattr(e, "status", _lib.OHM_ERR_HIP)
-                    r.error, r.result, r.stats, r.done = str(e), None, None, now
-            self._finish(batch)
-            ws.buf = None       # release the workspace between batches
+                # a request that raises finishes with the error; its slot (if
+                # built) is closed and its memory returned, the worker goes on
+                r.status = getattr(e, "status", _lib.OHM_ERR_HIP)
+                r.error, r.result, r.stats = str(e), None, None
+                if slot is not None:
+                    slot.close()
+                    with self.lock:
+                        self.resident -= slot.bytes
+                    slot = None
+                else:
+                    with self.lock:
+                        self.resident -= self.fp[self.keys[r.rid]]
+            r.done = self.now()
+            with self.lock:
+                if reused:
+                    self.reused += 1
+                if slot is not None:
+                    slot.last_used = r.done
+                    self.idle[(slot.key, id(slot))] = slot
+                self.finished.append(r)
+                self._admit()
+                self.lock.notify_all()
 
     def serve(self, requests, arrival_times):
         """Feed ``requests`` at ``arrival_times`` (seconds from now) and serve
-        them; returns the finished requests."""
+        them; returns the finished requests.  Idle slots stay resident for a
+        later call."""
         import torch
         if self.streams is None:
             self.streams = [torch.cuda.Stream() for _ in range(self.n_streams)]
         self.t0 = time.perf_counter()
+        self.closed = False
         workers = [threading.Thread(target=self._worker, args=(k,), daemon=True) for k in range(self.n_streams)]
         for w in workers:
             w.start()
@@ -248,6 +350,18 @@ class Server:
             w.join()
         return sorted(self.finished, key=lambda r: r.rid)
 
+    def shutdown(self):
+        """Close every idle slot and return its memory."""
+        with self.lock:
+            slots = list(self.idle.values())
+            self.idle.clear()
+            for s in slots:
+                self.resident -= s.bytes
+            slots += self.to_close
+            self.to_close = []
+        for s in slots:
+            s.close()
+
 
 def poisson_arrivals(rate: float, n: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
@@ -260,4 +374,5 @@ def latency_report(finished) -> dict:
     span = (max(r.done for r in ok) - min(r.arrival for r in ok)) if ok else 1.0
     return {"completed": len(ok), "rejected": sum(1 for r in finished if r.status not in (0,)),
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "cells_per_s": float(sum(r.cells for r in ok) / max(span, 1e-9))}
+            "cells_per_s": float(sum(r.cells for r in ok) / max(span, 1e-9)),
+            "requests_per_s": float(len(ok) / max(span, 1e-9))}

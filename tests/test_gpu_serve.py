@@ -1,7 +1,10 @@
 """Serving: requests of mixed sizes and 1-2 AMR levels arriving over time are
-admitted by footprint, batched across two streams, and each served result
-equals the same request solved alone (bitwise: per-problem reductions in a
-fixed order), and meets the FP64 residual tolerance."""
+admitted by footprint into resident slots, solved on several streams at once
+(their outer iterations interleave), and each served result equals the same
+request solved alone (bitwise: per-problem reductions in a fixed order) and
+meets the FP64 residual tolerance by the oracle's composite residual."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -41,11 +44,17 @@ def test_served_equals_alone(precision):
     from paper_1009_0798_amd.serve import Server, latency_report, poisson_arrivals
     announce("serve: served == alone")
     reqs = _requests(10, seed=71)
-    srv = Server(hbm_budget=2 << 30, n_streams=2, max_batch=4, precision=precision)
+    srv = Server(hbm_budget=2 << 30, n_streams=3, precision=precision)
     done = srv.serve(reqs, poisson_arrivals(200.0, len(reqs), seed=7))
+    # a second wave repeats three shapes (all distinct): their idle slots are reused
+    again = [dataclasses.replace(reqs[i], rid=10 + k, result=None, stats=None, status=-1)
+             for k, i in enumerate((0, 1, 2))]
+    built = srv.built
+    done = srv.serve(again, poisson_arrivals(200.0, len(again), seed=8))
     rep = latency_report(done)
-    print(rep)
-    assert rep["completed"] == len(reqs)
+    print(rep, "slots built", srv.built, "reused", srv.reused)
+    assert rep["completed"] == len(reqs) + len(again)
+    assert srv.built == built and srv.reused >= 3
     for r in done:
         assert r.status == 0 and r.stats["rel_res"] <= 1e-10
         st, stats, alone = _alone(r, precision)
@@ -95,7 +104,7 @@ def test_served_full_size_against_oracle(n0, L):
     from paper_1009_0798_amd.serve import Server
     announce(f"serve: full-size request base {n0}^3, {L} levels")
     r = _pool_request(n0, L, seed=700 + n0 + L)
-    srv = Server(hbm_budget=64 << 30, n_streams=1, max_batch=1, precision=1)
+    srv = Server(hbm_budget=64 << 30, n_streams=1, precision=1)
     done = srv.serve([r], [0.0])
     assert done[0].status == 0, done[0].error
     rel = _oracle_rel_residual(done[0])
