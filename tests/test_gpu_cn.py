@@ -539,3 +539,40 @@ def test_amr_multigrid_one_iteration_equals_the_oracle(fmg, precision):
     print("stats", stats, "max err / max correction", err / emax,
           "oracle max|R|", max(np.abs(R0[l]).max() for l in range(L)), "->", max(np.abs(r1[l]).max() for l in range(L)))
     assert err <= (1e-11 if precision == 0 else 2e-5) * emax
+
+
+def test_tuned_schedule_converges_to_the_oracle():
+    """The autotuner (quick table: BiCGStab around V-cycles, every pre/post
+    and coarse sweep count, mixed precision) on a three-problem batch picks a
+    schedule that converges, and a step with it meets the whole-step bound
+    against the oracle for every problem."""
+    import paper_1009_0798_amd as ohm
+    from paper_1009_0798_amd import tune
+    announce("tuner: chosen schedule against the oracle")
+    sizes, ms = [16, 24, 32], [20.0, 80.0, 200.0]
+    specs, Bs, Es, dts = [], [], [], []
+    for i, n in enumerate(sizes):
+        s = gen.uniform_spec(n)
+        specs.append(s)
+        Bs.append(gen.divfree(n, 2.0, seed=140 + i))
+        Es.append(gen.lognormal_eta(n, 2.0, seed=150 + i))
+        dts.append(gen.explicit_dt(s.dx0, 1.0, ms[i]))
+    H = ohm.Hierarchy([(s.base_blocks, s.dx0, s.levels) for s in specs])
+    B0 = cuda(np.concatenate([dense_to_blocks(B, s.levels[0]) for B, s in zip(Bs, specs)], axis=1))
+    E = cuda(np.concatenate([dense_to_blocks(e, s.levels[0])[None] for e, s in zip(Es, specs)], axis=1))
+    best, table = tune.tune(H, [B0], [E], dts, finest_dx=min(s.dx0 for s in specs), precisions=(1,),
+                            use_cache=False, quick=True)
+    print("best", best, "of", len(table))
+    assert sum(1 for _, t, _ in table if t is not None) >= len(table) // 2
+    Bt = [B0.clone()]
+    st, stats = ohm.ohm_cn_step(H, Bt, [E], dts, ohm.default_opts(rtol=RTOL, max_iters=200, **best))
+    assert st == 0
+    out = host(Bt[0])
+    o = 0
+    for i, s in enumerate(specs):
+        nb = len(s.levels[0])
+        got = blocks_to_dense(out[:, o:o + nb], s.levels[0], s.cells(0))
+        o += nb
+        ex, _ = mg.cn_step(Bs[i], Es[i], s.dx0, dts[i], rtol=1e-13)
+        S = ref.source(Bs[i], Es[i], s.dx0, dts[i])
+        assert np.linalg.norm(got - ex) <= _bound(np.linalg.norm(S), ex), i
