@@ -195,3 +195,44 @@ def test_step_operator_is_bounded_below_by_one(r):
     assert np.linalg.eigvalsh((A + A.T) / 2).min() < -1e-3 * np.abs(A).max()
     sv = np.linalg.svd(L, compute_uv=False)
     assert sv.min() >= 1 - 1e-9, sv.min()
+
+
+def test_null_space_is_the_one_dimensional_gradients():
+    """The flux divergence of eqs. (8)-(11) annihilates exactly the fields
+    (f(x), g(y), h(z)) -- every flux term is a transverse difference of a
+    component along its own axis or of another component, which vanish for
+    such fields -- for any resistivity; with constant eta nothing else is
+    annihilated: the symbol M(k) is singular only on the axis-aligned
+    wavevectors, 3 n zero eigenvalues on an n^3 grid (constants included),
+    while the central-difference gradient direction cc(k) of any other
+    wavevector keeps the Rayleigh quotient (h^2 / 4) sum_{c != d} cc_c^2 s_d^4
+    / |cc|^2 > 0 (fourth order in k: the near-null space of the step operator
+    that no discrete gradient spans exactly)."""
+    n, h = 8, 1.0 / 8
+    rng = np.random.default_rng(5)
+    eta = np.exp(rng.standard_normal((n, n, n)))
+    x = np.arange(n)
+    B = np.zeros((3, n, n, n))
+    B[0] = rng.standard_normal(n)[None, None, :]          # f(x)
+    B[1] = rng.standard_normal(n)[None, :, None]          # g(y)
+    B[2] = rng.standard_normal(n)[:, None, None]          # h(z)
+    assert np.abs(ref.apply(B, eta, h, 1.0) - B).max() <= 1e-13 * np.abs(B).max()
+    # a field that is not of that form is not annihilated
+    C = B.copy()
+    C[0] += np.sin(2 * np.pi * x / n)[None, :, None]
+    assert np.abs(ref.apply(C, eta, h, 1.0) - C).max() > 1e-3
+    k = 2 * np.pi * np.fft.fftfreq(n, d=h)
+    KZ, KY, KX = np.meshgrid(k, k, k, indexing="ij")
+    M = closed.symbol(KX, KY, KZ, h)
+    ev = np.linalg.eigvalsh(M)
+    scale = np.abs(ev).max()
+    assert int((ev < 1e-12 * scale).sum()) == 3 * n
+    s = np.stack([(2 / h) * np.sin(K * h / 2) for K in (KX, KY, KZ)], -1)
+    cc = np.stack([np.sin(K * h) / h for K in (KX, KY, KZ)], -1)
+    multi = ((KX != 0).astype(int) + (KY != 0) + (KZ != 0)) >= 2
+    c2 = (cc * cc).sum(-1)
+    ok = multi & (c2 > 1e-12 * scale)
+    rq = np.einsum("...i,...ij,...j->...", cc, M, cc)[ok] / c2[ok]
+    want = (h * h / 4) * sum(cc[..., a] ** 2 * s[..., b] ** 4 for a in range(3) for b in range(3) if a != b)[ok] / c2[ok]
+    assert np.allclose(rq, want, rtol=1e-10, atol=1e-12 * scale)
+    assert rq.min() > 0
