@@ -162,7 +162,10 @@ ohm_status ohm_residual(ohm_hier *h, int32_t level, const void *B, const void *B
  * holds until the process ends.  Differences from ohm_residual:
  *   norms  : DEVICE double[nprob][3][2] (sum R_c^2, max |R_c|), written
  *            asynchronously on `stream`; the call never synchronises;
- *   lam_dt : host double[nprob], copied to the device before the call returns.
+ *   lam_dt : host double[nprob], read when the call enqueues its work and
+ *            passed to the device as kernel arguments (so is the block range
+ *            of each problem): nothing is copied from host memory later, and
+ *            a graph captured from the call replays the values it was given.
  * Returns OHM_ERR_NOMEM, before any launch, when the level needs more scratch
  * than the array holds: 48 bytes per block of `level` plus about 72 bytes per
  * problem with norms (about 87,000 blocks, 4.4e7 cells, for one problem).

@@ -2,8 +2,11 @@
 // for callers that cannot allocate device memory.  Its scratch (the per-problem
 // coefficients, block ranges, the reduction's per-block partials and its
 // per-problem sums) lives in one file-scope device array of fixed size instead
-// of the handle's buffers, and the norms are written to caller device memory
-// without a synchronisation.  The kernels are those of ohm_residual.
+// of the handle's buffers, the per-call host scalars travel as kernel
+// arguments, and the norms are written to caller device memory without a
+// synchronisation or a copy, so the call can be captured into a HIP graph.
+// The stencil and reduction kernels are those of ohm_residual.
+#include <algorithm>
 #include <cmath>
 #include <mutex>
 #include <vector>
@@ -43,6 +46,29 @@ ohm_status scratch_ptr(char **out)
 }
 
 inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Per-call host scalars (coefficients, block ranges) reach the scratch through
+// kernel arguments, 16 problems per launch: the values are copied when the
+// kernel is enqueued, so a call captured into a graph replays them as they
+// were, and no host buffer has to outlive the call.
+constexpr int CHUNK = 16;
+struct ScalarChunk {
+    int first, n;
+    double coef[CHUNK];
+    long long lo[CHUNK], hi[CHUNK];
+};
+
+__global__ void __launch_bounds__(64) k_put_scalars(ScalarChunk c, double *__restrict__ coef,
+                                                    long long *__restrict__ rg)
+{
+    const int t = threadIdx.x;
+    if (t >= c.n) return;
+    coef[c.first + t] = c.coef[t];
+    if (rg) {
+        rg[2 * (c.first + t)] = c.lo[t];
+        rg[2 * (c.first + t) + 1] = c.hi[t];
+    }
+}
 
 // [nprob][6] = (sum R_x^2, sum R_y^2, sum R_z^2, max|R_x|, max|R_y|, max|R_z|)
 // -> [nprob][3][2] = (sum R_c^2, max |R_c|) per component
@@ -88,9 +114,20 @@ extern "C" ohm_status ohm_residual_noalloc(ohm_hier *h, int32_t level, const voi
     char *base = nullptr;
     OHM_TRY(scratch_ptr(&base));
     double *coef = (double *)(base + o_coef);
-    // the host arrays are consumed by the copies (pageable host memory is
-    // staged before hipMemcpyAsync returns)
-    OHM_HIP(hipMemcpyAsync(coef, lam_dt, 8 * np, hipMemcpyHostToDevice, stream));
+    long long *d_rg = norms ? (long long *)(base + o_rng) : nullptr;
+    for (size_t p0 = 0; p0 < np; p0 += CHUNK) {
+        ScalarChunk c{};
+        c.first = (int)p0;
+        c.n = (int)std::min<size_t>(CHUNK, np - p0);
+        for (int t = 0; t < c.n; ++t) {
+            const ohm_prob_host &P = h->probs[p0 + t];
+            c.coef[t] = lam_dt[p0 + t];
+            c.lo[t] = level >= 0 && level < P.nlevels ? P.boff[level] : 0;
+            c.hi[t] = level >= 0 && level < P.nlevels ? P.boff[level] + P.nb[level] : 0;
+        }
+        k_put_scalars<<<1, 64, 0, stream>>>(c, coef, d_rg);
+        OHM_TRY(check_launch("scalar upload"));
+    }
     double *part = norms ? (double *)(base + o_part) : nullptr;
     const long long cs = level >= 0 ? (long long)nb * NC : h->dense_cells[-level];
     if (level >= 0) {
@@ -114,15 +151,7 @@ extern "C" ohm_status ohm_residual_noalloc(ohm_hier *h, int32_t level, const voi
         OHM_TRY(st);
     }
     if (norms) {
-        std::vector<long long> rg(2 * np);
-        for (size_t p = 0; p < np; ++p) {
-            const ohm_prob_host &P = h->probs[p];
-            rg[2 * p] = level < P.nlevels ? P.boff[level] : 0;
-            rg[2 * p + 1] = level < P.nlevels ? P.boff[level] + P.nb[level] : 0;
-        }
-        long long *d_rg = (long long *)(base + o_rng);
         double *sums = (double *)(base + o_sum);
-        OHM_HIP(hipMemcpyAsync(d_rg, rg.data(), 16 * np, hipMemcpyHostToDevice, stream));
         OHM_TRY(launch_reduce_problem(h->nprob, 1, d_rg, part, 6, 3, sums, stream));
         const int n = 6 * h->nprob;
         k_norm_pairs<<<(n + 255) / 256, 256, 0, stream>>>(h->nprob, sums, norms);

@@ -2,7 +2,8 @@
 norms, no synchronisation) against ohm_residual on the same inputs: the same
 kernels in the same order, so R and the norms must agree bit for bit.  Two
 calls in a row, the second on a smaller input, then an AMR level with ghost
-blocks, then a level too large for the array (rejected before any launch)."""
+blocks, a call captured into a HIP graph and replayed, then a level too large
+for the array (rejected before any launch)."""
 import numpy as np
 import pytest
 
@@ -92,6 +93,48 @@ def test_noalloc_residual_amr_level_with_ghosts():
     ohm.ohm_fill_ghosts(H, 1, Ec, Eg)
     S1 = cuda(np.random.default_rng(9).standard_normal(tuple(B1.shape)))
     _compare(H, 1, B1, S1, E1, 1e-4, Bg, Eg)
+
+
+def test_noalloc_residual_captured_in_a_graph():
+    """18 problems (8^3 and 16^3, each its own lam_dt: the per-call scalars go
+    to the device in two kernel-argument chunks), the call captured once into a
+    HIP graph after an eager call, then replayed three times with new B written
+    eagerly in between; every replay equals ohm_residual on the same inputs."""
+    import torch
+    import paper_1009_0798_amd as ohm
+    announce("noalloc residual: 18 problems, captured into a graph, 3 replays")
+    specs, Bs, Es, Ss, lam = [], [], [], [], []
+    for i in range(18):
+        n = 8 if i % 2 else 16
+        spec, B, eta, S, dt = _problem(n, 400 + 2 * i)
+        specs.append(spec)
+        Bs.append(dense_to_blocks(B, spec.levels[0]))
+        Es.append(dense_to_blocks(eta, spec.levels[0])[None])
+        Ss.append(dense_to_blocks(S, spec.levels[0]))
+        lam.append(0.5 * dt * (1.0 + 0.1 * i))
+    H = ohm.Hierarchy([(s.base_blocks, s.dx0, s.levels) for s in specs])
+    assert H.nprob == 18
+    Bt, Et, St = cuda(np.concatenate(Bs, 1)), cuda(np.concatenate(Es, 1)), cuda(np.concatenate(Ss, 1))
+    R = torch.empty_like(Bt)
+    nrm = torch.zeros(6 * H.nprob, dtype=torch.float64, device="cuda")
+    ohm.ohm_residual_noalloc(H, 0, Bt, St, Et, lam, R=R, norms=nrm)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        ohm.ohm_residual_noalloc(H, 0, Bt, St, Et, lam, R=R, norms=nrm)
+    rng = np.random.default_rng(17)
+    for k in range(3):
+        Bt.copy_(torch.from_numpy(rng.standard_normal(tuple(Bt.shape))).cuda())
+        R.fill_(float("nan"))
+        nrm.fill_(float("nan"))
+        g.replay()
+        torch.cuda.synchronize()
+        R1 = torch.empty_like(Bt)
+        n1 = ohm.ohm_residual(H, 0, Bt, St, Et, lam, R=R1, norms=True)
+        assert torch.equal(R, R1), k
+        got = nrm.cpu().numpy().reshape(H.nprob, 3, 2)
+        assert np.array_equal(got, n1), (k, got, n1)
+    del g
 
 
 def test_noalloc_residual_rejects_a_level_beyond_the_array():
