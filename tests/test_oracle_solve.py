@@ -60,6 +60,43 @@ def test_fmg_reduces_residual():
     assert np.linalg.norm(r) < 0.05 * np.linalg.norm(S)
 
 
+def _fmg_case(n):
+    h = 1.0 / n
+    eta = gen.lognormal_eta(n, 3.0, seed=21)
+    lam_dt = 0.5 * gen.explicit_dt(h, 1.0, 20.0)
+    return mg.hierarchy(eta, h, lam_dt), gen.divfree(n, 3.0, seed=22), eta, h, lam_dt
+
+
+@pytest.mark.parametrize("n", [8, 16])
+def test_fmg_with_many_cycles_reaches_the_solution(n):
+    """FMG iterates the residual equation on the finest level, so with enough
+    V-cycles per level it returns L^{-1} r whatever its start: 2 and 3 levels,
+    log-normal eta over three decades.  The result satisfies L X = S to
+    rounding (L the oracle's operator, pinned on its own), and at 8^3 equals
+    SuperLU's solution."""
+    lv, S, eta, h, lam_dt = _fmg_case(n)
+    assert len(lv) == (2 if n == 8 else 3)
+    X = mg.fmg(lv, S, n_v=40)
+    assert np.linalg.norm(ref.residual(X, S, eta, h, lam_dt)) <= 1e-13 * np.linalg.norm(S)
+    if n == 8:
+        Xd = mg.direct_solve(eta, h, lam_dt, S)
+        assert np.linalg.norm(X - Xd) <= 1e-12 * np.linalg.norm(Xd)
+
+
+def test_fmg_start_beats_a_vcycle_from_zero():
+    """What makes it full multigrid: each level starts from the interpolated
+    coarser solution, so for a smooth right-hand side one V-cycle per level
+    leaves a small fraction of the error one V-cycle from zero leaves (0.14
+    here; without the interpolated start the two coincide).  The exact answer
+    is FMG's limit, whose residual is checked."""
+    lv, S, eta, h, lam_dt = _fmg_case(16)
+    X = mg.fmg(lv, S, n_v=40)
+    assert np.linalg.norm(ref.residual(X, S, eta, h, lam_dt)) <= 1e-13 * np.linalg.norm(S)
+    e_fmg = np.linalg.norm(mg.fmg(lv, S, n_v=1) - X)
+    e_v = np.linalg.norm(mg.vcycle(lv, S) - X)
+    assert e_fmg < 0.3 * e_v, (e_fmg, e_v)
+
+
 def test_heat_factor_and_paper_amplitude():
     """Sinusoidal test (section 3.1): B_z = sin(k.r), k = 2 pi (1, 2, 0),
     eta = 1, box [0,1] x [0,1/2] x [0,1/4].  The z-only field evolves as the
