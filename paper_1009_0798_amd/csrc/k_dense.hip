@@ -342,7 +342,154 @@ k_coarse_check(const CoarseJob *__restrict__ jobs, const int *__restrict__ force
     if (threadIdx.x == 0) flags[blockIdx.x] = diff;
 }
 
-// Gauss-Jordan inversion with partial pivoting, one 32x32 workgroup per job.
+// Gauss-Jordan inversion with partial pivoting of a job with n <= 32 RG
+// unknowns, the matrix held in registers.  Thread t of the 1024-thread
+// workgroup owns rows ty + 32 i and columns tx + 32 j (i, j < RG) with
+// ty = t mod 32, tx = t / 32, so the 32 owners of a column are one half of a
+// wavefront.  Rows are never moved: step k takes as pivot the largest
+// |A[r][k]| over the rows not pivoted yet (the lowest row on ties), scales
+// that row and eliminates column k from every other row, and column k's
+// storage then holds the column of the inverse-in-progress that the augmented
+// form [A | I] would keep at the pivot row's identity column (in place).  With
+// p_k the pivot row of step k and k(r) the step row r was pivot in, the
+// inverse is inverse[k(r)][p_j] = S[r][j] for the stored matrix S.  Each step:
+// the owners of column k reduce the candidates across their half-wavefront
+// and publish the pivot and the multipliers, the pivot row's owners publish
+// the scaled row (LDS, double-buffered by step parity), and every thread
+// updates its 36 entries; nothing goes through global memory.  Column k sits
+// in register slot k / 32, a compile-time index in the unrolled outer loop.
+// Rows and columns at or beyond n are zero padding.  Against the augmented
+// kernel below (one job of 192 unknowns): about 0.5 ms instead of 1.1 ms.
+constexpr int RG = 6;
+
+__global__ void __launch_bounds__(1024)
+k_coarse_invert_reg(const CoarseJob *__restrict__ jobs, const int *__restrict__ flags,
+                    const double *__restrict__ aug, double *__restrict__ inv)
+{
+    if (!flags[blockIdx.x]) return;
+    const CoarseJob J = jobs[blockIdx.x];
+    const int n = J.n3, w = 2 * n;
+    if (n > 32 * RG) return;
+    const double *A0 = aug + J.aug_off;
+    const int ty = threadIdx.x & 31, tx = threadIdx.x >> 5;
+    __shared__ double prow[2][32 * RG], fcol[2][32 * RG];
+    __shared__ int piv_of_step[32 * RG], step_of_row[32 * RG];
+    __shared__ int sp;
+    __shared__ double spv;
+    double a[RG][RG];
+    bool used[RG];
+#pragma unroll
+    for (int i = 0; i < RG; ++i) {
+        const int r = ty + 32 * i;
+        used[i] = r >= n;
+#pragma unroll
+        for (int j = 0; j < RG; ++j) {
+            const int c = tx + 32 * j;
+            a[i][j] = (r < n && c < n) ? A0[(long long)r * w + c] : 0.0;
+        }
+    }
+    // column k = 32 jk + tk: jk is a compile-time register slot
+#pragma unroll
+    for (int jk = 0; jk < RG; ++jk) {
+        for (int tk = 0; tk < 32; ++tk) {
+            const int k = 32 * jk + tk;
+            if (k >= n) break;
+            const int buf = k & 1;
+            if (tx == tk) {
+                // a NaN ranks as infinite, so some row not pivoted yet is
+                // always chosen (a non-finite matrix gives a non-finite
+                // inverse, never an index outside the matrix); a lane without
+                // such rows offers -1 and row n
+                double best = -1.0, sg = 0.0;
+                int id = n;
+#pragma unroll
+                for (int i = 0; i < RG; ++i) {
+                    const double v = a[i][jk];
+                    const double av = v != v ? INFINITY : fabs(v);
+                    const bool take = !used[i] && av > best;
+                    best = take ? av : best;
+                    sg = take ? v : sg;
+                    id = take ? ty + 32 * i : id;
+                }
+                // a lane's candidate rows increase with i and a later row
+                // replaced an earlier one only when strictly larger: the
+                // lowest row index wins ties
+#pragma unroll
+                for (int off = 16; off > 0; off >>= 1) {
+                    const double ob = __shfl_xor(best, off, 32), os = __shfl_xor(sg, off, 32);
+                    const int oi = __shfl_xor(id, off, 32);
+                    const bool take = ob > best || (ob == best && oi < id);
+                    best = take ? ob : best;
+                    sg = take ? os : sg;
+                    id = take ? oi : id;
+                }
+                if (ty == 0) {
+                    sp = id;
+                    spv = sg;
+                    piv_of_step[k] = id;
+                    step_of_row[id] = k;
+                }
+#pragma unroll
+                for (int i = 0; i < RG; ++i) {
+                    const int r = ty + 32 * i;
+                    fcol[buf][r] = r == id ? -1.0 : a[i][jk];
+                }
+            }
+            __syncthreads();
+            const int p = sp, ip = p >> 5, tp = p & 31;
+            const double d = 1.0 / spv;
+            if (ty == tp) {
+                // the pivot row scaled by 1 / pivot; its column-k entry is d
+#pragma unroll
+                for (int j = 0; j < RG; ++j) {
+                    double v = a[0][j];
+#pragma unroll
+                    for (int i = 1; i < RG; ++i) v = i == ip ? a[i][j] : v;
+                    const int c = tx + 32 * j;
+                    prow[buf][c] = (c == k ? 1.0 : v) * d;
+                }
+#pragma unroll
+                for (int i = 0; i < RG; ++i) used[i] = used[i] || i == ip;
+            }
+            __syncthreads();
+            double f[RG], y[RG];
+#pragma unroll
+            for (int i = 0; i < RG; ++i) f[i] = fcol[buf][ty + 32 * i];
+#pragma unroll
+            for (int j = 0; j < RG; ++j) y[j] = prow[buf][tx + 32 * j];
+            // a - f y on every other row; the pivot row (multiplier -1, its
+            // entries scaled by 0) becomes the scaled row y; then column k
+            // becomes -f d (d on the pivot row)
+#pragma unroll
+            for (int i = 0; i < RG; ++i) {
+                const double keep = ty + 32 * i == p ? 0.0 : 1.0;
+#pragma unroll
+                for (int j = 0; j < RG; ++j) a[i][j] = fma(-f[i], y[j], a[i][j] * keep);
+            }
+            if (tx == tk) {
+#pragma unroll
+                for (int i = 0; i < RG; ++i) a[i][jk] = fma(-f[i], y[jk], 0.0);
+            }
+        }
+    }
+    __syncthreads();
+    // stored transposed, as the mat-vec reads it: X[c][r] = inverse[r][c]
+    double *X = inv + J.inv_off;
+#pragma unroll
+    for (int i = 0; i < RG; ++i) {
+        const int r = ty + 32 * i;
+        if (r >= n) continue;
+        const int row = step_of_row[r];
+#pragma unroll
+        for (int j = 0; j < RG; ++j) {
+            const int c = tx + 32 * j;
+            if (c < n) X[(long long)piv_of_step[c] * n + row] = a[i][j];
+        }
+    }
+}
+
+// Gauss-Jordan inversion with partial pivoting of a job with more than 32 RG
+// unknowns, one 32x32 workgroup per job, on the augmented matrix in memory.
 // Without a row exchange, step k only meets columns k .. n+k of the augmented
 // matrix [A | I] (the identity entries of the rows below k lie further right
 // and are untouched).  A row exchange brings row p's identity entry, at column
@@ -356,6 +503,7 @@ k_coarse_invert(const CoarseJob *__restrict__ jobs, const int *__restrict__ flag
     if (!flags[blockIdx.x]) return;
     const CoarseJob J = jobs[blockIdx.x];
     const int n = J.n3, w = 2 * n;
+    if (n <= 32 * RG) return;
     double *A = aug + J.aug_off;
     const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * 32 + tx;
     __shared__ double sval[1024];
@@ -739,8 +887,17 @@ ohm_status launch_coarse_build(ohm_hier *h, const double *const *eta_dense, cons
         dim3 g(maxn, (unsigned)njobs[d]);
         k_coarse_assemble<<<g, 256, 0, s>>>(jd, fl, eta_dense[d], aug);
         OHM_TRY(check_launch("coarse assemble"));
-        k_coarse_invert<<<(unsigned)njobs[d], dim3(32, 32), 0, s>>>(jd, fl, aug, h->d_coarse_inv);
-        OHM_TRY(check_launch("coarse invert"));
+        int minn = maxn;
+        for (const CoarseJob &J : coarse_jobs(h, nullptr, d)) minn = std::min(minn, J.n3);
+        // each kernel skips the jobs of the other's size range
+        if (minn <= 32 * RG) {
+            k_coarse_invert_reg<<<(unsigned)njobs[d], 1024, 0, s>>>(jd, fl, aug, h->d_coarse_inv);
+            OHM_TRY(check_launch("coarse invert (registers)"));
+        }
+        if (maxn > 32 * RG) {
+            k_coarse_invert<<<(unsigned)njobs[d], dim3(32, 32), 0, s>>>(jd, fl, aug, h->d_coarse_inv);
+            OHM_TRY(check_launch("coarse invert"));
+        }
     }
     return OHM_OK;
 }
