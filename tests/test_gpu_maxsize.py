@@ -127,3 +127,5 @@ def test_level_beyond_4gib_per_component_sweep_and_residual():
         assert np.abs(Bc[:, m] - b_or).max() <= 1e-12 * scale, (cell, Bc[:, m], b_or)
     print("worst relative difference: residual", worst_r, "sweep", worst_s)
     H.close()
+    del B, S, E, Bf, Sf, Ef, nbr, centre
+    torch.cuda.empty_cache()
