@@ -1,12 +1,14 @@
-"""The largest level class: a 832^3-cell level (104^3 blocks, 576 M cells),
-whose FP64 field arrays exceed 4 GiB per component, so the smoother leaves the
-fused sweep (32-bit offsets) for one 64-bit-indexed launch per colour.  One
-red-black sweep (eq. 19) and the residual with its norms (eq. 20) are checked
-at sampled cells against the oracle: each sampled cell's neighbourhood of
+"""One red-black sweep (eq. 19) and the residual with its norms (eq. 20) on
+full-size levels, checked at sampled cells against the oracle: the 128^3 and
+256^3 levels on which the benchmark times the fused sweep (one launch per
+sweep, 32-bit offsets), and the largest level class, an 832^3-cell level
+(104^3 blocks, 576 M cells) whose FP64 field arrays exceed 4 GiB per
+component, so the smoother leaves the fused sweep for one 64-bit-indexed
+launch per colour.  At sampled cells: each sampled cell's neighbourhood of
 radius 3 (a sweep reads radius 2) is copied into a 16^3 periodic box with the
 colour parity kept, the oracle sweeps or evaluates the box, and its centre is
-compared; the sample includes cells of the last blocks, which lie more than
-4 GiB (2^32 bytes) into each component array.  The norms are checked as properties of
+compared; the sample includes cells of the last blocks (at 832^3 more than
+4 GiB, 2^32 bytes, into each component array).  The norms are checked as properties of
 the returned residual (sum of squares and maximum per component)."""
 import numpy as np
 import pytest
@@ -18,21 +20,20 @@ from gpu_util import announce
 
 pytestmark = pytest.mark.gpu
 
-NBA = 104                      # blocks per axis
-N = 8 * NBA                    # cells per axis
 RAD = 3
 
 
-def _sample_cells(spec, rng):
+def _sample_cells(spec, rng, N):
     ijk = spec.levels[0]
     last = [tuple(int(v) for v in 8 * ijk[-1] + o) for o in ((0, 0, 0), (7, 7, 7), (3, 0, 7))]
-    faces = [(8 * 17 - 1, 5, 9), (8 * 17, 5, 9), (0, 0, 0), (N - 1, N - 1, N - 1), (N - 1, 0, 7)]
+    faces = [(8 * 9 - 1, 5, 9), (8 * 9, 5, 9), (0, 0, 0), (N - 1, N - 1, N - 1), (N - 1, 0, 7)]
     rand = [tuple(int(v) for v in rng.integers(0, N, size=3)) for _ in range(40)]
     return last + faces + rand
 
 
 def _flat_index(lut, cells):
     """Element index of cells (M, 3) inside one component of the level array."""
+    N = 8 * lut.shape[0]
     c = np.asarray(cells) % N
     b = lut[c[:, 2] >> 3, c[:, 1] >> 3, c[:, 0] >> 3].astype(np.int64)
     return b * 512 + (c[:, 2] & 7) * 64 + (c[:, 1] & 7) * 8 + (c[:, 0] & 7)
@@ -60,12 +61,14 @@ def _box(vals, centre_parity):
     return box, (8, 8, 8 + centre_parity)
 
 
-def test_level_beyond_4gib_per_component_sweep_and_residual():
+@pytest.mark.parametrize("N", [128, 256, 832])
+def test_sweep_and_residual_sampled_at_full_size(N):
     import torch
     import paper_1009_0798_amd as ohm
-    announce(f"max size: {N}^3 level, {NBA ** 3} blocks, FP64 arrays above 4 GiB per component")
+    NBA = N // 8
+    announce(f"full size: {N}^3 level, {NBA ** 3} blocks, sampled sweep and residual")
     spec = gen.uniform_spec(N)
-    assert len(spec.levels[0]) * 512 * 8 > 2 ** 32
+    assert (len(spec.levels[0]) * 512 * 8 > 2 ** 32) == (N == 832)
     H = ohm.Hierarchy([(spec.base_blocks, spec.dx0, spec.levels)])
     lut = np.empty((NBA, NBA, NBA), np.int32)
     ijk = spec.levels[0]
@@ -82,16 +85,17 @@ def test_level_beyond_4gib_per_component_sweep_and_residual():
     h = spec.dx0
     lam_dt = 0.5 * gen.explicit_dt(h, 1.0, 20.0)
     rng = np.random.default_rng(11)
-    cells = _sample_cells(spec, rng)
+    cells = _sample_cells(spec, rng, N)
     nbr = torch.from_numpy(_neighbourhoods(lut, cells)).cuda()
     Bf, Sf, Ef = B.view(3, -1), S.view(3, -1), E.view(1, -1)
     Bn = Bf[:, nbr].cpu().numpy()               # (3, M, 343)
     Sn = Sf[:, nbr].cpu().numpy()
     En = Ef[:, nbr].cpu().numpy()
     centre = torch.from_numpy(_flat_index(lut, cells)).cuda()
-    assert int(centre.max()) * 8 > 2 ** 32
+    if N == 832:
+        assert int(centre.max()) * 8 > 2 ** 32
 
-    announce("max size: residual with norms")
+    announce(f"full size {N}^3: residual with norms")
     R = torch.empty_like(B)
     norms = ohm.ohm_residual(H, 0, B, S, E, lam_dt, R=R, norms=True)
     Rc = R.view(3, -1)[:, centre].cpu().numpy()
@@ -101,14 +105,14 @@ def test_level_beyond_4gib_per_component_sweep_and_residual():
         assert norms[0, c, 1] == float(rc.abs().max())
     del R
 
-    announce("max size: one red-black sweep (per-colour launches)")
+    announce(f"full size {N}^3: one red-black sweep")
     tmp = torch.empty_like(B)
     ohm.ohm_smooth(H, 0, B, S, E, lam_dt, 1, tmp)
     torch.cuda.synchronize()
     Bc = Bf[:, centre].cpu().numpy()
     del tmp
 
-    announce("max size: oracle on the sampled neighbourhoods")
+    announce(f"full size {N}^3: oracle on the sampled neighbourhoods")
     worst_r = worst_s = 0.0
     for m, cell in enumerate(cells):
         par = sum(cell) & 1
