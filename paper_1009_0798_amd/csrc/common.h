@@ -129,7 +129,7 @@ struct ohm_hier {
     std::vector<int> ng_host;        // ghosts per AMR level
     ohm::DenseLevelDev dense[16];    // index d = -level
     long long dense_cells[16] = {0};
-    // host copies used by the driver
+    // host copies read by the step code (cn.hip)
     std::vector<std::vector<int>> blk_prob_host;  // per level
     // scratch for per-problem scalars uploaded by the primitives
     double *d_scal = nullptr;        // [4 * nprob]
