@@ -227,6 +227,109 @@ def cpu_baseline(n_sample, min_seconds=8.0, repeats=3, n_single=32):
                                         f"{single[2]} iterations, {single[3]:.1f} s"}}
 
 
+def timed_oracle(make_work, min_seconds=8.0, repeats=3):
+    """A bounded oracle sample: make_work() returns a function that runs one
+    unit of oracle work (a CN step, or one problem) and returns (cells,
+    iterations); units run until about min_seconds.  The median of `repeats`
+    runs on every host thread, and one run limited to one thread (OpenMP and
+    BLAS).  Returns (median, runs, single), each run (cells/s, units, cells,
+    iterations, seconds, threads)."""
+    from threadpoolctl import threadpool_limits
+    from oracle import ref
+
+    def one():
+        work = make_work()
+        units = cells = iters = 0
+        t0 = time.perf_counter()
+        while True:
+            c, it = work()
+            units += 1
+            cells += c
+            iters += it
+            t = time.perf_counter() - t0
+            if t >= min_seconds or t * (units + 1) / units > 3 * min_seconds:
+                break
+        return cells / t, units, cells, iters, t, ref.threads()
+
+    runs = sorted((one() for _ in range(repeats)), key=lambda r: r[0])
+    nthr = ref.threads()
+    ref.set_threads(1)
+    try:
+        with threadpool_limits(limits=1):
+            single = one()
+    finally:
+        ref.set_threads(nthr)
+    return runs[len(runs) // 2], runs, single
+
+
+def oracle_baseline(make_work, what, unit_name, min_seconds=8.0):
+    """timed_oracle() as a cpu_baseline record; `what` names the sample."""
+    med, runs, single = timed_oracle(make_work, min_seconds)
+    return {"value": med[0], "unit": "cells/s", "cores": med[5], "kind": "oracle",
+            "sample": f"{med[1]} {unit_name} of {what}, {med[2]} cells, {med[3]} iterations, {med[4]:.1f} s; median "
+                      f"of {len(runs)} runs",
+            "runs_cells_per_s": [r[0] for r in runs], "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "single_thread": {"value": single[0], "unit": "cells/s", "cores": single[5],
+                              "sample": f"{single[1]} {unit_name}, {single[3]} iterations, {single[4]:.1f} s"}}
+
+
+def bench_fourier32(args):
+    """32^3, eta = 1, three axis-aligned Fourier modes plus noise, dt = 20x
+    explicit: consecutive CN steps in FP64 and mixed precision, and the
+    oracle on the same workload."""
+    import torch
+    import ohm_inputs as gen
+    import paper_1009_0798_amd as ohm
+    from oracle import mg
+    cfg = gen.config_fourier32()
+    spec = cfg["spec"]
+    ijk = spec.levels[0]
+    H = ohm.Hierarchy([(spec.base_blocks, spec.dx0, spec.levels)])
+    B0 = ohm.to_blocks(torch.from_numpy(cfg["B"]), ijk).cuda()
+    E = ohm.to_blocks(torch.from_numpy(cfg["eta"])[None], ijk).cuda()
+    cells = spec.cells(0)[0] ** 3
+    res = {}
+    for prec in (0, 1):
+        ws = ohm.Workspace()
+        opts = ohm.default_opts(rtol=1e-10, precision=prec, max_iters=200, nu_pre=SCHEDULE[prec][0],
+                                nu_post=SCHEDULE[prec][1], nu_coarse=NU_COARSE)
+        B = B0.clone()
+        for _ in range(args.warmup):
+            ohm.ohm_cn_step(H, [B], [E], cfg["dt"], opts, ws)
+        B = B0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = []
+        for _ in range(args.steps):
+            st, stats = ohm.ohm_cn_step(H, [B], [E], cfg["dt"], opts, ws)
+            assert st == 0, st
+            iters.append(stats[0]["iters"])
+        torch.cuda.synchronize()
+        res[prec] = ((time.perf_counter() - t0) / args.steps, iters)
+    t, iters = res[0]
+
+    def make_work():
+        state = {"B": cfg["B"]}
+
+        def work():
+            state["B"], hist = mg.cn_step(state["B"], cfg["eta"], spec.dx0, cfg["dt"], rtol=1e-10)
+            return cells, len(hist) - 1
+        return work
+
+    out = {"metric": METRIC, "value": cells / t, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "fourier32: 32^3, eta = 1, three Fourier modes + 1e-3 noise, dt = 20x explicit, "
+                                  "consecutive CN steps to rel. residual 1e-10", "cells": cells,
+                      "iterations_per_step": iters},
+           "mixed": {"value": cells / res[1][0], "ms_per_step": res[1][0] * 1e3, "iterations_per_step": res[1][1]}}
+    if args.cpu_sample:
+        _log("timing the oracle on the same workload")
+        out["cpu_baseline"] = oracle_baseline(make_work, "the 32^3 Fourier workload (the workload itself), FP64 "
+                                              "V(2,2)-BiCGStab to 1e-10", "consecutive CN steps")
+    return out
+
+
 def bench_batched(args):
     """256 independent problems of uneven size in one handle (one launch per
     kernel covers every problem); mixed precision; schedule from the tuner."""
@@ -255,12 +358,28 @@ def bench_batched(args):
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     worst = max(s["rel_res"] for s in stats)
-    return {"metric": METRIC, "value": cells * args.steps / t, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+    out = {"metric": METRIC, "value": cells * args.steps / t, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": t / args.steps * 1e3, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "f32 multigrid + f64 outer", "data": "synthetic",
             "config": {"workload": f"batched{args.nprob}: {args.nprob} independent CN solves, edges from "
                                    "{16,24,32,48,64}, eta log-normal 2 decades, dt 10-200x explicit",
                        "cells": cells, "schedule": best, "worst_rel_res": worst}}
+    if args.cpu_sample:
+        from oracle import mg
+        _log("timing the oracle on the batch's problems in order")
+
+        def make_work():
+            it = iter(probs)
+
+            def work():
+                p = next(it)
+                _, hist = mg.cn_step(p["B"], p["eta"], p["spec"].dx0, p["dt"], rtol=1e-10)
+                return p["spec"].cells(0)[0] ** 3, len(hist) - 1
+            return work
+
+        out["cpu_baseline"] = oracle_baseline(make_work, "the batch (one CN step each, taken in order), FP64 "
+                                              "V(2,2)-BiCGStab to 1e-10", "problems")
+    return out
 
 
 def bench_amr(args):
@@ -292,13 +411,35 @@ def bench_amr(args):
         torch.cuda.synchronize()
         out[prec] = ((time.perf_counter() - t0) / args.steps, stats[0])
     t, stats = out[0]
-    return {"metric": METRIC, "value": cells / t, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
-            "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak",
-            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-            "config": {"workload": "amr2: 64^3 base + level 1 over the central 1/8 and 20% of other base blocks, "
-                                   "dense-core eta, dt = 20x explicit on the fine level", "leaf_cells": cells,
-                       "iterations": stats["iters"], "V": [args.nu or AMR_SCHEDULE[0], args.nu or AMR_SCHEDULE[1]]},
-            "mixed": {"value": cells / out[1][0], "ms_per_step": out[1][0] * 1e3, "iterations": out[1][1]["iters"]}}
+    res = {"metric": METRIC, "value": cells / t, "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "amr2: 64^3 base + level 1 over the central 1/8 and 20% of other base blocks, "
+                                  "dense-core eta, dt = 20x explicit on the fine level", "leaf_cells": cells,
+                      "iterations": stats["iters"], "V": [args.nu or AMR_SCHEDULE[0], args.nu or AMR_SCHEDULE[1]]},
+           "mixed": {"value": cells / out[1][0], "ms_per_step": out[1][0] * 1e3, "iterations": out[1][1]["iters"]}}
+    if args.cpu_sample:
+        from oracle import amr
+        _log("timing the oracle's composite step on the 32^3-base version of the workload")
+        sspec = gen.config_amr2(n_base=32, extra_frac=0.2, seed=4)
+        sb, se = gen.amr_fields_fourier(sspec, seed=5)
+        sdt = 20.0 * sspec.dx(1) ** 2 / (6 * 10.0)
+        C = amr.Composite(sspec)
+        e = [C.to_dense(l, se[l]) for l in range(2)]
+
+        def make_work():
+            state = {"b": [C.to_dense(l, sb[l]) for l in range(2)]}
+
+            def work():
+                state["b"], hist = C.cn_step(state["b"], e, sdt, rtol=1e-10)
+                return sspec.leaf_cells(), len(hist) - 1
+            return work
+
+        res["cpu_baseline"] = oracle_baseline(
+            make_work, f"the same recipe on a 32^3 base ({sspec.leaf_cells()} leaf cells; the 64^3-base step takes "
+                       "about a minute on the oracle), composite operator with point-Jacobi BiCGStab to 1e-10",
+            "consecutive CN steps")
+    return res
 
 
 def bench_serve(args):
@@ -497,7 +638,7 @@ def main():
     ap.add_argument("--hbm-n", type=int, default=256,
                     help="grid edge of the second roofline leg, a working set above the last-level cache (0: skip)")
     ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--workload", default="lognormal128", choices=["lognormal128", "batched", "serve", "amr", "e8"])
+    ap.add_argument("--workload", default="lognormal128", choices=["lognormal128", "fourier32", "batched", "serve", "amr", "e8"])
     ap.add_argument("--nu", type=int, default=None, help="pre and post sweeps of the AMR workload's cycle")
     ap.add_argument("--nprob", type=int, default=256)
     ap.add_argument("--requests", type=int, default=64)
@@ -527,6 +668,9 @@ def main():
         return
     if args.workload == "e8":
         print(json.dumps(bench_e8(args)), flush=True)
+        return
+    if args.workload == "fourier32":
+        print(json.dumps(bench_fourier32(args)), flush=True)
         return
     if args.workload == "batched":
         print(json.dumps(bench_batched(args)), flush=True)
