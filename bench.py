@@ -486,13 +486,39 @@ def bench_serve(args):
         rate = 0.8 * rep["requests_per_s"]
     srv.shutdown()
     rep = legs["offered"]
-    return {"metric": METRIC, "value": rep["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": args.requests,
-            "warmup": len(pool), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f32 multigrid + f64 outer", "data": "synthetic",
-            "config": {"workload": f"serve: Poisson {args.rate}/s, {args.requests} requests of 1-3 level AMR, base "
-                                   "32-192^3", "streams": args.streams, "schedule": sched},
-            "latency": rep, "sustainable": legs["sustainable"],
-            "slots": {"built": srv.built, "reused": srv.reused}}
+    out = {"metric": METRIC, "value": rep["cells_per_s"], "unit": "cells/s", "n_gpus": 1, "steps": args.requests,
+           "warmup": len(pool), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 multigrid + f64 outer", "data": "synthetic",
+           "config": {"workload": f"serve: Poisson {args.rate}/s, {args.requests} requests of 1-3 level AMR, base "
+                                  "32-192^3", "streams": args.streams, "schedule": sched},
+           "latency": rep, "sustainable": legs["sustainable"],
+           "slots": {"built": srv.built, "reused": srv.reused}}
+    if args.cpu_sample:
+        from oracle import amr
+        limit = 200_000
+        small = sorted((d for d in pool if d["spec"].leaf_cells() <= limit), key=lambda d: d["spec"].leaf_cells())
+        if small:
+            _log("timing the oracle's composite step on the smallest request shapes")
+
+            def make_work():
+                it = iter(small * 100)
+
+                def work():
+                    d = next(it)
+                    C = amr.Composite(d["spec"])
+                    L = d["spec"].nlevels
+                    b = [C.to_dense(l, d["B"][l]) for l in range(L)]
+                    e = [C.to_dense(l, d["eta"][l]) for l in range(L)]
+                    _, hist = C.cn_step(b, e, d["dt"], rtol=1e-10)
+                    return d["spec"].leaf_cells(), len(hist) - 1
+                return work
+
+            cb = oracle_baseline(make_work, f"the pool's request shapes with at most {limit} leaf cells, smallest "
+                                            f"first ({[d['spec'].leaf_cells() for d in small]} leaf cells; the "
+                                            "others take minutes each), one composite step each, point-Jacobi "
+                                            "BiCGStab to 1e-10", "requests")
+            out["cpu_baseline"] = cb
+    return out
 
 
 def bench_e8(args):
