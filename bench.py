@@ -42,8 +42,8 @@ def kernel_source_hash() -> str:
 # --roofline-only: tag -> (kernel name prefix, algorithmic bytes per cell,
 # dispatches to average: the first k of that name, or all when None)
 COUNTED = {
-    "sweep_f64": ("k_blk_sweep<double, 0, false>", 80, 12),
-    "sweep_f32": ("k_blk_sweep<float, 0, false>", 40, 12),
+    "sweep_f64": ("k_blk_sweep<double, 0, false, true>", 80, 12),
+    "sweep_f32": ("k_blk_sweep<float, 0, false, false>", 40, 12),
     "apply_f64": ("k_blk_stencil<double, 0>", 56, 12),
     "resid_f64": ("k_blk_stencil<double, 1>", 80, 12),
     "resid_restrict_f64": ("k_blk_stencil<double, 3>", 59, None),

@@ -271,11 +271,13 @@ struct GhostBlockAddr {
     }
 };
 
+// DIRECT (plain FP64 sweeps, MODE 0): the tile is staged by loads that write
+// LDS directly instead of passing through registers.
 // MODE 0: sweep B -> out; 1: zero input (B not read); 2: sweep of B plus the
 // prolonged correction from the first dense level (coarse), B -> out; MODE 3
 // and 4 as 0 and 1 on a level with coarse-fine ghost blocks (Bg, etag).  With
 // O64 (MODE 0 or 2 of an FP32 sweep) the result is written as FP64 to out64.
-template <typename T, int MODE, bool O64 = false>
+template <typename T, int MODE, bool O64 = false, bool DIRECT = false>
 __global__ void __launch_bounds__(SWEEP_THREADS)
 k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ prob_of,
             const int *__restrict__ active, const double *__restrict__ inv_h2_p, const double *__restrict__ coef_p,
@@ -284,8 +286,9 @@ k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ p
             const T *__restrict__ coarse, long long ccs, const T *__restrict__ Bg, long long gcs,
             const T *__restrict__ etag, double *__restrict__ out64 = nullptr)
 {
-    __shared__ T sB[3][TC2];
-    __shared__ T sE[TC2];
+    constexpr int TS = DIRECT ? TC2 + 64 : TC2;
+    __shared__ T sB[3][TS];
+    __shared__ T sE[TS];
     __shared__ T sC[MODE == 2 ? 3 * 512 : 1];
     __shared__ int snbr[27];
     const int b = xcd_block(blockIdx.x, nblk);
@@ -294,6 +297,11 @@ k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ p
     if (threadIdx.x < 27) snbr[threadIdx.x] = nbr_tab[27 * (long long)b + threadIdx.x];
     __syncthreads();
     const T cih2 = T(coef_p[pr]) * T(inv_h2_p[pr]);
+    if constexpr (DIRECT) {
+        const BlockAddr A{snbr, b};
+        fused_sweep_tile<T, false, BlockAddr, NoCoarse<T>, T, TS, true>(A, B, cs, S, eta, out, cih2, sB, sE);
+        return;
+    } else {
     if constexpr (MODE >= 3) {
         const GhostBlockAddr<T> A{snbr, Bg, gcs, etag};
         fused_sweep_tile<T, MODE == 4>(A, B, cs, S, eta, out, cih2, sB, sE);
@@ -311,6 +319,7 @@ k_blk_sweep(int nblk, const int *__restrict__ nbr_tab, const int *__restrict__ p
             fused_sweep_tile<T, MODE == 1, BlockAddr, NoCoarse<T>, double>(A, B, cs, S, eta, out64, cih2, sB, sE);
         else
             fused_sweep_tile<T, MODE == 1>(A, B, cs, S, eta, out, cih2, sB, sE);
+    }
     }
 }
 
@@ -750,8 +759,10 @@ ohm_status launch_blk_sweep(const ohm_hier *h, int level, const T *B, long long 
                                                          out, L.ijk, h->dense[1].probs, coarse, ccs, nullptr, 0,
                                                          nullptr);
     } else if (B) {
-        k_blk_sweep<T, 0><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta,
-                                                         out, nullptr, nullptr, nullptr, 0, nullptr, 0, nullptr);
+        // FP64 tiles go straight from global memory into LDS (16-byte pairs)
+        k_blk_sweep<T, 0, false, std::is_same<T, double>::value><<<L.nb, SWEEP_THREADS, 0, s>>>(
+            L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta, out, nullptr, nullptr, nullptr, 0, nullptr,
+            0, nullptr);
     } else {
         k_blk_sweep<T, 1><<<L.nb, SWEEP_THREADS, 0, s>>>(L.nb, L.nbr, L.prob, active, L.inv_h2, coef_dev, B, cs, S, eta,
                                                          out, nullptr, nullptr, nullptr, 0, nullptr, 0, nullptr);

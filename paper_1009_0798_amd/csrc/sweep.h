@@ -111,15 +111,50 @@ struct TileCoarse {
 
 // The result goes to `out` as TO (T, or double from an FP32 sweep), with the
 // same element offsets and component stride as the input.
-template <typename T, bool ZERO, typename Addr, typename Coarse = NoCoarse<T>, typename TO = T>
+// 16 bytes from global memory straight into LDS: lane l of the wavefront
+// writes dst + 16 l bytes (dst uniform over the wavefront)
+__device__ __forceinline__ void lds_load16(const void *src, void *dst)
+{
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)src,
+                                     (void __attribute__((address_space(3))) *)dst, 16, 0, 0);
+}
+
+template <typename T, bool ZERO, typename Addr, typename Coarse = NoCoarse<T>, typename TO = T, int TS = TC2,
+          bool DIRECT = false>
 __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restrict__ B, long long cs,
                                                  const T *__restrict__ S, const T *__restrict__ eta,
-                                                 TO *__restrict__ out, const T cih2, T (*sB)[TC2], T *sE,
+                                                 TO *__restrict__ out, const T cih2, T (*sB)[TS], T *sE,
                                                  Coarse cor = Coarse())
 {
     const int u = threadIdx.x;
     const T *B0 = B, *B1 = ZERO ? B : B + cs, *B2 = ZERO ? B : B + 2 * cs;
     const T *S0 = S, *S1 = S + cs, *S2 = S + 2 * cs;
+    if constexpr (DIRECT) {
+        // FP64 tile pairs loaded straight into LDS: pair P = u + 512 k of
+        // the 864 (plane-major, as tix2 lays them out) lands at element 2 P,
+        // which is lane order within each wavefront; the lanes past the last
+        // pair reload pair 863 into 64 elements of padding (TS >= TC2 + 64)
+        static_assert(sizeof(T) == 8 && !ZERO && !Addr::ghosts && !Coarse::active && TS >= TC2 + 64,
+                      "direct tile loads are for plain FP64 sweeps");
+        constexpr int NPC = (TW2 / 2) * TW2, NP = NPC * TW2;
+        const int w = u >> 6;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int first = SWEEP_THREADS * k + 64 * w;
+            if (first < NP) {
+                const int P = min(u + SWEEP_THREADS * k, NP - 1);
+                const int pc = P % NPC, z = P / NPC - 2;
+                const int x = 2 * (pc % (TW2 / 2)) - 2, y = pc / (TW2 / 2) - 2;
+                const unsigned off = (unsigned)A.at(x, y, z) * (unsigned)sizeof(T);
+                lds_load16((const char *)B0 + off, &sB[0][2 * first]);
+                lds_load16((const char *)B1 + off, &sB[1][2 * first]);
+                lds_load16((const char *)B2 + off, &sB[2][2 * first]);
+                lds_load16((const char *)eta + off, &sE[2 * first]);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    } else {
     // tile load in pairs of x-neighbours (x even, so a pair never straddles a
     // block or a periodic wrap and is 2 sizeof(T) aligned): thread u < 432
     // owns pair column (px, y) = u mod 72 and the planes z = 2 (u / 72) - 2
@@ -176,6 +211,7 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
         }
     }
     __syncthreads();
+    }
     const T c8 = cih2 * T(0.125), c2 = cih2 * T(0.5);
     // the black cell of this thread and its S values, loaded before the red
     // half-sweep so that their latency overlaps it
