@@ -30,6 +30,7 @@ struct Plan {
     size_t rhs, e, tmp, res, mg_g, eta_t, eta_tg;
     size_t d_rhs[16], d_e[16], d_tmp[16], d_res[16], d_eta[16], d_eta64[16];
     size_t inv, aug, jobs, force, part, dots, scal, ranges, mlprob, active, cmask, coefs;
+    size_t ring, tol2;          // norms of queued BiCGStab iterations, convergence thresholds
     size_t rf;                  // FMG over AMR levels: right-hand side restricted under finer blocks
     size_t inv_elems = 0, aug_elems = 0;
 };
@@ -87,6 +88,8 @@ Plan make_plan(const ohm_hier *h, const ohm_cn_opts *o)
     P.part = take(8 * (size_t)P.NBt * 8);
     P.dots = take(8 * (size_t)h->nprob * 8);
     P.scal = take(8 * (size_t)h->nprob * scal_stride());
+    P.ring = take(8 * (size_t)h->nprob * 2 * ITER_SLOTS);
+    P.tol2 = take(8 * (size_t)h->nprob);
     // tables the host builds each step, contiguous from jobs to coefs (one
     // staged upload): coarse jobs and force flags per depth, block ranges
     // per problem and level, block -> problem, active flags, coarse masks,
@@ -690,24 +693,23 @@ struct Solver {
         OHM_TRY(composite(P.x, P.r, MODE_RESID, lam_dt, neg_lam_dt, P.S));
         const double *xs[2] = {at<double>(P.S), at<double>(P.r)};
         OHM_TRY(dots(xs, xs, 2));
-        return copy_dots(2);
+        OHM_TRY(copy_dots(2));
+        // thresholds of the stop rule; problems the initial guess already
+        // satisfies leave the active set before any iteration is queued
+        return launch_conv_init(h->nprob, at<double>(P.dots), o->rtol, at<double>(P.tol2), active_mut, st);
     }
 
     // |S|^2 per problem
     std::vector<double> Snorm2;
 
-    // true residual r = S - L x, returns per-problem |r|^2 (in dots[p*1])
-    ohm_status true_residual(std::vector<double> &r2)
+    // true residual r = S - L x; its per-problem |r|^2 goes to the pinned
+    // buffer (h_dots[p], read after a synchronisation)
+    ohm_status true_residual()
     {
         OHM_TRY(composite(P.x, P.r, MODE_RESID, lam_dt, neg_lam_dt, P.S));
         const double *xs[1] = {at<double>(P.r)};
         OHM_TRY(dots(xs, xs, 1));
-        // dots are packed with stride nq = 1
-        std::vector<double> d(h->nprob);
-        OHM_HIP(hipMemcpyAsync(d.data(), at<double>(P.dots), sizeof(double) * h->nprob, hipMemcpyDeviceToHost, st));
-        OHM_HIP(hipStreamSynchronize(st));
-        r2 = d;
-        return OHM_OK;
+        return copy_dots(1);
     }
 
     // device flags as last uploaded (setup uploads all ones)
@@ -747,9 +749,22 @@ struct Solver {
             OHM_TRY(vbicg_xr((int)P.NBt, mlprob, active, VN, at<double>(P.scal), at<double>(P.x),
                              at<double>(P.ph), at<double>(P.sh), at<double>(P.s), at<double>(P.t),
                              at<double>(P.r), at<double>(P.rhat), at<double>(P.part), st));
-            OHM_TRY(reduce_scal(2, 4));
-            return copy_dots(2);
+            // (r, r) and (rhat, r) into the iteration ring, which goes to
+            // the pinned buffer whole (one copy node)
+            IterRing ring;
+            ring.buf = at<double>(P.ring);
+            ring.flags = active_mut;
+            ring.tol2 = at<double>(P.tol2);
+            OHM_TRY(launch_reduce_scal(h->nprob, nlev(), at<long long>(P.ranges), at<double>(P.part), 2,
+                                       at<double>(P.dots), 4, active, at<double>(P.scal), st, ring));
+            OHM_HIP(hipMemcpyAsync(h_ring(), at<double>(P.ring), sizeof(double) * 2 * ITER_SLOTS * h->nprob,
+                                   hipMemcpyDeviceToHost, st));
+            return OHM_OK;
     }
+    // pinned regions after the first 8 nprob values: the iteration ring, then
+    // the final norms of a step
+    double *h_ring() const { return h->h_dots + 8 * (size_t)h->nprob; }
+    double *h_final() const { return h->h_dots + (8 + 2 * ITER_SLOTS) * (size_t)h->nprob; }
     // the first nq * nprob norms to the handle's pinned host buffer (part of a
     // captured iteration: one node, no separate copy command); read after a
     // synchronisation of the stream
@@ -865,36 +880,64 @@ struct Solver {
         return run_explicit(nsteps);
     }
 
+    // the end of a step, queued: norms of the true residual r (into the
+    // pinned buffer), average-down of x over the AMR levels and the copy to
+    // the user's fields.  It may be queued behind a true residual that turns
+    // out not to converge: the iteration then resumes (values of x under
+    // finer blocks are restored by every composite operator before use) and
+    // the end is queued again.
+    ohm_status finish_async()
+    {
+        const int np = h->nprob, L = nlev();
+        OHM_TRY(vnorms((int)P.NBt, mlprob, nullptr, VN, at<double>(P.r), at<double>(P.part), st));
+        OHM_TRY(reduce(6, 3, at<double>(P.dots)));
+        OHM_HIP(hipMemcpyAsync(h_final(), at<double>(P.dots), sizeof(double) * 6 * np, hipMemcpyDeviceToHost, st));
+        for (int l = L - 1; l >= 1; --l)
+            OHM_TRY(launch_restrict_blk<double>(h, l, vec(P.x, l), VN, vec(P.x, l - 1), VN, 3, nullptr, st));
+        for (int l = 0; l < L; ++l)
+            OHM_TRY(vcopy_level<double, double>(vec(P.x, l), VN, (double *)Buser[l], (long long)h->nb_host[l] * NC,
+                                                (long long)h->nb_host[l] * NC, 3, st));
+        return OHM_OK;
+    }
+
     ohm_status run(ohm_cn_stats *stats)
     {
         const int np = h->nprob;
         std::vector<int> iters(np, 0), mgapps(np, 0), act(np, 1);
-        // |S|^2 and the residual of the initial guess (start_device copied them)
-        std::vector<double> r2(np);
+        std::vector<double> r2(np), rfin(np, 0.0);
         Snorm2.assign(np, 0.0);
-        OHM_HIP(hipStreamSynchronize(st));
-        for (int p = 0; p < np; ++p) {
-            Snorm2[p] = h->h_dots[2 * p];
-            r2[p] = h->h_dots[2 * p + 1];
-        }
-        // |r|^2 of each problem's latest true residual.  A problem stops being
-        // updated only right after a true residual that included it, so at the
-        // end r holds every problem's residual at its final B.
-        std::vector<double> rfin = r2;
         auto converged = [&](int p, double v) {
-            return !(v > o->rtol * o->rtol * std::max(Snorm2[p], 1e-300));
+            return !(v > o->rtol * o->rtol * std::fmax(Snorm2[p], 1e-300));
         };
-        ohm_status result = OHM_OK;
-        for (int p = 0; p < np; ++p) {
-            if (!std::isfinite(r2[p])) return fail(OHM_ERR_NONFINITE, "problem %d: non-finite residual", p);
-            if (converged(p, r2[p])) act[p] = 0;
-        }
-        OHM_TRY(set_active(act));
+        auto any = [](const std::vector<int> &a) {
+            return std::any_of(a.begin(), a.end(), [](int x) { return x != 0; });
+        };
+        // |S|^2 and |r|^2 of the initial guess (start_device copied them and
+        // took the same decisions on the device: k_conv_init).  A problem
+        // stops being updated only right after a true residual that included
+        // it, so at the end r holds every problem's residual at its final B.
+        bool known = false;
+        auto read_start = [&]() -> ohm_status {
+            for (int p = 0; p < np; ++p) {
+                Snorm2[p] = h->h_dots[2 * p];
+                r2[p] = h->h_dots[2 * p + 1];
+            }
+            rfin = r2;
+            for (int p = 0; p < np; ++p) {
+                if (!std::isfinite(r2[p])) return fail(OHM_ERR_NONFINITE, "problem %d: non-finite residual", p);
+                if (converged(p, r2[p])) act[p] = 0;
+            }
+            act_dev = act;
+            known = true;
+            return OHM_OK;
+        };
         const int maxit = o->max_iters;
-        auto any = [&]() { return std::any_of(act.begin(), act.end(), [](int a) { return a != 0; }); };
+        bool finished = false;   // the end of the step is queued behind the last true residual
         if (o->outer == 0) {
+            OHM_HIP(hipStreamSynchronize(st));
+            OHM_TRY(read_start());
             // eqs. (16)-(18): R = S - L B; B <- B + M(R)
-            for (int it = 0; it < maxit && any(); ++it) {
+            for (int it = 0; it < maxit && any(act); ++it) {
                 OHM_TRY(replay(0, [&]() { return ir_iter(); }));
                 OHM_TRY(read_dots(1, r2));
                 for (int p = 0; p < np; ++p)
@@ -909,9 +952,14 @@ struct Solver {
             }
         } else {
             // BiCGStab; restarted from the true residual when the recurrence
-            // residual has converged but the true one has not
-            int it_total = 0;
-            while (any() && it_total < maxit) {
+            // residual has converged but the true one has not.  The first
+            // pass of a step queues as many iterations as the previous step's
+            // first pass took, less one, before it reads their norms (the
+            // device drops each problem at the iteration that converges it,
+            // so the iterations queued behind leave it unchanged); later reads
+            // follow every iteration.
+            int it_total = 0, first_pass = -1;
+            while (it_total < maxit && (!known || any(act))) {
                 // restart: rhat = r (copied by the dot kernel that forms
                 // (r, r)), rho = alpha = omega = 1, and a first direction p = r
                 // (the scalar stage sets beta = 0, which the direction update
@@ -921,60 +969,78 @@ struct Solver {
                     OHM_TRY(dots(xs, xs, 1, 0, at<double>(P.rhat)));
                 }
                 std::vector<int> inner(act);
+                int since = 0;   // iterations since the restart (the ring's slot count)
                 while (it_total < maxit) {
-                    OHM_TRY(replay(1, [&]() { return bicg_iter(); }));
-                    ++it_total;
+                    int nb = 1;
+                    if (first_pass < 0 && since == 0)
+                        nb = std::max(1, std::min({h->bicg_pred - 1, ITER_SLOTS, maxit - it_total}));
+                    for (int j = 0; j < nb; ++j) OHM_TRY(replay(1, [&]() { return bicg_iter(); }));
+                    it_total += nb;
                     OHM_HIP(hipStreamSynchronize(st));
-                    const double *d = h->h_dots;
-                    bool any_inner = false;
-                    for (int p = 0; p < np; ++p)
-                        if (inner[p]) {
-                            ++iters[p];
-                            mgapps[p] += 2;
-                            if (!std::isfinite(d[2 * p]))
-                                return fail(OHM_ERR_NONFINITE, "problem %d: non-finite residual", p);
-                            if (converged(p, d[2 * p])) inner[p] = 0;
-                            any_inner |= inner[p] != 0;
-                        }
-                    // stop updating problems whose recurrence residual converged
-                    OHM_TRY(set_active(inner));
-                    if (!any_inner) break;
+                    if (!known) {
+                        OHM_TRY(read_start());
+                        inner = act;
+                    }
+                    for (int j = 0; j < nb; ++j) {
+                        const double *d = h_ring() + 2 * (size_t)np * ((since + j) % ITER_SLOTS);
+                        for (int p = 0; p < np; ++p)
+                            if (inner[p]) {
+                                ++iters[p];
+                                mgapps[p] += 2;
+                                if (!std::isfinite(d[2 * p]))
+                                    return fail(OHM_ERR_NONFINITE, "problem %d: non-finite residual", p);
+                                if (converged(p, d[2 * p])) inner[p] = 0;
+                            }
+                    }
+                    since += nb;
+                    // the device dropped the same problems as the iterations ran
+                    act_dev = inner;
+                    if (!any(inner)) break;
                 }
-                // verify with the true residual
-                OHM_TRY(set_active(act));
-                OHM_TRY(true_residual(r2));
+                if (first_pass < 0) first_pass = since;
+                if (!any(act)) break;   // every problem satisfied by its initial guess
+                // verify with the true residual, the end of the step queued
+                // behind it.  It is formed for every problem (no flag upload):
+                // a problem that stopped earlier has the same x as when its
+                // residual was last formed, so it gets the same r again.
+                {
+                    const int *keep = active;
+                    active = nullptr;
+                    const ohm_status rs = true_residual();
+                    active = keep;
+                    OHM_TRY(rs);
+                }
+                OHM_TRY(finish_async());
+                OHM_HIP(hipStreamSynchronize(st));
+                finished = true;
                 for (int p = 0; p < np; ++p)
                     if (act[p]) {
-                        rfin[p] = r2[p];
-                        if (converged(p, r2[p])) act[p] = 0;
+                        rfin[p] = h->h_dots[p];
+                        if (converged(p, rfin[p])) act[p] = 0;
                     }
-                OHM_TRY(set_active(act));
+                if (any(act)) {
+                    finished = false;
+                    OHM_TRY(set_active(act));
+                }
             }
+            h->bicg_pred = first_pass;
         }
-        // final state: norms of the true residuals, average-down, copy out,
-        // one synchronisation
-        OHM_TRY(vnorms((int)P.NBt, mlprob, nullptr, VN, at<double>(P.r), at<double>(P.part), st));
-        OHM_TRY(reduce(6, 3, at<double>(P.dots)));
-        std::vector<double> nrm((size_t)np * 6);
-        OHM_HIP(hipMemcpyAsync(nrm.data(), at<double>(P.dots), sizeof(double) * 6 * np, hipMemcpyDeviceToHost, st));
-        const int L = nlev();
-        for (int l = L - 1; l >= 1; --l)
-            OHM_TRY(launch_restrict_blk<double>(h, l, vec(P.x, l), VN, vec(P.x, l - 1), VN, 3, nullptr, st));
-        for (int l = 0; l < L; ++l)
-            OHM_TRY(vcopy_level<double, double>(vec(P.x, l), VN, (double *)Buser[l], (long long)h->nb_host[l] * NC,
-                                                (long long)h->nb_host[l] * NC, 3, st));
-        OHM_HIP(hipStreamSynchronize(st));
-        r2 = rfin;
+        if (!finished) {
+            OHM_TRY(finish_async());
+            OHM_HIP(hipStreamSynchronize(st));
+        }
+        const double *nrm = h_final();
+        ohm_status result = OHM_OK;
         for (int p = 0; p < np; ++p) {
-            const double rel = std::sqrt(r2[p] / std::max(Snorm2[p], 1e-300));
+            const double rel = std::sqrt(rfin[p] / std::max(Snorm2[p], 1e-300));
             if (stats) {
                 stats[p].iters = iters[p];
                 stats[p].mg_apps = mgapps[p];
                 stats[p].rel_res = rel;
                 for (int c = 0; c < 3; ++c) stats[p].max_res[c] = nrm[6 * p + 3 + c];
             }
-            if (!std::isfinite(r2[p])) result = fail(OHM_ERR_NONFINITE, "problem %d: non-finite residual", p);
-            else if (!converged(p, r2[p]) && result == OHM_OK)
+            if (!std::isfinite(rfin[p])) result = fail(OHM_ERR_NONFINITE, "problem %d: non-finite residual", p);
+            else if (!converged(p, rfin[p]) && result == OHM_OK)
                 result = fail(OHM_ERR_NOCONV, "problem %d: relative residual %.3e after %d iterations", p, rel,
                               iters[p]);
         }

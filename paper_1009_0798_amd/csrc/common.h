@@ -137,7 +137,11 @@ struct ohm_hier {
     size_t part_cap = 0;
     double *d_norms = nullptr;       // [nprob * 6]
     size_t table_bytes = 0;          // device bytes of the tables and scratch above
-    double *h_dots = nullptr;        // pinned host copy of an iteration's norms [8 * nprob]
+    // pinned host copies of norms: [8 * nprob] of the latest reduction,
+    // then the iteration ring [2 * ITER_SLOTS * nprob], then the final
+    // norms of a step [6 * nprob]
+    double *h_dots = nullptr;
+    int bicg_pred = 0;               // iterations the last step's first BiCGStab pass took
     char *h_stage = nullptr;         // pinned staging of a step's host-built tables
     size_t stage_bytes = 0;
     hipEvent_t stage_ev = nullptr;   // recorded after the staged upload
@@ -329,15 +333,33 @@ ohm_status vbicg_s(int nblk, const int *prob_of, const int *active, long long cs
 ohm_status vbicg_xr(int nblk, const int *prob_of, const int *active, long long cs, const double *scal, double *x,
                     const double *ph, const double *sh, const double *sv, const double *t, double *r,
                     const double *rhat, double *part, hipStream_t s);
+// Record of the residual norms of consecutive BiCGStab iterations, so that the
+// host can queue several iterations before it reads them: iteration j since
+// the last restart stores {(r, r), (rhat, r)} of problem p at
+// buf[2 (nprob (j mod ITER_SLOTS) + p)], and a problem whose (r, r) is not
+// above tol2[p] (NaN included) leaves the active set (flags[p] = 0), so the
+// iterations queued behind it skip it.
+constexpr int ITER_SLOTS = 8;
+struct IterRing {
+    double *buf = nullptr;
+    int *flags = nullptr;
+    const double *tol2 = nullptr;
+};
 // per-problem sums of k <= 4 block partials into out[p][k], then the BiCGStab
-// scalar update `stage` (< 0: none) for the active problems
+// scalar update `stage` (< 0: none) for the active problems; stage 0 (restart)
+// also resets every problem's iteration count, and stage 4 (end of an
+// iteration) with ring.buf set records the norms in the ring as above
 ohm_status launch_reduce_scal(int nprob, int nrange, const long long *range_dev, const double *part, int k,
-                              double *out, int stage, const int *active, double *scal, hipStream_t s);
+                              double *out, int stage, const int *active, double *scal, hipStream_t s,
+                              IterRing ring = IterRing());
+// tol2[p] = rtol^2 max(|S|^2, 1e-300) from dots[2 p] = |S|^2, and problems whose
+// initial |r|^2 = dots[2 p + 1] is not above it (NaN included) leave the
+// active set
+ohm_status launch_conv_init(int nprob, const double *dots, double rtol, double *tol2, int *active, hipStream_t s);
 ohm_status vmean2(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,
                   hipStream_t s);
 ohm_status vaxpy1(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,
                   hipStream_t s);
-ohm_status vscal(int nprob, int stage, const int *active, const double *dots, int nq, double *scal, hipStream_t s);
 int scal_stride();
 
 }  // namespace ohm

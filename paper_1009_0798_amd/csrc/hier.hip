@@ -519,7 +519,7 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
     std::lock_guard<std::mutex> lock(capture_mutex());
     OHM_HIP(hipMalloc((void **)&H->d_scal, sizeof(double) * 4 * nprob));
     OHM_HIP(hipMalloc((void **)&H->d_norms, sizeof(double) * 8 * nprob));
-    OHM_HIP(hipHostMalloc((void **)&H->h_dots, sizeof(double) * 8 * nprob, hipHostMallocDefault));
+    OHM_HIP(hipHostMalloc((void **)&H->h_dots, sizeof(double) * (8 + 2 * ITER_SLOTS + 6) * nprob, hipHostMallocDefault));
     size_t maxnb = 1;
     for (int l = 0; l < H->nlev; ++l) maxnb = std::max(maxnb, (size_t)H->nb_host[l]);
     H->part_cap = maxnb * 8 + 2 * (size_t)nprob * OHM_MAX_LEVELS + 64;

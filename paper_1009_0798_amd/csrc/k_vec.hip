@@ -114,7 +114,7 @@ k_norms(int nblk, const int *__restrict__ prob_of, const int *__restrict__ activ
 }
 
 // Scalars per problem (double[SC_N]):
-enum { SC_RHO = 0, SC_ALPHA, SC_OMEGA, SC_BETA, SC_RHONEW, SC_RR, SC_SS, SC_N = 16 };
+enum { SC_RHO = 0, SC_ALPHA, SC_OMEGA, SC_BETA, SC_RHONEW, SC_RR, SC_SS, SC_IT, SC_N = 16 };
 
 // the result of a vector update, and optionally a copy of it in the
 // multigrid cycle's precision (c32 or c64, same layout)
@@ -263,25 +263,17 @@ __device__ __forceinline__ void scal_update(int stage, double *S, const double *
     if (stage == 0) S[SC_BETA] = 0.0;
 }
 
-// per-problem scalar updates (one thread per problem) from reduced products
-__global__ void k_scal(int nprob, int stage, const int *__restrict__ active, const double *__restrict__ dots, int nq,
-                       double *__restrict__ scal)
-{
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= nprob) return;
-    if (active && !active[p]) return;
-    scal_update(stage, scal + SC_N * p, dots + (long long)nq * p);
-}
-
 // Per-problem sums of k block partials (part[block][k]) followed by the
 // scalar update of `stage` (stage < 0: sums only).  One workgroup per problem,
 // 256 threads per quantity; every sum is formed exactly as by the block
 // reduction kernel (thread t owns the problem-local indices = t mod 256, wave
 // shuffle, then the 4 wavefronts in order), so results do not depend on the
-// other problems of the handle.
+// other problems of the handle.  Every problem's iteration count (SC_IT) is
+// reset by stage 0 and advanced by stage 4, active or not, so that the ring
+// slot of an iteration is the same for all problems.
 __global__ void __launch_bounds__(1024)
 k_reduce_scal(int nrange, const long long *__restrict__ range, const double *__restrict__ part, int k,
-              double *__restrict__ out, int stage, const int *__restrict__ active, double *__restrict__ scal)
+              double *__restrict__ out, int stage, const int *active, double *__restrict__ scal, IterRing ring)
 {
     __shared__ double sred[4][4];
     const int p = blockIdx.x;
@@ -293,7 +285,16 @@ k_reduce_scal(int nrange, const long long *__restrict__ range, const double *__r
             const long long b0 = range[2 * ((long long)p * nrange + r)], b1 = range[2 * ((long long)p * nrange + r) + 1];
             const long long n = b1 - b0;
             const long long first = ((tid - base) % 256 + 256) % 256;
-            for (long long i = first; i < n; i += 256) v = v + part[(b0 + i) * k + g];
+            // eight loads in flight, then the adds in index order
+            long long i = first;
+            for (; i + 7 * 256 < n; i += 8 * 256) {
+                double a[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] = part[(b0 + i + 256 * u) * k + g];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v = v + a[u];
+            }
+            for (; i < n; i += 256) v = v + part[(b0 + i) * k + g];
             base += n;
         }
         for (int o = 32; o > 0; o >>= 1) v = v + __shfl_down(v, o, 64);
@@ -308,8 +309,30 @@ k_reduce_scal(int nrange, const long long *__restrict__ range, const double *__r
             d[q] = t;
             out[(long long)p * k + q] = t;
         }
-        if (stage >= 0 && !(active && !active[p])) scal_update(stage, scal + SC_N * p, d);
+        double *S = scal + SC_N * p;
+        const bool on = !(active && !active[p]);
+        if (stage >= 0 && on) scal_update(stage, S, d);
+        if (stage == 0) S[SC_IT] = 0.0;
+        if (stage == 4 && ring.buf) {
+            const int it = (int)S[SC_IT];
+            double *slot = ring.buf + 2 * ((long long)gridDim.x * (it % ITER_SLOTS) + p);
+            slot[0] = d[0];
+            slot[1] = d[1];
+            S[SC_IT] = (double)(it + 1);
+            if (on && !(d[0] > ring.tol2[p])) ring.flags[p] = 0;
+        }
     }
+}
+
+// convergence thresholds and the initial active set (see launch_conv_init)
+__global__ void k_conv_init(int nprob, const double *__restrict__ dots, double rtol, double *__restrict__ tol2,
+                            int *__restrict__ active)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nprob) return;
+    const double t = rtol * rtol * fmax(dots[2 * p], 1e-300);
+    tol2[p] = t;
+    if (!(dots[2 * p + 1] > t)) active[p] = 0;
 }
 
 }  // namespace
@@ -377,11 +400,19 @@ ohm_status vbicg_xr(int nblk, const int *prob_of, const int *active, long long c
 }
 
 ohm_status launch_reduce_scal(int nprob, int nrange, const long long *range_dev, const double *part, int k,
-                              double *out, int stage, const int *active, double *scal, hipStream_t s)
+                              double *out, int stage, const int *active, double *scal, hipStream_t s, IterRing ring)
 {
     if (k < 1 || k > 4) return fail(OHM_ERR_ARG, "reduce + scalars takes 1 to 4 quantities, got %d", k);
-    k_reduce_scal<<<nprob, 256 * k, 0, s>>>(nrange, range_dev, part, k, out, stage, active, scal);
+    if (ring.buf && (stage != 4 || k < 2 || !ring.flags || !ring.tol2))
+        return fail(OHM_ERR_ARG, "the iteration ring is written by stage 4 with two norms and needs flags and thresholds");
+    k_reduce_scal<<<nprob, 256 * k, 0, s>>>(nrange, range_dev, part, k, out, stage, active, scal, ring);
     return check_launch("reduce + scalars");
+}
+
+ohm_status launch_conv_init(int nprob, const double *dots, double rtol, double *tol2, int *active, hipStream_t s)
+{
+    k_conv_init<<<(nprob + 63) / 64, 64, 0, s>>>(nprob, dots, rtol, tol2, active);
+    return check_launch("convergence thresholds");
 }
 
 ohm_status vmean2(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,
@@ -398,11 +429,6 @@ ohm_status vaxpy1(int nblk, const int *prob_of, const int *active, long long cs,
     return check_launch("axpy");
 }
 
-ohm_status vscal(int nprob, int stage, const int *active, const double *dots, int nq, double *scal, hipStream_t s)
-{
-    k_scal<<<(nprob + 63) / 64, 64, 0, s>>>(nprob, stage, active, dots, nq, scal);
-    return check_launch("scalars");
-}
 
 ohm_status vnorms(int nblk, const int *prob_of, const int *active, long long cs, const double *x, double *part,
                   hipStream_t s)

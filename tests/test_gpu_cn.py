@@ -325,6 +325,43 @@ def test_batched_equals_alone(ordering):
         assert np.linalg.norm(mine - ex) <= _bound(np.linalg.norm(S), ex), i
 
 
+def test_queued_iterations_equal_step_by_step():
+    """A step queues as many BiCGStab iterations as the previous step on the
+    handle needed, less one, before it reads their norms; each problem is
+    dropped on the device at the iteration that converges it.  A hard step
+    (dt 150x explicit) followed by an easy one (dt 2x) on the same handles, a
+    single problem and a batch of three, must give the easy step bit for bit
+    as fresh handles do (which read after every iteration), with the same
+    iteration counts."""
+    import paper_1009_0798_amd as ohm
+    announce("cn queued iterations vs step by step")
+    sizes = [16, 24, 32]
+    specs = [gen.uniform_spec(n) for n in sizes]
+    Bs = [gen.divfree(n, 2.0, seed=90 + i) for i, n in enumerate(sizes)]
+    Es = [gen.lognormal_eta(n, 3.0, seed=95 + i) for i, n in enumerate(sizes)]
+
+    def run(which, multiples, H=None):
+        ss = [specs[i] for i in which]
+        if H is None:
+            H = ohm.Hierarchy([(s.base_blocks, s.dx0, s.levels) for s in ss])
+        Bt = [cuda(np.concatenate([dense_to_blocks(Bs[i], specs[i].levels[0]) for i in which], axis=1))]
+        Et = [cuda(np.concatenate([dense_to_blocks(Es[i], specs[i].levels[0])[None] for i in which], axis=1))]
+        dts = [gen.explicit_dt(specs[i].dx0, 1.0, m) for i, m in zip(which, multiples)]
+        st, stats = ohm.ohm_cn_step(H, Bt, Et, dts, ohm.default_opts(rtol=RTOL, max_iters=300))
+        assert st == 0
+        return H, host(Bt[0]), stats
+
+    for which, hard, easy in (([2], [150.0], [2.0]), ([0, 1, 2], [150.0, 60.0, 150.0], [2.0, 30.0, 1.0])):
+        H, _, st_hard = run(which, hard)
+        _, got, st_q = run(which, easy, H)
+        _, ref_out, st_1 = run(which, easy)
+        print(which, [s["iters"] for s in st_hard], [s["iters"] for s in st_q])
+        assert max(s["iters"] for s in st_hard) - 1 > min(s["iters"] for s in st_q)   # iterations were masked
+        assert [s["iters"] for s in st_q] == [s["iters"] for s in st_1]
+        assert [s["rel_res"] for s in st_q] == [s["rel_res"] for s in st_1]
+        assert np.array_equal(got, ref_out)
+
+
 def test_noconv_reports_and_keeps_last_iterate():
     import paper_1009_0798_amd as ohm
     announce("cn noconv")
