@@ -79,8 +79,9 @@ Plan make_plan(const ohm_hier *h, const ohm_cn_opts *o)
         P.d_e[d] = take(tb * 3 * nc);
         P.d_tmp[d] = take(tb * 3 * nc);
         P.d_res[d] = take(tb * 3 * nc);
-        P.d_eta[d] = take(tb * nc);
         P.d_eta64[d] = take(8 * nc);
+        // an FP64 cycle reads the FP64 resistivity itself
+        P.d_eta[d] = P.T32 ? take(tb * nc) : P.d_eta64[d];
     }
     coarse_sizes(h, &P.inv_elems, &P.aug_elems);
     P.inv = take(8 * P.inv_elems + 8);
@@ -677,7 +678,8 @@ struct Solver {
             else
                 OHM_TRY(launch_dense_restrict<double>(h, -(d - 1), at<double>(P.d_eta64[d - 1]), at<double>(P.d_eta64[d]),
                                                       1, nullptr, st));
-            OHM_TRY(vconvert<double, T>(at<double>(P.d_eta64[d]), at<T>(P.d_eta[d]), h->dense_cells[d], st));
+            if (P.T32)
+                OHM_TRY(vconvert<double, T>(at<double>(P.d_eta64[d]), at<T>(P.d_eta[d]), h->dense_cells[d], st));
         }
         // coarsest grids: dense inverses (kept in the handle, rebuilt when
         // lam_dt or the coarsest resistivity changes)
