@@ -293,11 +293,18 @@ ohm_status ohm_cn_workspace_size(const ohm_hier *h, const ohm_cn_opts *opts, siz
  *   dt     : host double[nprob]
  *   workspace : device memory of at least ohm_cn_workspace_size bytes, 256-byte aligned
  *   stats  : host ohm_cn_stats[nprob] (may be NULL)
- * Synchronises `stream` once after the initial residual and once per outer
- * iteration to test convergence (the norms reach the host through a pinned
- * buffer of the handle), and once at the end.
+ * The norms that test convergence reach the host through a pinned buffer of
+ * the handle.  With BiCGStab the host queues the iterations it expects from
+ * the previous step on the same handle (and, from the expected count on, the
+ * verification and the copy to B) before it synchronises `stream`; a problem
+ * leaves the iteration on the device at the iteration that converges it, so
+ * results do not depend on how far ahead the host queued.  The iteration of
+ * eqs. (16)-(18) synchronises once after the initial residual and once per
+ * iteration.  B is complete when the call returns.
  * Returns OHM_ERR_NOCONV if a problem reached max_iters (B then holds the last
- * iterate and stats are filled) and OHM_ERR_NONFINITE on a non-finite norm.
+ * iterate and stats are filled) and OHM_ERR_NONFINITE on a non-finite norm
+ * (B then keeps its input values if the norm was that of the initial
+ * residual or of a BiCGStab iteration).
  */
 ohm_status ohm_cn_step(ohm_hier *h, void *const B[], const void *const eta[], const double *dt,
                        const ohm_cn_opts *opts, void *workspace, size_t ws_bytes,

@@ -31,6 +31,7 @@ struct Plan {
     size_t d_rhs[16], d_e[16], d_tmp[16], d_res[16], d_eta[16], d_eta64[16];
     size_t inv, aug, jobs, force, part, dots, scal, ranges, mlprob, active, cmask, coefs;
     size_t ring, tol2;          // norms of queued BiCGStab iterations, convergence thresholds
+    size_t hold;                // set on the device when a norm is non-finite: no copy out
     size_t rf;                  // FMG over AMR levels: right-hand side restricted under finer blocks
     size_t inv_elems = 0, aug_elems = 0;
 };
@@ -101,6 +102,7 @@ Plan make_plan(const ohm_hier *h, const ohm_cn_opts *o)
     P.mlprob = take(4 * (size_t)P.NBt);
     P.active = take(4 * (size_t)h->nprob);
     P.cmask = take(4 * (size_t)h->nprob * 17);
+    P.hold = take(4);
     P.coefs = take(8 * (size_t)h->nprob * 4);
     P.total = off;
     return P;
@@ -604,6 +606,7 @@ struct Solver {
         std::copy(coefs.begin(), coefs.end(), (double *)host(P.coefs));
         std::vector<int> ones(np, 1);
         std::copy(ones.begin(), ones.end(), (int *)host(P.active));
+        *(int *)host(P.hold) = 0;
         // coarsest grids: a dense inverse (job tables, force flags) or, for
         // grids above 768 unknowns, smoothing sweeps (mask per depth)
         njobs.assign(17, 0);
@@ -698,20 +701,31 @@ struct Solver {
         OHM_TRY(copy_dots(2));
         // thresholds of the stop rule; problems the initial guess already
         // satisfies leave the active set before any iteration is queued
-        return launch_conv_init(h->nprob, at<double>(P.dots), o->rtol, at<double>(P.tol2), active_mut, st);
+        return launch_conv_init(h->nprob, at<double>(P.dots), o->rtol, at<double>(P.tol2), active_mut, at<int>(P.hold),
+                                st);
     }
 
     // |S|^2 per problem
     std::vector<double> Snorm2;
 
     // true residual r = S - L x; its per-problem |r|^2 goes to the pinned
-    // buffer (h_dots[p], read after a synchronisation)
-    ohm_status true_residual()
+    // buffer (h_dots[2 nprob + p], read after a synchronisation; the first
+    // 2 nprob values hold |S|^2 and |r|^2 of the step's start)
+    // (into = P.r, or P.t for a verification queued before the host knows
+    // that the recurrence has converged: t is rewritten by every iteration
+    // before it is read).  It is formed for every problem: a problem that
+    // stopped earlier has the same x as when its residual was last formed,
+    // so it gets the same r again.
+    ohm_status true_residual(size_t into)
     {
-        OHM_TRY(composite(P.x, P.r, MODE_RESID, lam_dt, neg_lam_dt, P.S));
-        const double *xs[1] = {at<double>(P.r)};
-        OHM_TRY(dots(xs, xs, 1));
-        return copy_dots(1);
+        const int *keep = active;
+        active = nullptr;
+        ohm_status s = composite(P.x, into, MODE_RESID, lam_dt, neg_lam_dt, P.S);
+        const double *xs[1] = {at<double>(into)};
+        if (s == OHM_OK) s = dots(xs, xs, 1);
+        active = keep;
+        OHM_TRY(s);
+        return copy_dots(1, 2 * (size_t)h->nprob);
     }
 
     // device flags as last uploaded (setup uploads all ones)
@@ -757,6 +771,7 @@ struct Solver {
             ring.buf = at<double>(P.ring);
             ring.flags = active_mut;
             ring.tol2 = at<double>(P.tol2);
+            ring.hold = at<int>(P.hold);
             OHM_TRY(launch_reduce_scal(h->nprob, nlev(), at<long long>(P.ranges), at<double>(P.part), 2,
                                        at<double>(P.dots), 4, active, at<double>(P.scal), st, ring));
             OHM_HIP(hipMemcpyAsync(h_ring(), at<double>(P.ring), sizeof(double) * 2 * ITER_SLOTS * h->nprob,
@@ -770,10 +785,11 @@ struct Solver {
     // the first nq * nprob norms to the handle's pinned host buffer (part of a
     // captured iteration: one node, no separate copy command); read after a
     // synchronisation of the stream
-    ohm_status copy_dots(int nq)
+    // (at element `at_host` of the pinned buffer)
+    ohm_status copy_dots(int nq, size_t at_host = 0)
     {
-        OHM_HIP(hipMemcpyAsync(h->h_dots, at<double>(P.dots), sizeof(double) * nq * h->nprob, hipMemcpyDeviceToHost,
-                               st));
+        OHM_HIP(hipMemcpyAsync(h->h_dots + at_host, at<double>(P.dots), sizeof(double) * nq * h->nprob,
+                               hipMemcpyDeviceToHost, st));
         return OHM_OK;
     }
 
@@ -882,23 +898,24 @@ struct Solver {
         return run_explicit(nsteps);
     }
 
-    // the end of a step, queued: norms of the true residual r (into the
+    // the end of a step, queued: norms of the true residual `res` (into the
     // pinned buffer), average-down of x over the AMR levels and the copy to
-    // the user's fields.  It may be queued behind a true residual that turns
-    // out not to converge: the iteration then resumes (values of x under
-    // finer blocks are restored by every composite operator before use) and
-    // the end is queued again.
-    ohm_status finish_async()
+    // the user's fields (skipped on the device once a norm was non-finite).
+    // It may be queued behind a true residual that turns out not to
+    // converge: the iteration then resumes (values of x under finer blocks
+    // are restored by every composite operator before use) and the end is
+    // queued again.
+    ohm_status finish_async(size_t res)
     {
         const int np = h->nprob, L = nlev();
-        OHM_TRY(vnorms((int)P.NBt, mlprob, nullptr, VN, at<double>(P.r), at<double>(P.part), st));
+        OHM_TRY(vnorms((int)P.NBt, mlprob, nullptr, VN, at<double>(res), at<double>(P.part), st));
         OHM_TRY(reduce(6, 3, at<double>(P.dots)));
         OHM_HIP(hipMemcpyAsync(h_final(), at<double>(P.dots), sizeof(double) * 6 * np, hipMemcpyDeviceToHost, st));
         for (int l = L - 1; l >= 1; --l)
             OHM_TRY(launch_restrict_blk<double>(h, l, vec(P.x, l), VN, vec(P.x, l - 1), VN, 3, nullptr, st));
         for (int l = 0; l < L; ++l)
             OHM_TRY(vcopy_level<double, double>(vec(P.x, l), VN, (double *)Buser[l], (long long)h->nb_host[l] * NC,
-                                                (long long)h->nb_host[l] * NC, 3, st));
+                                                (long long)h->nb_host[l] * NC, 3, st, at<int>(P.hold)));
         return OHM_OK;
     }
 
@@ -954,13 +971,18 @@ struct Solver {
             }
         } else {
             // BiCGStab; restarted from the true residual when the recurrence
-            // residual has converged but the true one has not.  The first
-            // pass of a step queues as many iterations as the previous step's
-            // first pass took, less one, before it reads their norms (the
-            // device drops each problem at the iteration that converges it,
-            // so the iterations queued behind leave it unchanged); later reads
-            // follow every iteration.
+            // residual has converged but the true one has not.  The host
+            // queues iterations ahead of its reads: the first pass of a step
+            // queues as many as the previous step's first pass took before
+            // its first read (the device drops each problem at the iteration
+            // that converges it, so the iterations queued behind leave it
+            // unchanged), later reads follow every iteration.  From the
+            // predicted count on, the verifying true residual (into t) and the
+            // end of the step are queued behind the iterations as well, so a
+            // step whose prediction holds takes one synchronisation; when the
+            // recurrence has not converged they are simply queued again.
             int it_total = 0, first_pass = -1;
+            const int pred = h->bicg_pred;
             while (it_total < maxit && (!known || any(act))) {
                 // restart: rhat = r (copied by the dot kernel that forms
                 // (r, r)), rho = alpha = omega = 1, and a first direction p = r
@@ -971,19 +993,25 @@ struct Solver {
                     OHM_TRY(dots(xs, xs, 1, 0, at<double>(P.rhat)));
                 }
                 std::vector<int> inner(act);
-                int since = 0;   // iterations since the restart (the ring's slot count)
+                int since = 0;          // iterations since the restart (the ring's slot count)
+                bool spec = false;      // a verification is queued behind the last iteration
                 while (it_total < maxit) {
                     int nb = 1;
-                    if (first_pass < 0 && since == 0)
-                        nb = std::max(1, std::min({h->bicg_pred - 1, ITER_SLOTS, maxit - it_total}));
+                    if (first_pass < 0 && since == 0) nb = std::max(1, std::min({pred, ITER_SLOTS, maxit - it_total}));
                     for (int j = 0; j < nb; ++j) OHM_TRY(replay(1, [&]() { return bicg_iter(); }));
                     it_total += nb;
+                    spec = first_pass < 0 && pred > 0 && since + nb >= pred;
+                    if (spec) {
+                        OHM_TRY(true_residual(P.t));
+                        OHM_TRY(finish_async(P.t));
+                    }
                     OHM_HIP(hipStreamSynchronize(st));
                     if (!known) {
                         OHM_TRY(read_start());
                         inner = act;
                     }
-                    for (int j = 0; j < nb; ++j) {
+                    int done_at = -1;
+                    for (int j = 0; j < nb && done_at < 0; ++j) {
                         const double *d = h_ring() + 2 * (size_t)np * ((since + j) % ITER_SLOTS);
                         for (int p = 0; p < np; ++p)
                             if (inner[p]) {
@@ -993,42 +1021,44 @@ struct Solver {
                                     return fail(OHM_ERR_NONFINITE, "problem %d: non-finite residual", p);
                                 if (converged(p, d[2 * p])) inner[p] = 0;
                             }
+                        if (!any(inner)) done_at = since + j + 1;
                     }
                     since += nb;
                     // the device dropped the same problems as the iterations ran
                     act_dev = inner;
-                    if (!any(inner)) break;
+                    if (done_at >= 0) {
+                        if (first_pass < 0) first_pass = done_at;
+                        break;
+                    }
                 }
                 if (first_pass < 0) first_pass = since;
                 if (!any(act)) break;   // every problem satisfied by its initial guess
                 // verify with the true residual, the end of the step queued
-                // behind it.  It is formed for every problem (no flag upload):
-                // a problem that stopped earlier has the same x as when its
-                // residual was last formed, so it gets the same r again.
-                {
-                    const int *keep = active;
-                    active = nullptr;
-                    const ohm_status rs = true_residual();
-                    active = keep;
-                    OHM_TRY(rs);
+                // behind it (unless both are queued already)
+                if (!spec || any(inner)) {
+                    OHM_TRY(true_residual(P.r));
+                    OHM_TRY(finish_async(P.r));
+                    OHM_HIP(hipStreamSynchronize(st));
+                    spec = false;
                 }
-                OHM_TRY(finish_async());
-                OHM_HIP(hipStreamSynchronize(st));
                 finished = true;
                 for (int p = 0; p < np; ++p)
                     if (act[p]) {
-                        rfin[p] = h->h_dots[p];
+                        rfin[p] = h->h_dots[2 * (size_t)np + p];
                         if (converged(p, rfin[p])) act[p] = 0;
                     }
                 if (any(act)) {
                     finished = false;
+                    // the restart reads the true residual from r
+                    if (spec)
+                        OHM_TRY(vconvert<double, double>(at<double>(P.t), at<double>(P.r), 3 * VN, st));
                     OHM_TRY(set_active(act));
                 }
             }
             h->bicg_pred = first_pass;
         }
         if (!finished) {
-            OHM_TRY(finish_async());
+            OHM_TRY(finish_async(P.r));
             OHM_HIP(hipStreamSynchronize(st));
         }
         const double *nrm = h_final();

@@ -137,9 +137,11 @@ struct ohm_hier {
     size_t part_cap = 0;
     double *d_norms = nullptr;       // [nprob * 6]
     size_t table_bytes = 0;          // device bytes of the tables and scratch above
-    // pinned host copies of norms: [8 * nprob] of the latest reduction,
-    // then the iteration ring [2 * ITER_SLOTS * nprob], then the final
-    // norms of a step [6 * nprob]
+    // pinned host copies of norms: [8 * nprob] of reductions (a step's
+    // start: |S|^2, |r|^2 at [0, 2 nprob); the verifying true residual at
+    // [2 nprob, 3 nprob); an iteration of eqs. 16-18 at [0, nprob)), then the
+    // iteration ring [2 * ITER_SLOTS * nprob], then the final norms of a
+    // step [6 * nprob]
     double *h_dots = nullptr;
     int bicg_pred = 0;               // iterations the last step's first BiCGStab pass took
     char *h_stage = nullptr;         // pinned staging of a step's host-built tables
@@ -317,7 +319,8 @@ ohm_status vfill(T *a, long long n, T v, hipStream_t s);
 template <typename S, typename D>
 ohm_status vconvert(const S *a, D *b, long long n, hipStream_t s);
 template <typename S, typename D>
-ohm_status vcopy_level(const S *a, long long acs, D *b, long long bcs, long long n, int ncomp, hipStream_t s);
+ohm_status vcopy_level(const S *a, long long acs, D *b, long long bcs, long long n, int ncomp, hipStream_t s,
+                       const int *hold = nullptr);
 ohm_status vdot(int nblk, const int *prob_of, const int *active, long long cs, const double *const *x,
                 const double *const *y, int nq, double *part, hipStream_t s, double *copy = nullptr);
 ohm_status vnorms(int nblk, const int *prob_of, const int *active, long long cs, const double *x, double *part,
@@ -338,12 +341,15 @@ ohm_status vbicg_xr(int nblk, const int *prob_of, const int *active, long long c
 // the last restart stores {(r, r), (rhat, r)} of problem p at
 // buf[2 (nprob (j mod ITER_SLOTS) + p)], and a problem whose (r, r) is not
 // above tol2[p] (NaN included) leaves the active set (flags[p] = 0), so the
-// iterations queued behind it skip it.
+// iterations queued behind it skip it; a non-finite (r, r) of an active
+// problem also sets *hold, which turns the copy of the result to the user's
+// fields into a no-op (a step that fails leaves them as they were).
 constexpr int ITER_SLOTS = 8;
 struct IterRing {
     double *buf = nullptr;
     int *flags = nullptr;
     const double *tol2 = nullptr;
+    int *hold = nullptr;
 };
 // per-problem sums of k <= 4 block partials into out[p][k], then the BiCGStab
 // scalar update `stage` (< 0: none) for the active problems; stage 0 (restart)
@@ -354,8 +360,9 @@ ohm_status launch_reduce_scal(int nprob, int nrange, const long long *range_dev,
                               IterRing ring = IterRing());
 // tol2[p] = rtol^2 max(|S|^2, 1e-300) from dots[2 p] = |S|^2, and problems whose
 // initial |r|^2 = dots[2 p + 1] is not above it (NaN included) leave the
-// active set
-ohm_status launch_conv_init(int nprob, const double *dots, double rtol, double *tol2, int *active, hipStream_t s);
+// active set; a non-finite initial |r|^2 sets *hold (see IterRing)
+ohm_status launch_conv_init(int nprob, const double *dots, double rtol, double *tol2, int *active, int *hold,
+                            hipStream_t s);
 ohm_status vmean2(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,
                   hipStream_t s);
 ohm_status vaxpy1(int nblk, const int *prob_of, const int *active, long long cs, double *x, const double *y,

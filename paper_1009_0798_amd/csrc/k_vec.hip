@@ -33,8 +33,9 @@ __global__ void k_convert(const S *__restrict__ a, D *__restrict__ b, long long 
 // per-level arrays and the multi-level vectors)
 template <typename S, typename D>
 __global__ void k_copy_level(const S *__restrict__ a, long long acs, D *__restrict__ b, long long bcs, long long n,
-                             int ncomp)
+                             int ncomp, const int *__restrict__ hold)
 {
+    if (hold && *hold) return;
     for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
         for (int c = 0; c < ncomp; ++c) b[c * bcs + i] = (D)a[c * acs + i];
 }
@@ -320,19 +321,21 @@ k_reduce_scal(int nrange, const long long *__restrict__ range, const double *__r
             slot[1] = d[1];
             S[SC_IT] = (double)(it + 1);
             if (on && !(d[0] > ring.tol2[p])) ring.flags[p] = 0;
+            if (on && !isfinite(d[0])) *ring.hold = 1;
         }
     }
 }
 
 // convergence thresholds and the initial active set (see launch_conv_init)
 __global__ void k_conv_init(int nprob, const double *__restrict__ dots, double rtol, double *__restrict__ tol2,
-                            int *__restrict__ active)
+                            int *__restrict__ active, int *__restrict__ hold)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nprob) return;
     const double t = rtol * rtol * fmax(dots[2 * p], 1e-300);
     tol2[p] = t;
     if (!(dots[2 * p + 1] > t)) active[p] = 0;
+    if (!isfinite(dots[2 * p + 1])) *hold = 1;
 }
 
 }  // namespace
@@ -357,10 +360,11 @@ ohm_status vconvert(const S *a, D *b, long long n, hipStream_t s)
 }
 
 template <typename S, typename D>
-ohm_status vcopy_level(const S *a, long long acs, D *b, long long bcs, long long n, int ncomp, hipStream_t s)
+ohm_status vcopy_level(const S *a, long long acs, D *b, long long bcs, long long n, int ncomp, hipStream_t s,
+                       const int *hold)
 {
     if (n <= 0) return OHM_OK;
-    k_copy_level<S, D><<<grid_for(n), 256, 0, s>>>(a, acs, b, bcs, n, ncomp);
+    k_copy_level<S, D><<<grid_for(n), 256, 0, s>>>(a, acs, b, bcs, n, ncomp, hold);
     return check_launch("copy level");
 }
 
@@ -403,15 +407,16 @@ ohm_status launch_reduce_scal(int nprob, int nrange, const long long *range_dev,
                               double *out, int stage, const int *active, double *scal, hipStream_t s, IterRing ring)
 {
     if (k < 1 || k > 4) return fail(OHM_ERR_ARG, "reduce + scalars takes 1 to 4 quantities, got %d", k);
-    if (ring.buf && (stage != 4 || k < 2 || !ring.flags || !ring.tol2))
+    if (ring.buf && (stage != 4 || k < 2 || !ring.flags || !ring.tol2 || !ring.hold))
         return fail(OHM_ERR_ARG, "the iteration ring is written by stage 4 with two norms and needs flags and thresholds");
     k_reduce_scal<<<nprob, 256 * k, 0, s>>>(nrange, range_dev, part, k, out, stage, active, scal, ring);
     return check_launch("reduce + scalars");
 }
 
-ohm_status launch_conv_init(int nprob, const double *dots, double rtol, double *tol2, int *active, hipStream_t s)
+ohm_status launch_conv_init(int nprob, const double *dots, double rtol, double *tol2, int *active, int *hold,
+                            hipStream_t s)
 {
-    k_conv_init<<<(nprob + 63) / 64, 64, 0, s>>>(nprob, dots, rtol, tol2, active);
+    k_conv_init<<<(nprob + 63) / 64, 64, 0, s>>>(nprob, dots, rtol, tol2, active, hold);
     return check_launch("convergence thresholds");
 }
 
@@ -447,8 +452,8 @@ template ohm_status vconvert<float, double>(const float *, double *, long long, 
 template ohm_status vconvert<double, double>(const double *, double *, long long, hipStream_t);
 template ohm_status vconvert<float, float>(const float *, float *, long long, hipStream_t);
 template ohm_status vcopy_level<double, double>(const double *, long long, double *, long long, long long, int,
-                                                hipStream_t);
+                                                 hipStream_t, const int *);
 template ohm_status vcopy_level<double, float>(const double *, long long, float *, long long, long long, int,
-                                               hipStream_t);
+                                                hipStream_t, const int *);
 
 }  // namespace ohm

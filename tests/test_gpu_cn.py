@@ -240,7 +240,9 @@ def test_amr_three_levels_corner_gap_against_oracle(precision, ordering):
 @pytest.mark.parametrize("where", ["B", "eta"])
 def test_nonfinite_input_is_reported(where):
     """A NaN in B or in the resistivity reaches the source and the initial
-    residual: the step stops with OHM_ERR_NONFINITE before any iteration."""
+    residual: the step stops with OHM_ERR_NONFINITE and leaves B unchanged,
+    also when it follows a clean step on the same handle (iterations and the
+    copy to B are then queued before the first synchronisation)."""
     import paper_1009_0798_amd as ohm
     from paper_1009_0798_amd import _lib
     announce(f"cn non-finite input in {where}")
@@ -253,11 +255,21 @@ def test_nonfinite_input_is_reported(where):
     else:
         eta[2, 5, 7] = np.nan
     H = hier(spec)
-    Bt = [cuda(dense_to_blocks(B, spec.levels[0]))]
+    dt = gen.explicit_dt(spec.dx0, 1.0, 50.0)
+    # a clean step first, so that the failing one queues iterations (and the
+    # copy to B) before its first synchronisation
+    clean = [cuda(dense_to_blocks(gen.divfree(n, 2.0, seed=3), spec.levels[0]))]
+    Eclean = [cuda(dense_to_blocks(gen.lognormal_eta(n, 1.0, seed=4), spec.levels[0])[None])]
+    st, _ = ohm.ohm_cn_step(H, clean, Eclean, dt, ohm.default_opts())
+    assert st == 0
+    Bin = dense_to_blocks(B, spec.levels[0])
+    Bt = [cuda(Bin)]
     Et = [cuda(dense_to_blocks(eta, spec.levels[0])[None])]
     with pytest.raises(_lib.OhmError) as err:
-        ohm.ohm_cn_step(H, Bt, Et, gen.explicit_dt(spec.dx0, 1.0, 50.0), ohm.default_opts())
+        ohm.ohm_cn_step(H, Bt, Et, dt, ohm.default_opts())
     assert err.value.status == _lib.OHM_ERR_NONFINITE
+    # the failed step leaves B as it was
+    assert np.array_equal(host(Bt[0]), Bin, equal_nan=True)
 
 
 @pytest.mark.parametrize("lam", [0.5, 1.0])
@@ -352,6 +364,7 @@ def test_queued_iterations_equal_step_by_step():
         return H, host(Bt[0]), stats
 
     for which, hard, easy in (([2], [150.0], [2.0]), ([0, 1, 2], [150.0, 60.0, 150.0], [2.0, 30.0, 1.0])):
+        # hard then easy: more iterations queued than the easy step needs
         H, _, st_hard = run(which, hard)
         _, got, st_q = run(which, easy, H)
         _, ref_out, st_1 = run(which, easy)
@@ -359,6 +372,16 @@ def test_queued_iterations_equal_step_by_step():
         assert max(s["iters"] for s in st_hard) - 1 > min(s["iters"] for s in st_q)   # iterations were masked
         assert [s["iters"] for s in st_q] == [s["iters"] for s in st_1]
         assert [s["rel_res"] for s in st_q] == [s["rel_res"] for s in st_1]
+        assert [s["max_res"] for s in st_q] == [s["max_res"] for s in st_1]
+        assert np.array_equal(got, ref_out)
+        # easy then hard: fewer queued than needed, verifications queued
+        # behind iterations that have not converged yet
+        H, _, _ = run(which, easy)
+        _, got, st_q = run(which, hard, H)
+        _, ref_out, st_1 = run(which, hard)
+        assert [s["iters"] for s in st_q] == [s["iters"] for s in st_1]
+        assert [s["rel_res"] for s in st_q] == [s["rel_res"] for s in st_1]
+        assert [s["max_res"] for s in st_q] == [s["max_res"] for s in st_1]
         assert np.array_equal(got, ref_out)
 
 
