@@ -93,8 +93,9 @@ struct DenseLevelDev {
     int *tiles = nullptr;      // [ntile][2]: problem, first cell
     int ntile_all = 0;         // tiles of every problem present
     int *tiles_all = nullptr;
-    // smoothing: 8^3 tiles (fused sweeps) of problems whose grid is a whole
-    // number of tiles, 256-cell tiles (two half-sweeps) of the others;
+    // smoothing: 8^3 tiles (fused sweeps) of problems whose grid has even
+    // edges (the last tile along an edge that is not a multiple of 8 wraps
+    // around), 256-cell tiles (two half-sweeps) of the others;
     // "all" variants cover every problem present, the others the problems
     // that are not coarsest here
     int nftile = 0, nftile_all = 0, nptile = 0, nptile_all = 0;

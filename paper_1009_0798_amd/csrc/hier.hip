@@ -474,7 +474,11 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
             double h = P.dx0 * (double)(1 << dd);
             q.inv_h2 = 1.0 / (h * h);
             int nc = q.nx * q.ny * q.nz;
-            const bool tiled = q.nx % NB == 0 && q.ny % NB == 0 && q.nz % NB == 0;
+            // fused sweeps on 8^3 tiles for even edges (the last tile of an
+            // edge that is not a multiple of 8 wraps around), two half-sweeps
+            // on 256-cell runs for an odd edge (its wrap would change colours)
+            const bool tiled = q.nx % 2 == 0 && q.ny % 2 == 0 && q.nz % 2 == 0;
+            const int ntiles = ((q.nx + NB - 1) / NB) * ((q.ny + NB - 1) / NB) * ((q.nz + NB - 1) / NB);
             for (int s = 0; s < nc; s += 256) {
                 tiles_all.push_back(p);
                 tiles_all.push_back(s);
@@ -492,7 +496,7 @@ static ohm_status build(ohm_hier *H, const ohm_problem_desc *probs, int nprob)
                 }
             }
             if (tiled)
-                for (int t = 0; t < nc / NC; ++t) {
+                for (int t = 0; t < ntiles; ++t) {
                     ft_all.push_back(p);
                     ft_all.push_back(t);
                     if (q.active) {

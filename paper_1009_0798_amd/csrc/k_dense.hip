@@ -71,24 +71,37 @@ k_dense_stencil(const int *__restrict__ tiles, const DenseProbDev *__restrict__ 
     }
 }
 
-// fused red-black sweep on 8^3 tiles of a dense level (periodic wrap)
+// Fused red-black sweep on 8^3 tiles of a dense level (periodic wrap).  A
+// grid whose edges are even but not multiples of 8 is covered by
+// ceil(n / 8) tiles per axis: the cells of the last tile past the edge are
+// copies of cells at the start (an even period keeps their colour), computed
+// from the same values as by the tile that owns them, so the duplicate
+// stores write equal values.
+__device__ __forceinline__ int wrap_cell(int i, int n)
+{
+    // i >= -2; past the first period only on grids narrower than a tile
+    if (i < 0) return i + n;
+    if (i >= n) {
+        i -= n;
+        if (i >= n) i %= n;
+    }
+    return i;
+}
+
 struct DenseAddr {
     static constexpr bool ghosts = false;
     DenseProbDev q;
     int ox, oy, oz;
     __device__ __forceinline__ long long at(int x, int y, int z) const
     {
-        int i = ox + x, j = oy + y, k = oz + z;
-        i = i < 0 ? i + q.nx : (i >= q.nx ? i - q.nx : i);
-        j = j < 0 ? j + q.ny : (j >= q.ny ? j - q.ny : j);
-        k = k < 0 ? k + q.nz : (k >= q.nz ? k - q.nz : k);
+        const int i = wrap_cell(ox + x, q.nx), j = wrap_cell(oy + y, q.ny), k = wrap_cell(oz + z, q.nz);
         return q.off + i + (long long)q.nx * (j + (long long)q.ny * k);
     }
 };
 
 __device__ __forceinline__ DenseAddr dense_tile(const DenseProbDev &q, int t)
 {
-    const int tx = q.nx >> 3, ty = q.ny >> 3;
+    const int tx = (q.nx + 7) >> 3, ty = (q.ny + 7) >> 3;
     return DenseAddr{q, 8 * (t % tx), 8 * ((t / tx) % ty), 8 * (t / (tx * ty))};
 }
 
@@ -215,9 +228,11 @@ k_dense_resid_restrict(const int *__restrict__ ftiles, const DenseProbDev *__res
 #pragma unroll
         for (int c = 0; c < 3; ++c) sB[c][threadIdx.x + 256 * half] = r[half][c];
     __syncthreads();
-    if (threadIdx.x < 64) {
-        const int i = threadIdx.x & 3, j = (threadIdx.x >> 2) & 3, k = threadIdx.x >> 4;
-        const DenseProbDev cq = cdp[pr];
+    const int i = threadIdx.x & 3, j = (threadIdx.x >> 2) & 3, k = threadIdx.x >> 4;
+    const DenseProbDev cq = cdp[pr];
+    // a coarse cell past the grid's edge belongs to the tile that owns its
+    // children (they are copies here)
+    if (threadIdx.x < 64 && A.ox / 2 + i < cq.nx && A.oy / 2 + j < cq.ny && A.oz / 2 + k < cq.nz) {
         const long long ci = cq.off + (A.ox / 2 + i) + (long long)cq.nx * ((A.oy / 2 + j) + (long long)cq.ny * (A.oz / 2 + k));
 #pragma unroll
         for (int c = 0; c < 3; ++c) {

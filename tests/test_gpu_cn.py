@@ -182,6 +182,37 @@ def test_ragged_box_variable_eta():
     assert np.linalg.norm(got - ex) <= _bound(np.linalg.norm(S), ex)
 
 
+@pytest.mark.parametrize("precision,cycle", [(0, 0), (1, 0), (0, 1)])
+def test_ragged_box_one_iteration_equals_the_oracle_cycle(precision, cycle):
+    """One iteration of eqs. (16)-(18) on the 24 x 16 x 32 box against the
+    oracle's V(2, 2) cycle or FMG on the same hierarchy: the dense levels
+    12x8x16 and 6x4x8 are covered by 8^3 tiles whose last tile along an edge
+    wraps around (fused sweeps, the sweep that adds the prolonged correction,
+    the residual with restriction), the odd 3x2x4 coarsest grid is solved
+    directly.  Bounds as for the 32^3 cycle."""
+    import paper_1009_0798_amd as ohm
+    announce(f"cn ragged box one iteration precision={precision} cycle={cycle}")
+    spec = gen.HierSpec((3, 2, 4), 0.05, [gen.full_level((3, 2, 4))])
+    nx, ny, nz = spec.cells(0)
+    rng = np.random.default_rng(33)
+    B = rng.standard_normal((3, nz, ny, nx))
+    eta = np.exp(rng.uniform(-3, 0, (nz, ny, nx)))
+    h = spec.dx0
+    dt = gen.explicit_dt(h, 1.0, 30.0)
+    st, stats, got = _gpu_step(spec, B, eta, dt, precision=precision, outer=0, cycle=cycle, n_vcycles=1,
+                               nu_pre=2, nu_post=2, nu_coarse=0, max_iters=1, rtol=1e-14)
+    assert st == ohm._lib.OHM_ERR_NOCONV and stats[0]["iters"] == 1
+    lam_dt = 0.5 * dt
+    S = ref.source(B, eta, h, dt)
+    levels = mg.hierarchy(eta, h, lam_dt)
+    assert [lv.eta.shape for lv in levels] == [(32, 16, 24), (16, 8, 12), (8, 4, 6), (4, 2, 3)]
+    R0 = ref.residual(B, S, eta, h, lam_dt)
+    e = mg.vcycle(levels, R0, 2, 2) if cycle == 0 else mg.fmg(levels, R0, 1, 2, 2)
+    err = np.abs(got - (B + e)).max() / np.abs(e).max()
+    print("stats", stats, "max err / max correction", err)
+    assert err <= (1e-11 if precision == 0 else 2e-5)
+
+
 def test_amr_two_levels_against_oracle():
     announce("cn amr 2 levels")
     spec = gen.config_amr2(n_base=32, extra_frac=0.2, seed=4)

@@ -114,9 +114,10 @@ def test_uniform_apply_residual_smooth(dtype):
 @pytest.mark.parametrize("dtype,bb", [("f64", (3, 2, 4)), ("f32", (3, 2, 4)), ("f64", (4, 4, 2)), ("f32", (4, 4, 2))])
 def test_dense_levels_and_transfers(dtype, bb):
     """Restriction level 0 -> -1 -> -2, prolongation back, and the stencil
-    calls on the dense levels.  Box 24 x 16 x 32: coarsenings 12x8x16, 6x4x8,
-    3x2x4 (two half-sweep path); box 32 x 32 x 16: level -1 is 16x16x8, a whole
-    number of 8^3 tiles (fused-sweep path)."""
+    calls on the dense levels.  Box 24 x 16 x 32: coarsenings 12x8x16 and
+    6x4x8 (fused sweeps on 8^3 tiles, the last tile along an edge wrapping
+    around) and 3x2x4 (odd: two half-sweeps); box 32 x 32 x 16: level -1 is
+    16x16x8, a whole number of 8^3 tiles."""
     import torch
     import paper_1009_0798_amd as ohm
     announce(f"dense levels {dtype} {bb}")
@@ -160,9 +161,21 @@ def test_dense_levels_and_transfers(dtype, bb):
     assert np.abs(host(out).reshape(ex1.shape) - ref.apply(ex1, e1, h1, lam_dt)).max() <= tol * scale
     ohm.ohm_residual(H, -1, c1, St1, et1, lam_dt, R=out)
     assert np.abs(host(out).reshape(ex1.shape) - ref.residual(ex1, S1, e1, h1, lam_dt)).max() <= tol * scale
-    Bs = c1.clone()
-    ohm.ohm_smooth(H, -1, Bs, St1, et1, lam_dt, 2, torch.empty_like(c1))
-    assert np.abs(host(Bs).reshape(ex1.shape) - ref.smooth(ex1, S1, e1, h1, lam_dt, 2)).max() <= 8 * tol * scale
+    for ns in (1, 2, 3):
+        Bs = c1.clone()
+        ohm.ohm_smooth(H, -1, Bs, St1, et1, lam_dt, ns, torch.empty_like(c1))
+        ex = ref.smooth(ex1, S1, e1, h1, lam_dt, ns)
+        assert np.abs(host(Bs).reshape(ex1.shape) - ex).max() <= 8 * ns * tol * scale, ns
+    if bb == (3, 2, 4):
+        # level -2 (6 x 4 x 8): one 8^3 tile that wraps around in x and y
+        e2, S2, h2 = ref.restrict(e1), ref.restrict(S1), 2 * h1
+        et2, St2 = cuda(e2.reshape(1, -1), tdt), cuda(S2.reshape(3, -1), tdt)
+        scale2 = _scale(ex2, e2, lam_dt, h2)
+        for ns in (1, 2):
+            Bs = c2.clone()
+            ohm.ohm_smooth(H, -2, Bs, St2, et2, lam_dt, ns, torch.empty_like(c2))
+            ex = ref.smooth(ex2, S2, e2, h2, lam_dt, ns)
+            assert np.abs(host(Bs).reshape(ex2.shape) - ex).max() <= 8 * ns * tol * scale2, ns
     for ns in (1, 2):
         Bs = c1.clone()
         ohm.ohm_smooth(H, -1, Bs, St1, et1, lam_dt, ns, torch.empty_like(c1), ordering=1)
