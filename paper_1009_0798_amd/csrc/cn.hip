@@ -708,14 +708,13 @@ struct Solver {
     // |S|^2 per problem
     std::vector<double> Snorm2;
 
-    // true residual r = S - L x; its per-problem |r|^2 goes to the pinned
-    // buffer (h_dots[2 nprob + p], read after a synchronisation; the first
-    // 2 nprob values hold |S|^2 and |r|^2 of the step's start)
-    // (into = P.r, or P.t for a verification queued before the host knows
-    // that the recurrence has converged: t is rewritten by every iteration
-    // before it is read).  It is formed for every problem: a problem that
-    // stopped earlier has the same x as when its residual was last formed,
-    // so it gets the same r again.
+    // True residual S - L x into `into` (P.r, or P.t for a verification
+    // queued before the host knows that the recurrence has converged: every
+    // iteration rewrites t before reading it); its per-problem square norm
+    // goes to the pinned buffer at h_dots[2 nprob + p] (the first 2 nprob
+    // values hold |S|^2 and |r|^2 of the step's start).  It is formed for
+    // every problem: a problem that stopped earlier has the same x as when
+    // its residual was last formed, so it gets the same residual again.
     ohm_status true_residual(size_t into)
     {
         const int *keep = active;
