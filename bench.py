@@ -11,6 +11,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import statistics
 import os
 import sys
 import time
@@ -23,6 +24,7 @@ HBM_PEAK_GBS = 8000.0
 # below it) picked by the autotuner on MI355X, per precision of the cycle, for
 # the 128^3 log-normal workload, and for the two-level AMR workload
 SCHEDULE = {0: (2, 5), 1: (2, 5)}
+REPEATS = 5                 # timed blocks of the kernel rates (median)
 NU_COARSE = 1
 AMR_SCHEDULE = (4, 4)
 SERVE_SCHEDULE = (2, 2, 0)   # (pre, post, below the base grid; 0 = as the base grid) for serving
@@ -143,9 +145,10 @@ def run_steps(ohm, H, B0, E, dt, K, precision, ws):
 
 
 def smoother_rate(ohm, H, B, S, E, lam_dt, dtype, nsweeps=10):
-    """Average duration of one smoother launch on the level-0 blocks (one
-    fused red-black sweep per launch on a complete periodic level), measured
-    with HIP events on the stream the library launches on."""
+    """Duration of one smoother launch on the level-0 blocks (one fused
+    red-black sweep per launch on a complete periodic level), measured with
+    HIP events on the stream the library launches on: the median over
+    REPEATS blocks of the per-launch average of `nsweeps` launches."""
     import torch
     Bt = B.to(dtype).clone()
     St = S.to(dtype).contiguous()
@@ -154,11 +157,14 @@ def smoother_rate(ohm, H, B, S, E, lam_dt, dtype, nsweeps=10):
     ohm.ohm_smooth(H, 0, Bt, St, Et, lam_dt, 2, tmp)        # warm
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    ohm.ohm_smooth(H, 0, Bt, St, Et, lam_dt, nsweeps, tmp)
-    ev1.record()
-    torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / 1e3 / nsweeps
+    runs = []
+    for _ in range(REPEATS):
+        ev0.record()
+        ohm.ohm_smooth(H, 0, Bt, St, Et, lam_dt, nsweeps, tmp)
+        ev1.record()
+        torch.cuda.synchronize()
+        runs.append(ev0.elapsed_time(ev1) / 1e3 / nsweeps)
+    return statistics.median(runs)
 
 
 def cpu_model() -> str:
@@ -577,9 +583,10 @@ def bench_e8(args):
 
 
 def stencil_rate(ohm, H, B, S, E, coef, kind, nlaunch=10):
-    """Average duration of one launch of the level-0 operator apply
-    (out = B + coef div F(B)) or residual (R = S - L B, no norms), measured
-    with HIP events on the stream the library launches on."""
+    """Duration of one launch of the level-0 operator apply (out = B + coef
+    div F(B)) or residual (R = S - L B, no norms), measured with HIP events
+    on the stream the library launches on: the median over REPEATS blocks of
+    the per-launch average of `nlaunch` launches."""
     import torch
     out = torch.empty_like(B)
 
@@ -593,12 +600,15 @@ def stencil_rate(ohm, H, B, S, E, coef, kind, nlaunch=10):
     once()
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(nlaunch):
-        once()
-    ev1.record()
-    torch.cuda.synchronize()
-    return ev0.elapsed_time(ev1) / 1e3 / nlaunch
+    runs = []
+    for _ in range(REPEATS):
+        ev0.record()
+        for _ in range(nlaunch):
+            once()
+        ev1.record()
+        torch.cuda.synchronize()
+        runs.append(ev0.elapsed_time(ev1) / 1e3 / nlaunch)
+    return statistics.median(runs)
 
 
 def random_level(n, seed=11):
@@ -749,6 +759,7 @@ def main():
                      "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic("sweep_f64", n),
                      "us_per_launch": t_sw * 1e6, "bytes_per_launch": bytes_sw,
+                     "timing": f"median of {REPEATS} blocks of 10 launches (HIP events on the library's stream)",
                      "residency": f"{n}^3: {bytes_sw / 1e6:.0f} MB working set"
                                   + (", inside the 256 MB last-level cache" if bytes_sw < 256e6 else "")},
     }
@@ -761,6 +772,7 @@ def main():
                "achieved": ch * 80 / t_h / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": ch * 80 / t_h / 1e9 / HBM_PEAK_GBS, "traffic": counter_traffic("sweep_f64", nh),
                "us_per_launch": t_h * 1e6, "bytes_per_launch": ch * 80,
+               "timing": f"median of {REPEATS} blocks of 10 launches (HIP events on the library's stream)",
                "residency": f"{nh}^3: {ch * 80 / 1e9:.2f} GB working set, streamed from HBM", "others": {}}
         for kind, tag, bpc in (("apply", "apply_f64", 56), ("resid", "resid_f64", 80)):
             t_k = stencil_rate(ohm, Hh, Bh, Sh, Eh, 0.5 * dth, kind)
