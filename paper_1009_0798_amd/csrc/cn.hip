@@ -658,7 +658,8 @@ struct Solver {
     // device part of the start of a step: the staged tables, coarse-fine
     // ghosts of eta (FP64) and FP32 copies, dense-level resistivity, coarsest
     // inverses, S = b - (1 - lambda) dt div F(b), and (multigrid) the initial
-    // residual with |S|^2 and |r|^2 copied to the pinned buffer
+    // residual with |r|^2 and |S|^2 copied to the pinned buffer, the stop
+    // rule's thresholds and, for BiCGStab, the first restart
     ohm_status start_device(bool multigrid)
     {
         const int L = nlev();
@@ -696,8 +697,13 @@ struct Solver {
         OHM_TRY(composite(P.x, P.S, MODE_APPLY, src_coef, src_coef, 0));
         // the initial residual and its norms
         OHM_TRY(composite(P.x, P.r, MODE_RESID, lam_dt, neg_lam_dt, P.S));
-        const double *xs[2] = {at<double>(P.S), at<double>(P.r)};
-        OHM_TRY(dots(xs, xs, 2));
+        // (r, r) and (S, S) per problem; for BiCGStab the same launch makes
+        // the first restart (rhat = r, its scalars from (r, r))
+        const double *xs[2] = {at<double>(P.r), at<double>(P.S)};
+        if (o->outer == 1)
+            OHM_TRY(dots(xs, xs, 2, 0, at<double>(P.rhat)));
+        else
+            OHM_TRY(dots(xs, xs, 2));
         OHM_TRY(copy_dots(2));
         // thresholds of the stop rule; problems the initial guess already
         // satisfies leave the active set before any iteration is queued
@@ -712,7 +718,7 @@ struct Solver {
     // queued before the host knows that the recurrence has converged: every
     // iteration rewrites t before reading it); its per-problem square norm
     // goes to the pinned buffer at h_dots[2 nprob + p] (the first 2 nprob
-    // values hold |S|^2 and |r|^2 of the step's start).  It is formed for
+    // values hold |r|^2 and |S|^2 of the step's start).  It is formed for
     // every problem: a problem that stopped earlier has the same x as when
     // its residual was last formed, so it gets the same residual again.
     ohm_status true_residual(size_t into)
@@ -937,8 +943,8 @@ struct Solver {
         bool known = false;
         auto read_start = [&]() -> ohm_status {
             for (int p = 0; p < np; ++p) {
-                Snorm2[p] = h->h_dots[2 * p];
-                r2[p] = h->h_dots[2 * p + 1];
+                r2[p] = h->h_dots[2 * p];
+                Snorm2[p] = h->h_dots[2 * p + 1];
             }
             rfin = r2;
             for (int p = 0; p < np; ++p) {
@@ -982,15 +988,17 @@ struct Solver {
             // recurrence has not converged they are simply queued again.
             int it_total = 0, first_pass = -1;
             const int pred = h->bicg_pred;
+            bool restarted = true;   // the step's start made the first restart
             while (it_total < maxit && (!known || any(act))) {
                 // restart: rhat = r (copied by the dot kernel that forms
                 // (r, r)), rho = alpha = omega = 1, and a first direction p = r
                 // (the scalar stage sets beta = 0, which the direction update
                 // reads as p = v = 0, so neither is filled)
-                {
+                if (!restarted) {
                     const double *xs[1] = {at<double>(P.r)};
                     OHM_TRY(dots(xs, xs, 1, 0, at<double>(P.rhat)));
                 }
+                restarted = false;
                 std::vector<int> inner(act);
                 int since = 0;          // iterations since the restart (the ring's slot count)
                 bool spec = false;      // a verification is queued behind the last iteration

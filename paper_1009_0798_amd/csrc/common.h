@@ -139,7 +139,7 @@ struct ohm_hier {
     double *d_norms = nullptr;       // [nprob * 6]
     size_t table_bytes = 0;          // device bytes of the tables and scratch above
     // pinned host copies of norms: [8 * nprob] of reductions (a step's
-    // start: |S|^2, |r|^2 at [0, 2 nprob); the verifying true residual at
+    // start: |r|^2, |S|^2 at [0, 2 nprob); the verifying true residual at
     // [2 nprob, 3 nprob); an iteration of eqs. 16-18 at [0, nprob)), then the
     // iteration ring [2 * ITER_SLOTS * nprob], then the final norms of a
     // step [6 * nprob]
@@ -359,8 +359,8 @@ struct IterRing {
 ohm_status launch_reduce_scal(int nprob, int nrange, const long long *range_dev, const double *part, int k,
                               double *out, int stage, const int *active, double *scal, hipStream_t s,
                               IterRing ring = IterRing());
-// tol2[p] = rtol^2 max(|S|^2, 1e-300) from dots[2 p] = |S|^2, and problems whose
-// initial |r|^2 = dots[2 p + 1] is not above it (NaN included) leave the
+// tol2[p] = rtol^2 max(|S|^2, 1e-300) from dots[2 p + 1] = |S|^2, and problems
+// whose initial |r|^2 = dots[2 p] is not above it (NaN included) leave the
 // active set; a non-finite initial |r|^2 sets *hold (see IterRing)
 ohm_status launch_conv_init(int nprob, const double *dots, double rtol, double *tol2, int *active, int *hold,
                             hipStream_t s);

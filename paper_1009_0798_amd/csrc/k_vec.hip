@@ -332,10 +332,10 @@ __global__ void k_conv_init(int nprob, const double *__restrict__ dots, double r
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nprob) return;
-    const double t = rtol * rtol * fmax(dots[2 * p], 1e-300);
+    const double t = rtol * rtol * fmax(dots[2 * p + 1], 1e-300);
     tol2[p] = t;
-    if (!(dots[2 * p + 1] > t)) active[p] = 0;
-    if (!isfinite(dots[2 * p + 1])) *hold = 1;
+    if (!(dots[2 * p] > t)) active[p] = 0;
+    if (!isfinite(dots[2 * p])) *hold = 1;
 }
 
 }  // namespace
