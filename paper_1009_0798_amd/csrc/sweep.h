@@ -138,6 +138,9 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
                       "direct tile loads are for plain FP64 sweeps");
         constexpr int NPC = (TW2 / 2) * TW2, NP = NPC * TW2;
         const int w = u >> 6;
+        // the waves of a group that issues its tile's loads take precedence
+        // over the other resident group's updates until the loads are out
+        __builtin_amdgcn_s_setprio(3);
 #pragma unroll
         for (int k = 0; k < 2; ++k) {
             const int first = SWEEP_THREADS * k + 64 * w;
@@ -152,6 +155,7 @@ __device__ __forceinline__ void fused_sweep_tile(const Addr &A, const T *__restr
                 lds_load16((const char *)eta + off, &sE[2 * first]);
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
     } else {
